@@ -1,0 +1,437 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests re-types an oracle formula and compares it with itself:
+each checks a property the paper states (Secs. 3-4) or that follows from it
+(conservation, exact fixed points, moment identities, a textbook special
+case, transport coefficients, symmetry), so that a dropped term, a wrong
+sign, a transposed index or a mistyped matrix entry fails at least one.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _built():
+    O.build(force=False)
+
+
+# ---------------------------------------------------------------- lattices
+
+def test_d3q19_velocity_set_and_weights():
+    """Eqs. (12), (13), (18): the 19 velocities are the rest vector, the 6 axis
+    and the 12 face-diagonal unit-lattice vectors, and the weights give the
+    isotropic moments of a lattice with c_s^2 = 1/3 up to fourth order."""
+    e, w, _, _ = O.velocities()
+    vecs = {tuple(v) for v in e}
+    expect = {(a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)
+              if abs(a) + abs(b) + abs(c) <= 2}
+    assert vecs == expect and len(e) == 19
+    assert tuple(e[0]) == (0, 0, 0)
+    assert all(np.abs(e[1:7]).sum(1) == 1) and all(np.abs(e[7:]).sum(1) == 2)
+    assert math.isclose(w.sum(), 1.0, abs_tol=1e-15)
+    d = np.eye(3)
+    assert np.allclose(np.einsum("i,ia->a", w, e), 0, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, e, e), d / 3, atol=1e-16)
+    assert np.allclose(np.einsum("i,ia,ib,ic->abc", w, e, e, e), 0, atol=1e-16)
+    four = np.einsum("i,ia,ib,ic,id->abcd", w, e, e, e, e)
+    iso = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+           + np.einsum("ad,bc->abcd", d, d)) / 9
+    assert np.allclose(four, iso, atol=1e-16)
+
+
+def test_d3q7_velocity_set_and_weights():
+    """Eqs. (28), (31), (34), (36): D3Q7 has second moment sum w e e = I/4,
+    the epsilon = 1/4 of Eq. (36), and a = 7 w_1 - 1 = 3/4."""
+    _, _, e, w = O.velocities()
+    assert {tuple(v) for v in e} == {(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0),
+                                     (0, -1, 0), (0, 0, 1), (0, 0, -1)}
+    assert math.isclose(w.sum(), 1.0)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, e, e), np.eye(3) / 4)
+    assert 7 * w[0] - 1 == 0.75
+
+
+def _moment_polynomials(e):
+    """The moment basis of Eq. (22) as polynomials of the velocities (the
+    d'Humieres D3Q19 basis the paper cites for its M)."""
+    ex, ey, ez = e[:, 0], e[:, 1], e[:, 2]
+    e2 = ex * ex + ey * ey + ez * ez
+    one = np.ones_like(ex)
+    return np.array([
+        one,                                     # rho
+        19 * e2 - 30,                            # e
+        (21 * e2 * e2 - 53 * e2 + 24) / 2,       # epsilon
+        ex, (5 * e2 - 9) * ex,                   # j_x, q_x
+        ey, (5 * e2 - 9) * ey,                   # j_y, q_y
+        ez, (5 * e2 - 9) * ez,                   # j_z, q_z
+        3 * ex * ex - e2,                        # 3 p_xx
+        (3 * e2 - 5) * (3 * ex * ex - e2),       # 3 pi_xx
+        ey * ey - ez * ez,                       # p_ww
+        (3 * e2 - 5) * (ey * ey - ez * ez),      # pi_ww
+        ex * ey, ey * ez, ex * ez,               # p_xy, p_yz, p_xz
+        (ey * ey - ez * ez) * ex,                # m_x
+        (ez * ez - ex * ex) * ey,                # m_y
+        (ex * ex - ey * ey) * ez,                # m_z
+    ], dtype=np.float64)
+
+
+def test_transform_matrix_rows_are_the_named_moments():
+    """Eq. (21) against Eq. (22): every row of M is the polynomial of e_i that
+    its moment names, evaluated on the velocities of Eq. (12).  Row 14 (p_xy)
+    only matches with the correction the oracle applies (reading R1)."""
+    m, _, _, _ = O.matrices()
+    e, _, _, _ = O.velocities()
+    assert np.array_equal(m, _moment_polynomials(e))
+
+
+def test_printed_row_14_would_be_singular():
+    """Reading R1: the row printed for p_xy makes M rank 18, so no M^-1 of
+    Eq. (19) exists; the corrected row gives rank 19."""
+    m, _, _, _ = O.matrices()
+    printed = m.copy()
+    printed[13, 7:11] = [1, -1, 1, -1]
+    assert np.linalg.matrix_rank(printed) == 18
+    assert np.linalg.matrix_rank(m) == 19
+
+
+def test_transforms_are_orthogonal_and_inverted():
+    m, minv, n, ninv = O.matrices()
+    norms = np.array([19, 2394, 252, 10, 40, 10, 40, 10, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8])
+    assert np.array_equal(m @ m.T, np.diag(norms).astype(float))
+    assert np.abs(minv @ m - np.eye(19)).max() < 1e-15
+    assert np.abs(m @ minv - np.eye(19)).max() < 1e-15
+    assert np.array_equal(n @ n.T, np.diag([7, 2, 2, 2, 42, 12, 4]).astype(float))
+    assert np.abs(ninv @ n - np.eye(7)).max() < 1e-15
+
+
+def test_thermal_transform_rows():
+    """Eq. (32): the rows of N are 1, e_x, e_y, e_z, 6 - 7|e|^2, 3e_x^2 - |e|^2,
+    e_y^2 - e_z^2 on the D3Q7 velocities (Eq. 28)."""
+    _, _, n, _ = O.matrices()
+    _, _, e, _ = O.velocities()
+    ex, ey, ez = e.T
+    e2 = ex * ex + ey * ey + ez * ez
+    expect = np.array([np.ones(7), ex, ey, ez, 6 - 7 * e2, 3 * ex * ex - e2, ey * ey - ez * ez])
+    assert np.array_equal(n, expect.astype(float))
+
+
+# ------------------------------------------------------------- equilibria
+
+def _he_luo_feq(rho, j, e, w):
+    """Textbook incompressible (He-Luo) equilibrium with rho_0 = 1."""
+    ej = e @ j
+    return w * (rho + 3 * ej + 4.5 * ej ** 2 - 1.5 * (j @ j))
+
+
+def test_equilibrium_moments_reproduced_by_M():
+    """Eq. (24) is M applied to the He-Luo equilibrium (rho_0 = 1, ref. [39])."""
+    m, _, _, _ = O.matrices()
+    e, w, _, _ = O.velocities()
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        rho = 1 + 0.01 * rng.standard_normal()
+        j = 0.05 * rng.standard_normal(3)
+        got = O.meq(rho, *j)
+        want = m @ _he_luo_feq(rho, j, e, w)
+        assert np.abs(got - want).max() < 1e-14
+
+
+def test_eq17_equilibrium_moments():
+    """Eq. (17) carries rho, rho V and rho (c_s^2 I + V V) exactly."""
+    e, _, _, _ = O.velocities()
+    rng = np.random.default_rng(4)
+    for _ in range(20):
+        rho = 1 + 0.01 * rng.standard_normal()
+        v = 0.05 * rng.standard_normal(3)
+        fe = O.feq(rho, v)
+        assert abs(fe.sum() - rho) < 1e-15
+        assert np.abs(e.T @ fe - rho * v).max() < 1e-16
+        assert np.abs(np.einsum("i,ia,ib->ab", fe, e, e)
+                      - rho * (np.eye(3) / 3 + np.outer(v, v))).max() < 1e-15
+
+
+def test_thermal_equilibrium_moments():
+    """Eq. (33): g^eq_i = w_T,i theta (1 + 4 e_i . V) has N g^eq = n^eq."""
+    _, _, n, _ = O.matrices()
+    _, _, e, w = O.velocities()
+    rng = np.random.default_rng(5)
+    for _ in range(20):
+        th = rng.standard_normal()
+        v = 0.05 * rng.standard_normal(3)
+        geq = w * th * (1 + 4 * (e @ v))
+        want = np.array([th, v[0] * th, v[1] * th, v[2] * th, 0.75 * th, 0, 0])
+        assert np.abs(n @ geq - want).max() < 1e-15
+
+
+def test_force_moments():
+    """Eq. (15) (reading R3): the force adds no mass and exactly rho G of momentum."""
+    e, _, _, _ = O.velocities()
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        rho = 1 + 0.01 * rng.standard_normal()
+        v = 0.05 * rng.standard_normal(3)
+        gz = 1e-4 * rng.standard_normal()
+        F = O.force(rho, v, gz)
+        assert abs(F.sum()) < 1e-19
+        assert np.abs(e.T @ F - np.array([0, 0, rho * gz])).max() < 1e-19
+
+
+# ---------------------------------------------------------- collision
+
+def _random_state(rng, e, w, ew, scale=1e-3):
+    rho = 1 + 0.01 * rng.standard_normal()
+    j = 0.03 * rng.standard_normal(3)
+    f = _he_luo_feq(rho, j, e, w) + scale * w * rng.standard_normal(19)
+    g = ew * (0.3 + 0.01 * rng.standard_normal(7))
+    return f, g
+
+
+def test_collision_conserves_mass_energy_and_adds_force():
+    """Eqs. (14), (19), (29): collision keeps sum f and sum g, and changes the
+    momentum by rho G, G = g beta (theta - theta_ref) e_z (Eq. 16, R7)."""
+    e, w, _, w7 = O.velocities()
+    o = O.Oracle(8, 1, ra=1e4)
+    gb = o.derived()["gbeta"]
+    rng = np.random.default_rng(7)
+    for _ in range(10):
+        f, g = _random_state(rng, e, w, w7)
+        fo, go = o.collide_node(f, g)
+        rho, th = f.sum(), g.sum()
+        assert abs(fo.sum() - rho) < 1e-15
+        assert abs(go.sum() - th) < 1e-15
+        dj = e.T @ (fo - f)
+        assert np.abs(dj - np.array([0, 0, rho * gb * th])).max() < 2e-16
+
+
+def test_bgk_special_case():
+    """With every s_k = 1/tau the MRT collision of Eq. (19) is the BGK collision
+    towards the He-Luo equilibrium; with a uniform Q it is D3Q7 BGK towards
+    g^eq = w_T theta (1 + 4 e.V).  theta = theta_ref removes the force."""
+    e, w, e7, w7 = O.velocities()
+    for tau, tau_g in ((0.8, 0.7), (0.55, 1.3)):
+        o = O.Oracle(8, 1, ra=1e4, s19=np.full(19, 1 / tau), tau7=np.full(7, tau_g))
+        rng = np.random.default_rng(8)
+        for _ in range(10):
+            f, g = _random_state(rng, e, w, w7)
+            g = g - w7 * g.sum()  # theta = 0 = theta_ref: no buoyancy
+            g = g + w7 * 0.0
+            fo, go = o.collide_node(f, g)
+            rho, j = f.sum(), e.T @ f
+            want = f - (f - _he_luo_feq(rho, j, e, w)) / tau
+            assert np.abs(fo - want).max() < 1e-15
+            th, v = g.sum(), j / rho
+            geq = w7 * th * (1 + 4 * (e7 @ v))
+            assert np.abs(go - (g - (g - geq) / tau_g)).max() < 1e-15
+
+
+def test_bgk_special_case_with_temperature():
+    """As above with theta != 0 on the energy lattice (force switched off)."""
+    e, w, e7, w7 = O.velocities()
+    o = O.Oracle(8, 1, ra=1e4, buoyancy_scale=0.0, tau7=np.full(7, 0.9))
+    rng = np.random.default_rng(9)
+    for _ in range(10):
+        f, g = _random_state(rng, e, w, w7)
+        _, go = o.collide_node(f, g)
+        rho, j = f.sum(), e.T @ f
+        th, v = g.sum(), j / rho
+        geq = w7 * th * (1 + 4 * (e7 @ v))
+        assert np.abs(go - (g - (g - geq) / 0.9)).max() < 1e-15
+
+
+# ------------------------------------------------------------ whole steps
+
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
+def test_uniform_temperature_stays_at_rest(wall_type):
+    """Fluid at rest with theta = theta_ref on every wall and in the bulk stays
+    exactly at rest: no spurious velocity from walls, corners or collision."""
+    o = O.Oracle(7, wall_type, ra=1e4, theta_hot=0.0, theta_cold=0.0)
+    o.step(150)
+    rho, ux, uy, uz, th = o.macro()
+    assert np.abs(np.stack([ux, uy, uz])).max() == 0.0
+    assert np.ptp(rho) == 0.0 and np.abs(rho - 1).max() <= 4.5e-16  # sum of w_i rounds
+    assert np.abs(th).max() == 0.0
+
+
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
+def test_conduction_limit(wall_type):
+    """Without buoyancy the steady temperature is the linear conduction profile
+    theta = theta_h + (theta_c - theta_h) Y, for every wall type (the side
+    walls are adiabatic or carry that same profile, Eqs. 6-10), and the local
+    Nusselt number of Eq. (39) is 1 on the whole hot wall."""
+    n = 8
+    o = O.Oracle(n, wall_type, ra=100.0, buoyancy_scale=0.0)
+    o.step(6000)
+    _, ux, uy, uz, th = o.macro()
+    y = (np.arange(n) + 0.5) / n
+    lin = 0.5 - y
+    assert np.abs(th - lin[None, :, None]).max() < 1e-12
+    assert np.abs(np.stack([ux, uy, uz])).max() == 0.0
+    nu = o.nusselt(with_map=True)
+    assert np.abs(nu["map"] - 1).max() < 1e-11
+    for k in ("nu3d", "nu2d", "numax"):
+        assert abs(nu[k] - 1) < 1e-11
+
+
+def test_conduction_limit_ignores_tau5_to_tau7():
+    """End of Sec. 3.2: tau_5..tau_7 only change error terms; the conduction
+    solution stays exact for other values."""
+    n = 8
+    o = O.Oracle(n, 2, ra=100.0, buoyancy_scale=0.0, tau7=[1.0, 0.7, 0.7, 0.7, 0.8, 1.3, 0.6])
+    o.step(8000)
+    th = o.macro()[4]
+    lin = 0.5 - (np.arange(n) + 0.5) / n
+    assert np.abs(th - lin[None, :, None]).max() < 1e-12
+
+
+def test_mass_conservation_with_flow():
+    """Collision, forcing and bounce-back conserve total mass: sum rho stays n^3."""
+    n = 12
+    o = O.Oracle(n, 2, ra=1e5)
+    o.step(400)
+    rho, ux, uy, uz, _ = o.macro()
+    assert np.abs(uz).max() > 1e-4  # there is flow
+    assert abs(rho.sum() - n ** 3) / n ** 3 < 1e-13
+
+
+def test_conserved_rates_do_not_matter():
+    """Rates of conserved moments (s_1, s_4, s_6, s_8; tau_1) multiply an exact
+    zero: changing them leaves the solution bitwise unchanged."""
+    base = O.Oracle(9, 3, ra=1e5)
+    s = np.array([1.0, 1.19, 1.4, 1.0, 1.2, 1.0, 1.2, 1.0, 1.2, base.derived()["s_nu"],
+                  1.4, base.derived()["s_nu"], 1.4] + [base.derived()["s_nu"]] * 3 + [1.98] * 3)
+    s_mod = s.copy()
+    s_mod[[0, 3, 5, 7]] = [0.3, 1.7, 0.6, 1.9]
+    tau = [1.0] + [base.derived()["tau_t"]] * 3 + [1.0] * 3
+    tau_mod = list(tau)
+    tau_mod[0] = 0.77
+    a = O.Oracle(9, 3, ra=1e5, s19=s, tau7=tau)
+    b = O.Oracle(9, 3, ra=1e5, s19=s_mod, tau7=tau_mod)
+    base.step(120), a.step(120), b.step(120)
+    fa, ga = a.get_state()
+    fb, gb = b.get_state()
+    f0, g0 = base.get_state()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    assert np.array_equal(fa, f0) and np.array_equal(ga, g0)
+
+
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
+def test_x_mirror_symmetry(wall_type):
+    """Walls and gravity are symmetric under x -> H - x, so without noise the
+    flow is: u_x odd, u_y, u_z, theta, rho even."""
+    n = 10
+    o = O.Oracle(n, wall_type, ra=1e5)
+    o.step(300)
+    rho, ux, uy, uz, th = o.macro()
+    assert np.abs(uy).max() > 1e-4
+    flip = lambda a: a[:, :, ::-1]
+    scale = np.abs(np.stack([ux, uy, uz])).max()
+    assert np.abs(ux + flip(ux)).max() < 1e-12 * scale
+    for a in (uy, uz):
+        assert np.abs(a - flip(a)).max() < 1e-12 * scale
+    assert np.abs(th - flip(th)).max() < 1e-13
+    assert np.abs(rho - flip(rho)).max() < 1e-15
+
+
+def _decay_ratio(n, ra, kind, t0=100, t1=1100):
+    """Measured decay rate of a sine mode of wavelength n in a periodic box,
+    divided by (coefficient * k^2) with the coefficient the oracle derived."""
+    k = 2 * np.pi / n
+    y = np.arange(n)
+    if kind == "nu":
+        o = O.Oracle(n, 0, ra=ra, buoyancy_scale=0.0)
+        ref = o.derived()["nu"]
+        f = np.zeros((19, n, n, n))
+        for yy in range(n):
+            f[:, :, yy, :] = O.feq(1.0, [1e-4 * np.sin(k * yy), 0, 0])[:, None, None]
+        o.set_state(f.reshape(19, -1), np.zeros((7, n ** 3)))
+        amp = lambda: 2 * np.mean(o.macro()[1][0, :, 0] * np.sin(k * y))
+    else:
+        th0 = np.broadcast_to((0.1 * np.sin(k * y))[None, :, None], (n, n, n)).reshape(-1)
+        o = O.Oracle(n, 0, ra=ra, buoyancy_scale=0.0, theta0=th0)
+        ref = o.derived()["alpha"]
+        amp = lambda: 2 * np.mean(o.macro()[4][0, :, 0] * np.sin(k * y))
+    o.step(t0)
+    a0 = amp()
+    o.step(t1 - t0)
+    a1 = amp()
+    return -np.log(a1 / a0) / (t1 - t0) / k ** 2 / ref
+
+
+@pytest.mark.parametrize("ra", [1e3, 1e5])
+def test_shear_wave_viscosity(ra):
+    """A transverse shear wave u_x = A sin(k y) in a periodic box decays at
+    nu k^2 (1 + O(k^2)); nu = (1/s_nu - 1/2)/3 is the viscosity that Eq. (26)
+    sets from the nu of Eq. (38).  Wavelengths 16 and 32 are extrapolated
+    (Richardson, second order) to remove the lattice O(k^2) term."""
+    r16, r32 = _decay_ratio(16, ra, "nu"), _decay_ratio(32, ra, "nu")
+    assert abs(r32 - 1) < 5e-3
+    assert abs((4 * r32 - r16) / 3 - 1) < 1e-3, (r16, r32)
+
+
+@pytest.mark.parametrize("ra", [1e3, 1e5])
+def test_temperature_mode_diffusivity(ra):
+    """A temperature sine mode in a periodic box at rest decays at alpha k^2,
+    alpha = nu / Pr, through tau = 1/2 + alpha/epsilon (Eq. 36, epsilon = 1/4)."""
+    r16, r32 = _decay_ratio(16, ra, "alpha"), _decay_ratio(32, ra, "alpha")
+    assert abs(r32 - 1) < 5e-3
+    assert abs((4 * r32 - r16) / 3 - 1) < 2.5e-3, (r16, r32)
+
+
+# ------------------------------------------------------------ observables
+
+def test_nusselt_stencil_exact_for_quadratic_profiles():
+    """Eq. (39) with reading R17: the one-sided stencil through the wall value
+    and two nodes is exact when theta is quadratic in Y near the hot wall.
+    With theta = theta_h + a(x,z) Y + b Y^2 the local Nu is -a(x,z); Eq. (40)
+    averages it, Eq. (41) takes the X = 0.5 line (R18), Nu_max its maximum."""
+    for n in (6, 7):
+        o = O.Oracle(n, 1, ra=1e4)
+        _, _, _, w7 = O.velocities()
+        xc = (np.arange(n) + 0.5) / n
+        Y = (np.arange(n) + 0.5) / n
+        a = -(1.5 + np.cos(np.pi * xc)[None, :] * (1 + 0.3 * xc[:, None]))  # [z, x]
+        th = 0.5 + a[:, None, :] * Y[None, :, None] + 0.7 * Y[None, :, None] ** 2
+        g = w7[:, None] * th.reshape(1, -1)
+        f, _ = o.get_state()
+        o.set_state(f, g)
+        nu = o.nusselt(with_map=True)
+        assert np.abs(nu["map"] + a).max() < 1e-12
+        assert abs(nu["nu3d"] + a.mean()) < 1e-12
+        line = -(a[:, n // 2] if n % 2 else 0.5 * (a[:, n // 2 - 1] + a[:, n // 2]))
+        assert abs(nu["nu2d"] - line.mean()) < 1e-12
+        assert abs(nu["numax"] - (-a).max()) < 1e-12
+
+
+def test_parameter_derivation():
+    """Eq. (38) with Ma = 0.1, Pr = 0.71: u_c = Ma c_s, Ra = g beta dT H^3 Pr / nu^2,
+    Pr = nu / alpha, and the velocity scaling of Eq. (42) equals u H / alpha."""
+    for n, ra in ((16, 1e3), (50, 1e4), (60, 1e5), (256, 1e6)):
+        d = O.derive(n, ra, 0.71, 0.1)
+        assert math.isclose(d["u_c"] / math.sqrt(1 / 3), 0.1, rel_tol=1e-15)
+        assert math.isclose(d["gbeta"] * n, d["u_c"] ** 2, rel_tol=1e-15)
+        assert math.isclose(d["gbeta"] * n ** 3 * 0.71 / d["nu"] ** 2, ra, rel_tol=1e-13)
+        assert math.isclose(d["nu"] / d["alpha"], 0.71, rel_tol=1e-15)
+        assert math.isclose(math.sqrt(3 * 0.71 * ra) / 0.1, n / d["alpha"], rel_tol=1e-13)
+        assert 0 < d["s_nu"] < 2 and d["tau_t"] > 0.5
+
+
+def test_golden_tables_are_well_formed():
+    """The paper's printed steady results (Tables 1-8) used by the physics
+    validation; the fixture cites each table."""
+    with open(os.path.join(GOLDEN, "paper_tables.json")) as fh:
+        tab = json.load(fh)
+    for row in tab["cases"]:
+        assert row["wall_type"] in (1, 2, 3) and row["n"] in (50, 60)
+        assert "source" in row
+    # Sec. 4.3: Nu(Type 2) < Nu(Type 3) < Nu(Type 1) at equal Ra.
+    by = {(r["wall_type"], r["ra"]): r["nu3d"] for r in tab["cases"]
+          if r["n"] == (50 if r["ra"] == 1e4 else 60)}
+    for ra in (1e4, 1e5):
+        assert by[(2, ra)] < by[(3, ra)] < by[(1, ra)]
