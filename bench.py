@@ -1,0 +1,123 @@
+#!/usr/bin/env python3
+"""Throughput of the double-MRT cavity step on one MI355X.
+
+Workload (default): 256^3 cube, Type 1 walls, Ra = 1e6, Pr = 0.71, Ma = 0.1,
+FP32 storage and arithmetic, fluid at rest with seeded +-1e-6 theta noise.
+A "step" is one fused streaming + collision update of every node (both
+lattices, all walls).  W untimed warm-up steps, then K timed steps bracketed
+by device synchronisation.  Prints one JSON line.
+
+value = n^3 * K / wall time, in MLUPS (million lattice-node updates / s).
+roofline: algorithmic bytes per launch (26 populations read + written per
+node, 208 B at FP32) over the average kernel time from HIP events recorded
+on the stream the kernels run on, against the 8 TB/s HBM peak.
+cpu_baseline: the FP64 CPU oracle timed on a bounded sample (64^3, same case).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def cpu_baseline(seconds: float, n: int = 64, ra: float = 1e6, wall_type: int = 1):
+    from oracle import oracle as ora
+    from paper_1511_04633_amd import inputs
+
+    o = ora.Oracle(n, wall_type, ra=ra, theta0=inputs.theta_noise(n, 20151115))
+    o.step(1)  # first touch of the arrays
+    steps, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        o.step(5)
+        steps += 5
+    dt = time.perf_counter() - t0
+    return {"value": round(n ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": ora.threads(), "kind": "oracle",
+            "sample": f"FP64 oracle, {n}^3 Type {wall_type} Ra {ra:g}, {steps} steps in {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=500)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--ra", type=float, default=1e6)
+    ap.add_argument("--wall-type", type=int, default=1)
+    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--launch", default="", help="bx,by override of the step kernel block")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(this build has no multi-GPU path)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1511_04633_amd import inputs, lbmx
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n = args.n
+    cav = lbmx.Cavity(n=n, wall_type=args.wall_type, ra=args.ra, storage=args.storage,
+                      theta0=inputs.theta_noise(n, 20151115))
+    if args.launch:
+        bx, by = (int(v) for v in args.launch.split(","))
+        cav.set_launch(bx, by)
+    print(f"bench: n={n} storage={args.storage} launch={cav.get_launch()} "
+          f"warmup={args.warmup} steps={args.steps}", file=sys.stderr, flush=True)
+    cav.step(args.warmup)
+    torch.cuda.synchronize()
+
+    t0 = time.perf_counter()
+    ev_ms = cav.step_timed(args.steps)   # HIP events on the cavity's stream
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+
+    nu = cav.nusselt()
+    cells = n ** 3
+    mlups = cells * args.steps / wall / 1e6
+    bpc = lbmx.bytes_per_cell(args.storage)
+    kernel_s = ev_ms / 1e3 / args.steps
+    achieved = cells * bpc / kernel_s / 1e9
+    dtype = {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32"}
+    line = {
+        "metric": "double-MRT MLUPS + % HBM roofline at 256^3; wall time to steady Nu",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": dtype[args.storage],
+        "data": "synthetic: cavity at rest + seeded theta noise (SplitMix64, amp 1e-6)",
+        "config": {"workload": f"double-MRT cubic cavity {n}^3, Type {args.wall_type}, "
+                               f"Ra {args.ra:g}, Pr 0.71, Ma 0.1",
+                   "n": n, "cells": cells, "storage": args.storage,
+                   "launch": list(cav.get_launch())},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "bytes_per_cell": bpc,
+                     "kernel_us": round(kernel_s * 1e6, 2)},
+        "nu3d_after": nu["nu3d"],
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wall_type=args.wall_type, ra=args.ra)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

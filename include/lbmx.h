@@ -1,0 +1,175 @@
+/*
+ * lbmx.h -- C-ABI of the MI355X double-MRT lattice Boltzmann library for
+ * natural convection in a differentially heated cubic cavity
+ * (Li, Yang & Zhang, arXiv:1511.04633).
+ *
+ * Problem (Sec. 2, Eqs. 1-10): a cube of edge H = n lattice cells, walls at
+ * y = 0 (hot, theta_hot) and y = H (cold, theta_cold), no-slip everywhere
+ * (Eq. 8); the four other walls are adiabatic (Type 1), carry the linear
+ * profile theta_h + (theta_c - theta_h) y/H (Type 2, Eq. 9), or carry it on
+ * x = 0, H and are adiabatic on z = 0, H (Type 3, Eq. 10).  Gravity points
+ * along -z.
+ *
+ * Method (Sec. 3): D3Q19-MRT flow (Eqs. 11-26) with the Boussinesq force of
+ * Eqs. (15)-(17), coupled to a D3Q7-MRT energy lattice (Eqs. 27-37);
+ * parameters in lattice units from Ma, Pr, Ra (Sec. 4, Eq. 38).
+ *
+ * Conventions for every call:
+ *   - Status codes only; no exception or abort crosses this boundary.  On a
+ *     failure lbmx_last_error() returns a thread-local message.
+ *   - Host arrays are caller-owned and hold n^3 values, x fastest:
+ *     index = x + n*(y + n*z).  Population arrays are population-major:
+ *     f[i*n^3 + index], i in the paper's order (Eqs. 12, 28), 0-based.
+ *   - Device work is enqueued on the cavity's HIP stream; calls that return
+ *     host data synchronise that stream before returning.
+ *   - A cavity handle may be used by one host thread at a time.
+ *   - Time: a fresh or re-initialised cavity is at t = 0; lbmx_step advances
+ *     t.  Every read returns the state at the current t (pre-collision
+ *     populations, i.e. after streaming and wall conditions).
+ */
+#ifndef LBMX_H
+#define LBMX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBMX_OK = 0,
+    LBMX_EINVAL = 1,         /* invalid argument or parameter set            */
+    LBMX_ENOMEM = 2,         /* device or host allocation failed             */
+    LBMX_EDEVICE = 3,        /* a HIP runtime call failed                    */
+    LBMX_EUNSTABLE = 4,      /* non-finite values found (run diverged)       */
+    LBMX_ENOTCONVERGED = 5,  /* run_to_steady hit max_steps                  */
+    LBMX_ESTATE = 6          /* call not valid in the handle's current state */
+} lbmx_status;
+
+/* Population storage in HBM.  Collision arithmetic is FP64 for LBMX_F64 and
+ * FP32 otherwise.  D3Q19 populations are stored as offsets f_i - w_i from the
+ * lattice weights; LBMX_F16 / LBMX_BF16 store 16-bit offsets scaled by 1/w_i
+ * (flow) and 1/w_T,i (energy). */
+typedef enum { LBMX_F64 = 0, LBMX_F32 = 1, LBMX_F16 = 2, LBMX_BF16 = 3 } lbmx_storage;
+
+typedef struct {
+    int32_t n;              /* cells per edge, H = n; 4 <= n <= 1024              */
+    int32_t wall_type;      /* 1, 2 or 3 (Sec. 2, Eqs. 6-10)                      */
+    double ra;              /* Rayleigh number, > 0 (Eq. 38)                      */
+    double pr;              /* Prandtl number, > 0 (paper: 0.71)                  */
+    double ma;              /* Mach number u_c / c_s, in (0, 0.5] (paper: 0.1)    */
+    double theta_hot;       /* wall value at y = 0, Eq. (6)  (+0.5)               */
+    double theta_cold;      /* wall value at y = H, Eq. (7)  (-0.5)               */
+    double theta_ref;       /* T_l of Eq. (16) (0.0, the mean of the two walls)   */
+    double buoyancy_scale;  /* multiplies g beta; 1.0 normally, 0.0 = no force    */
+    int32_t storage;        /* lbmx_storage                                       */
+    int32_t custom_rates;   /* 0: rates of Eq. (26) and Sec. 3.2; 1: use s, tau   */
+    double s[19];           /* diagonal of S (Eq. 23) when custom_rates = 1       */
+    double tau[7];          /* diagonal of Q^-1 (Eq. 35) when custom_rates = 1    */
+} lbmx_params;
+
+typedef struct {
+    double nu3d;            /* Eq. (40): mean local Nu over the hot wall        */
+    double nu2d;            /* Eq. (41): mean over the X = 0.5 line             */
+    double numax;           /* maximum local Nu on the hot wall                 */
+    int64_t step;           /* time t the values belong to                      */
+    int32_t nonfinite;      /* count of non-finite local values (0 if healthy)  */
+} lbmx_nu;
+
+typedef struct lbmx_cavity lbmx_cavity;
+
+/* Fill *p with the defaults: n = 16, Type 1, Ra = 1e3, Pr = 0.71, Ma = 0.1,
+ * theta_hot = 0.5, theta_cold = -0.5, theta_ref = 0, buoyancy 1, LBMX_F32. */
+lbmx_status lbmx_params_default(lbmx_params *p);
+
+/* Lattice-unit parameters (Sec. 4, Eq. 38; Eqs. 26, 36):
+ * out[6] = {u_c = Ma c_s, g beta (per unit theta), nu, alpha = nu/Pr,
+ *           s_nu = 1/(3 nu + 1/2), tau_T = 1/2 + alpha/epsilon (epsilon 1/4)}.
+ * EINVAL if the set is invalid (including s_nu outside (0, 2) or tau_T <= 1/2). */
+lbmx_status lbmx_derive(const lbmx_params *p, double *out);
+
+/* Device bytes a cavity needs (two lattices plus reduction scratch). */
+lbmx_status lbmx_workspace_bytes(const lbmx_params *p, size_t *bytes);
+
+/* Algorithmic HBM bytes moved by one cell update of lbmx_step:
+ * 26 populations read once and written once at the storage width. */
+lbmx_status lbmx_bytes_per_cell(int32_t storage, double *bytes);
+
+/* Create a cavity.  dev_workspace: device memory of at least
+ * lbmx_workspace_bytes() bytes, 256-byte aligned, borrowed for the handle's
+ * life; NULL makes the library allocate (and free) its own.  stream: a
+ * hipStream_t for all device work; NULL uses a stream the library creates.
+ * The cavity starts at rest with theta = 0 (as lbmx_init_rest(h, NULL)). */
+lbmx_status lbmx_create(const lbmx_params *p, void *dev_workspace, size_t ws_bytes,
+                        void *stream, lbmx_cavity **out);
+
+/* Destroy a cavity (NULL-safe).  Waits for its pending work. */
+void lbmx_destroy(lbmx_cavity *h);
+
+/* Set the state at t = 0 to fluid at rest, rho = 1: f_i = w_i, and
+ * g_i = w_T,i theta0 (host array of n^3 doubles; NULL = theta 0 everywhere). */
+lbmx_status lbmx_init_rest(lbmx_cavity *h, const double *theta0_host);
+
+/* Set the state at time t from host populations: f (19 n^3) and g (7 n^3)
+ * doubles, population-major (as returned by lbmx_get_populations). */
+lbmx_status lbmx_set_populations(lbmx_cavity *h, const double *f_host, const double *g_host,
+                                 int64_t t);
+
+/* Copy the populations of the current state to host (19 n^3 and 7 n^3
+ * doubles; either pointer may be NULL). */
+lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host);
+
+/* Set the state at t = 0 from velocity and temperature fields given on a
+ * src_n^3 grid of node-centred device FP32 arrays (x fastest): each cavity
+ * node samples them trilinearly (clamped at the walls) and takes
+ * f = f^eq(rho = 1, u) of Eq. (17) and g = g^eq(theta, u) with
+ * N g^eq = n^eq of Eq. (33).  Velocities in lattice units. */
+lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *dev_v,
+                             const float *dev_w, const float *dev_theta, int32_t src_n);
+
+/* Advance nsteps >= 0 time steps (fused streaming + double-MRT collision,
+ * Eqs. 14 and 29, wall conditions of Eqs. 6-10).  Asynchronous. */
+lbmx_status lbmx_step(lbmx_cavity *h, int64_t nsteps);
+
+/* As lbmx_step, and also report the elapsed device time of the nsteps
+ * kernels measured with HIP events on the cavity's stream (synchronises). */
+lbmx_status lbmx_step_timed(lbmx_cavity *h, int64_t nsteps, double *ms);
+
+/* Current time step t. */
+lbmx_status lbmx_time(const lbmx_cavity *h, int64_t *t);
+
+/* Macroscopic fields at the current t to host arrays (n^3 doubles each,
+ * any may be NULL): rho = sum f (Eq. 20), u = j / rho with j = sum e_i f_i,
+ * theta = sum g (Eq. 30). */
+lbmx_status lbmx_read_macro(lbmx_cavity *h, double *rho, double *ux, double *uy, double *uz,
+                            double *theta);
+
+/* Hot-wall Nusselt numbers at the current t (Eqs. 39-41): local
+ * Nu = -n (9 theta_0 - theta_1 - 8 theta_hot)/3 from the two wall-adjacent
+ * nodes (second order, exact for quadratic profiles); map_host (n*n doubles,
+ * x fastest then z) may be NULL.  Returns EUNSTABLE (with *out filled) if any
+ * local value is not finite. */
+lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host);
+
+/* Step in chunks of `every` and stop once |Nu_3D(t) - Nu_3D(t - every)| < tol
+ * (the paper gives no criterion; this is the criterion the library uses).
+ * ENOTCONVERGED if max_steps pass first; EUNSTABLE on divergence.  *out holds
+ * the last Nu evaluation either way. */
+lbmx_status lbmx_run_to_steady(lbmx_cavity *h, double tol, int64_t every, int64_t max_steps,
+                               lbmx_nu *out);
+
+/* Launch shape of the step kernel: block = (bx, by) threads over (x, y),
+ * grid covers the cube; bx*by must be a multiple of 64 (one wavefront) and
+ * at most 1024, unless bx = n and by = 1.  0, 0 restores the default. */
+lbmx_status lbmx_set_launch(lbmx_cavity *h, int32_t bx, int32_t by);
+lbmx_status lbmx_get_launch(const lbmx_cavity *h, int32_t *bx, int32_t *by);
+
+const char *lbmx_strerror(lbmx_status s);
+const char *lbmx_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMX_H */

@@ -1,0 +1,519 @@
+// kernels.hpp -- HIP kernels of the double-MRT cavity step for gfx950.
+//
+// Data layout in HBM: two lattices (ping-pong), each 26 population planes
+// (19 D3Q19 then 7 D3Q7) of `plane` elements; inside a plane the node
+// (x, y, z) sits at x + n*(y + n*z), x fastest, so a wavefront reads and
+// writes 64 consecutive nodes of one row per population.
+//
+// What a lattice holds: the post-collision populations f*(t-1), g*(t-1).
+// The step kernel gathers ("pulls") them from the upstream neighbours, which
+// is streaming (Eq. 14, Eq. 29) together with the wall conditions, then
+// collides in registers and writes f*(t), g*(t) at the node itself (aligned
+// stores).  Reads of the state at time t (fields, Nu, populations) perform
+// the same pull without colliding.  Initialising a state S_0 therefore means
+// writing the unique post-collision set whose pull gives S_0 ("unstream").
+//
+// Wall conditions in pull form (walls half way between nodes, at rest):
+//   D3Q19: f_i(x) = f*_ibar(x) when x - e_i is outside (bounce-back, Eq. 8);
+//   D3Q7 : g_i(x) = -g*_ibar(x) + 2 w_T,i theta_W on a Dirichlet wall,
+//          g_i(x) =  g*_ibar(x) on an adiabatic wall.
+// Each D3Q7 link crosses a single wall, so edges and corners need no rule.
+#pragma once
+
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "collide.hpp"
+
+namespace lbmx {
+
+// ------------------------------------------------------------------ storage
+// Codec<S>: how a population is held in HBM.  T is the compute type.
+// Flow populations are stored as offsets df = f - w_i; 16-bit formats store
+// df / w_i and g / w_T,i (the ratio a population has to its weight), which
+// keeps the stored magnitudes O(u) and O(theta) for every direction.
+template <typename S>
+struct Codec;
+
+template <>
+struct Codec<double> {
+    using T = double;
+    static __device__ __forceinline__ T dec_f(double v, T) { return v; }
+    static __device__ __forceinline__ double enc_f(T v, T) { return v; }
+    static __device__ __forceinline__ T dec_g(double v, T) { return v; }
+    static __device__ __forceinline__ double enc_g(T v, T) { return v; }
+};
+
+template <>
+struct Codec<float> {
+    using T = float;
+    static __device__ __forceinline__ T dec_f(float v, T) { return v; }
+    static __device__ __forceinline__ float enc_f(T v, T) { return v; }
+    static __device__ __forceinline__ T dec_g(float v, T) { return v; }
+    static __device__ __forceinline__ float enc_g(T v, T) { return v; }
+};
+
+template <>
+struct Codec<__half> {
+    using T = float;
+    // w is the lattice weight of the population.
+    static __device__ __forceinline__ T dec_f(__half v, T w) { return __half2float(v) * w; }
+    static __device__ __forceinline__ __half enc_f(T v, T w) { return __float2half_rn(v / w); }
+    static __device__ __forceinline__ T dec_g(__half v, T w) { return __half2float(v) * w; }
+    static __device__ __forceinline__ __half enc_g(T v, T w) { return __float2half_rn(v / w); }
+};
+
+template <>
+struct Codec<__hip_bfloat16> {
+    using T = float;
+    static __device__ __forceinline__ T dec_f(__hip_bfloat16 v, T w) { return __bfloat162float(v) * w; }
+    static __device__ __forceinline__ __hip_bfloat16 enc_f(T v, T w) { return __float2bfloat16(v / w); }
+    static __device__ __forceinline__ T dec_g(__hip_bfloat16 v, T w) { return __bfloat162float(v) * w; }
+    static __device__ __forceinline__ __hip_bfloat16 enc_g(T v, T w) { return __float2bfloat16(v / w); }
+};
+
+// ---------------------------------------------------------- lattice tables
+// D3Q19 (Eq. 12) and D3Q7 (Eq. 28) in the paper's order, 0-based.
+__device__ __forceinline__ constexpr int ex19(int i)
+{
+    constexpr int v[19] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return v[i];
+}
+__device__ __forceinline__ constexpr int ey19(int i)
+{
+    constexpr int v[19] = {0, 0, 0, 1, -1, 0, 0, 1, 1, -1, -1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return v[i];
+}
+__device__ __forceinline__ constexpr int ez19(int i)
+{
+    constexpr int v[19] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, 1, -1, -1, 1, 1, -1, -1};
+    return v[i];
+}
+__device__ __forceinline__ constexpr int opp19(int i)
+{
+    constexpr int v[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
+    return v[i];
+}
+// Eq. (18)
+__device__ __forceinline__ constexpr double w19(int i)
+{
+    return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+// Eq. (31)
+__device__ __forceinline__ constexpr double w7(int i) { return i == 0 ? 0.25 : 0.125; }
+
+// ---------------------------------------------------------------- arguments
+template <typename T>
+struct Geometry {
+    int n;
+    int wall_type;     // 1, 2, 3
+    T theta_hot, theta_cold;
+    size_t plane;      // elements per population plane
+};
+
+// theta on a linear wall (Eqs. 9-10) at node height y: the crossing point of
+// an x or z link has the node's y = j + 1/2.
+template <typename T>
+__device__ __forceinline__ T theta_linear(const Geometry<T> &geo, int y)
+{
+    return geo.theta_hot + (geo.theta_cold - geo.theta_hot) * (T(y) + T(0.5)) / T(geo.n);
+}
+
+// Dirichlet flags of the x and z walls for the three cavity types.
+__device__ __forceinline__ bool x_wall_dirichlet(int wall_type) { return wall_type != 1; }
+__device__ __forceinline__ bool z_wall_dirichlet(int wall_type) { return wall_type == 2; }
+
+// ------------------------------------------------------------------- pull
+// Gather the populations of node (x, y, z) at time t from the post-collision
+// lattice `src` (time t-1): streaming plus wall conditions.
+template <typename S>
+__device__ __forceinline__ void pull(const S *__restrict__ src, const Geometry<typename Codec<S>::T> &geo,
+                                     int x, int y, int z, typename Codec<S>::T f[19],
+                                     typename Codec<S>::T g[7])
+{
+    using T = typename Codec<S>::T;
+    using C = Codec<S>;
+    const int n = geo.n;
+    const size_t P = geo.plane;
+    const int idx = x + n * (y + n * z);
+    const bool xl = x == 0, xh = x == n - 1;
+    const bool yl = y == 0, yh = y == n - 1;
+    const bool zl = z == 0, zh = z == n - 1;
+    const int sy = n, sz = n * n;
+
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+        const int ex = ex19(i), ey = ey19(i), ez = ez19(i);
+        const bool out = (ex > 0 && xl) || (ex < 0 && xh) || (ey > 0 && yl) || (ey < 0 && yh) ||
+                         (ez > 0 && zl) || (ez < 0 && zh);
+        const int d = ex + ey * sy + ez * sz;
+        // Inside: f*_i(x - e_i).  Outside: f*_ibar(x) reflected at the wall.
+        const S v = out ? src[(size_t)opp19(i) * P + idx] : src[(size_t)i * P + (idx - d)];
+        f[i] = C::dec_f(v, T(w19(i)));
+    }
+
+    const S *gs = src + 19 * P;
+    const T two_w = T(0.25);  // 2 w_T,i for the moving directions
+    const T th_lin = theta_linear(geo, y);
+    const bool xd = x_wall_dirichlet(geo.wall_type);
+    const bool zd = z_wall_dirichlet(geo.wall_type);
+    g[0] = C::dec_g(gs[idx], T(w7(0)));
+    {   // +x from x-1 | wall x = 0
+        const T v = C::dec_g(xl ? gs[2 * P + idx] : gs[1 * P + idx - 1], T(w7(1)));
+        g[1] = xl ? (xd ? two_w * th_lin - v : v) : v;
+    }
+    {   // -x from x+1 | wall x = H
+        const T v = C::dec_g(xh ? gs[1 * P + idx] : gs[2 * P + idx + 1], T(w7(2)));
+        g[2] = xh ? (xd ? two_w * th_lin - v : v) : v;
+    }
+    {   // +y from y-1 | hot wall y = 0 (Eq. 6)
+        const T v = C::dec_g(yl ? gs[4 * P + idx] : gs[3 * P + idx - sy], T(w7(3)));
+        g[3] = yl ? two_w * geo.theta_hot - v : v;
+    }
+    {   // -y from y+1 | cold wall y = H (Eq. 7)
+        const T v = C::dec_g(yh ? gs[3 * P + idx] : gs[4 * P + idx + sy], T(w7(4)));
+        g[4] = yh ? two_w * geo.theta_cold - v : v;
+    }
+    {   // +z from z-1 | wall z = 0
+        const T v = C::dec_g(zl ? gs[6 * P + idx] : gs[5 * P + idx - sz], T(w7(5)));
+        g[5] = zl ? (zd ? two_w * th_lin - v : v) : v;
+    }
+    {   // -z from z+1 | wall z = H
+        const T v = C::dec_g(zh ? gs[5 * P + idx] : gs[6 * P + idx + sz], T(w7(6)));
+        g[6] = zh ? (zd ? two_w * th_lin - v : v) : v;
+    }
+}
+
+template <typename S>
+__device__ __forceinline__ void put(S *__restrict__ dst, size_t P, int idx,
+                                    const typename Codec<S>::T f[19],
+                                    const typename Codec<S>::T g[7])
+{
+    using T = typename Codec<S>::T;
+    using C = Codec<S>;
+#pragma unroll
+    for (int i = 0; i < 19; ++i)
+        dst[(size_t)i * P + idx] = C::enc_f(f[i], T(w19(i)));
+#pragma unroll
+    for (int i = 0; i < 7; ++i)
+        dst[(size_t)(19 + i) * P + idx] = C::enc_g(g[i], T(w7(i)));
+}
+
+// -------------------------------------------------------------- step kernel
+// One thread per node; block (bx, by) over (x, y), grid.z = z.
+template <typename S>
+__global__ __launch_bounds__(1024) void k_step(const S *__restrict__ src, S *__restrict__ dst,
+                                               Geometry<typename Codec<S>::T> geo,
+                                               Rates<typename Codec<S>::T> rates)
+{
+    using T = typename Codec<S>::T;
+    const int x = blockIdx.x * blockDim.x + threadIdx.x;
+    const int y = blockIdx.y * blockDim.y + threadIdx.y;
+    const int z = blockIdx.z;
+    if (x >= geo.n || y >= geo.n)
+        return;
+    T f[19], g[7];
+    pull<S>(src, geo, x, y, z, f, g);
+    collide<T>(f, g, rates);
+    put<S>(dst, geo.plane, x + geo.n * (y + geo.n * z), f, g);
+}
+
+// --------------------------------------------------------- state sources
+// Pre-collision populations of an initial state S_0, node by node, as
+// offsets (flow) and plain values (energy), in double precision.
+struct SourceRest {            // f = w_i, g = w_T,i theta0
+    const double *theta0;      // n^3, may be null (theta 0)
+    __device__ double f(int, int) const { return 0.0; }
+    __device__ double g(int i, int c) const { return theta0 ? w7(i) * theta0[c] : 0.0; }
+};
+
+struct SourcePops {            // full population arrays f[19][n^3], g[7][n^3]
+    const double *fa, *ga;
+    size_t cells;
+    __device__ double f(int i, int c) const { return fa[(size_t)i * cells + c] - w19(i); }
+    __device__ double g(int i, int c) const { return ga[(size_t)i * cells + c]; }
+};
+
+// Velocity / temperature fields sampled trilinearly from a node-centred
+// src_n^3 grid: f = f^eq(1, u) (Eq. 17) and g = w_T theta (1 + 4 e.u),
+// whose moments are n^eq of Eq. (33).
+struct SourceFields {
+    const float *u, *v, *w, *th;
+    int src_n, n;
+    __device__ float sample(const float *a, int x, int y, int z) const
+    {
+        const float s = float(src_n) / float(n);
+        float p[3] = {(x + 0.5f) * s - 0.5f, (y + 0.5f) * s - 0.5f, (z + 0.5f) * s - 0.5f};
+        int i0[3];
+        float fr[3];
+        for (int d = 0; d < 3; ++d) {
+            float q = fminf(fmaxf(p[d], 0.0f), float(src_n - 1));
+            int k = min(int(floorf(q)), src_n - 2 < 0 ? 0 : src_n - 2);
+            i0[d] = k;
+            fr[d] = q - float(k);
+        }
+        auto at = [&](int dx, int dy, int dz) {
+            int xx = min(i0[0] + dx, src_n - 1), yy = min(i0[1] + dy, src_n - 1),
+                zz = min(i0[2] + dz, src_n - 1);
+            return a[xx + (size_t)src_n * (yy + (size_t)src_n * zz)];
+        };
+        float c00 = at(0, 0, 0) * (1 - fr[0]) + at(1, 0, 0) * fr[0];
+        float c10 = at(0, 1, 0) * (1 - fr[0]) + at(1, 1, 0) * fr[0];
+        float c01 = at(0, 0, 1) * (1 - fr[0]) + at(1, 0, 1) * fr[0];
+        float c11 = at(0, 1, 1) * (1 - fr[0]) + at(1, 1, 1) * fr[0];
+        float c0 = c00 * (1 - fr[1]) + c10 * fr[1];
+        float c1 = c01 * (1 - fr[1]) + c11 * fr[1];
+        return c0 * (1 - fr[2]) + c1 * fr[2];
+    }
+    __device__ void node(int c, double *vel, double &theta) const
+    {
+        int x = c % n, y = (c / n) % n, z = c / (n * n);
+        vel[0] = sample(u, x, y, z);
+        vel[1] = sample(v, x, y, z);
+        vel[2] = sample(w, x, y, z);
+        theta = sample(th, x, y, z);
+    }
+    __device__ double f(int i, int c) const
+    {
+        double vel[3], t;
+        node(c, vel, t);
+        const int e[3] = {ex19(i), ey19(i), ez19(i)};
+        double eu = e[0] * vel[0] + e[1] * vel[1] + e[2] * vel[2];
+        double uu = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
+        return w19(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+    __device__ double g(int i, int c) const
+    {
+        double vel[3], t;
+        node(c, vel, t);
+        const int e[3] = {i == 1 ? 1 : (i == 2 ? -1 : 0), i == 3 ? 1 : (i == 4 ? -1 : 0),
+                          i == 5 ? 1 : (i == 6 ? -1 : 0)};
+        return w7(i) * t * (1.0 + 4.0 * (e[0] * vel[0] + e[1] * vel[1] + e[2] * vel[2]));
+    }
+};
+
+// "Unstream": write the post-collision lattice P whose pull reproduces S.
+// For population i at node y: if y + e_i is inside, P_i(y) = S_i(y + e_i);
+// otherwise P_i(y) is the value that the wall turns into S_ibar(y).
+template <typename S, typename Src>
+__global__ __launch_bounds__(256) void k_unstream(S *__restrict__ dst,
+                                                  Geometry<typename Codec<S>::T> geo, Src srcS)
+{
+    using T = typename Codec<S>::T;
+    using C = Codec<S>;
+    const int n = geo.n;
+    const long long cells = (long long)n * n * n;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells)
+        return;
+    const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
+    const size_t P = geo.plane;
+    for (int i = 0; i < 19; ++i) {
+        const int tx = x + ex19(i), ty = y + ey19(i), tz = z + ez19(i);
+        const bool in = tx >= 0 && tx < n && ty >= 0 && ty < n && tz >= 0 && tz < n;
+        double v = in ? srcS.f(i, tx + n * (ty + n * tz)) : srcS.f(opp19(i), int(c));
+        dst[(size_t)i * P + c] = C::enc_f(T(v), T(w19(i)));
+    }
+    const double th_lin = geo.theta_hot + (geo.theta_cold - geo.theta_hot) * (y + 0.5) / n;
+    const int gx[7] = {0, 1, -1, 0, 0, 0, 0}, gy[7] = {0, 0, 0, 1, -1, 0, 0},
+              gz[7] = {0, 0, 0, 0, 0, 1, -1}, go[7] = {0, 2, 1, 4, 3, 6, 5};
+    for (int i = 0; i < 7; ++i) {
+        const int tx = x + gx[i], ty = y + gy[i], tz = z + gz[i];
+        double v;
+        if (tx >= 0 && tx < n && ty >= 0 && ty < n && tz >= 0 && tz < n) {
+            v = srcS.g(i, tx + n * (ty + n * tz));
+        } else {
+            const double s_in = srcS.g(go[i], int(c));
+            bool dir;
+            double tw = 0.0;
+            if (ty < 0) { dir = true; tw = geo.theta_hot; }
+            else if (ty >= n) { dir = true; tw = geo.theta_cold; }
+            else if (tx < 0 || tx >= n) { dir = x_wall_dirichlet(geo.wall_type); tw = th_lin; }
+            else { dir = z_wall_dirichlet(geo.wall_type); tw = th_lin; }
+            // S_ibar = -P_i + 2 w theta_W (Dirichlet) or P_i (adiabatic)
+            v = dir ? 2.0 * w7(go[i]) * tw - s_in : s_in;
+        }
+        dst[(size_t)(19 + i) * P + c] = C::enc_g(T(v), T(w7(i)));
+    }
+}
+
+// ------------------------------------------------------------ read kernels
+// Macroscopic fields at time t: rho, u = j / rho, theta (double outputs).
+template <typename S>
+__global__ __launch_bounds__(256) void k_macro(const S *__restrict__ src,
+                                               Geometry<typename Codec<S>::T> geo,
+                                               double *rho, double *ux, double *uy, double *uz,
+                                               double *theta)
+{
+    using T = typename Codec<S>::T;
+    const int n = geo.n;
+    const long long cells = (long long)n * n * n;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells)
+        return;
+    const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
+    T f[19], g[7];
+    pull<S>(src, geo, x, y, z, f, g);
+    double dr = 0.0, j[3] = {0.0, 0.0, 0.0}, th = 0.0;
+    for (int i = 0; i < 19; ++i) {
+        dr += double(f[i]);
+        j[0] += ex19(i) * double(f[i]);
+        j[1] += ey19(i) * double(f[i]);
+        j[2] += ez19(i) * double(f[i]);
+    }
+    for (int i = 0; i < 7; ++i)
+        th += double(g[i]);
+    const double r = 1.0 + dr;
+    if (rho) rho[c] = r;
+    if (ux) ux[c] = j[0] / r;
+    if (uy) uy[c] = j[1] / r;
+    if (uz) uz[c] = j[2] / r;
+    if (theta) theta[c] = th;
+}
+
+// Populations at time t as plain doubles, population-major.
+template <typename S>
+__global__ __launch_bounds__(256) void k_pops(const S *__restrict__ src,
+                                              Geometry<typename Codec<S>::T> geo, double *fo,
+                                              double *go)
+{
+    using T = typename Codec<S>::T;
+    const int n = geo.n;
+    const long long cells = (long long)n * n * n;
+    const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= cells)
+        return;
+    const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
+    T f[19], g[7];
+    pull<S>(src, geo, x, y, z, f, g);
+    if (fo)
+        for (int i = 0; i < 19; ++i)
+            fo[(size_t)i * cells + c] = w19(i) + double(f[i]);
+    if (go)
+        for (int i = 0; i < 7; ++i)
+            go[(size_t)i * cells + c] = double(g[i]);
+}
+
+// --------------------------------------------------------- Nusselt number
+// Wavefront-wide reductions (64 lanes on CDNA).
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+__device__ __forceinline__ double wave_max(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// One block per z row of the hot wall (y = 0).  Local Nu (Eq. 39) from the
+// two wall-adjacent nodes, second order: dtheta/dy = (9 th0 - th1 - 8 th_w)/3.
+// partial[z] = {sum over x, X = 0.5 line contribution, max, non-finite count}.
+template <typename S>
+__global__ __launch_bounds__(256) void k_nu_rows(const S *__restrict__ src,
+                                                 Geometry<typename Codec<S>::T> geo,
+                                                 double theta_hot, double *partial, double *map)
+{
+    using T = typename Codec<S>::T;
+    const int n = geo.n;
+    const int z = blockIdx.x;
+    double sum = 0.0, line = 0.0, mx = -1.0e300, bad = 0.0;
+    for (int x = threadIdx.x; x < n; x += blockDim.x) {
+        T f[19], g0[7], g1[7];
+        pull<S>(src, geo, x, 0, z, f, g0);
+        pull<S>(src, geo, x, 1, z, f, g1);
+        double th0 = 0.0, th1 = 0.0;
+        for (int i = 0; i < 7; ++i) {
+            th0 += double(g0[i]);
+            th1 += double(g1[i]);
+        }
+        const double nu = -double(n) * (9.0 * th0 - th1 - 8.0 * theta_hot) / 3.0;
+        if (map)
+            map[x + (size_t)n * z] = nu;
+        if (!isfinite(nu)) {
+            bad += 1.0;
+            continue;
+        }
+        sum += nu;
+        mx = fmax(mx, nu);
+        if (n & 1) {
+            if (x == n / 2) line += nu;
+        } else if (x == n / 2 - 1 || x == n / 2) {
+            line += 0.5 * nu;
+        }
+    }
+    __shared__ double red[4][16];
+    sum = wave_sum(sum);
+    line = wave_sum(line);
+    mx = wave_max(mx);
+    bad = wave_sum(bad);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = sum;
+        red[1][wv] = line;
+        red[2][wv] = mx;
+        red[3][wv] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double s = 0.0, l = 0.0, m = -1.0e300, b = 0.0;
+        for (int k = 0; k < nw; ++k) {
+            s += red[0][k];
+            l += red[1][k];
+            m = fmax(m, red[2][k]);
+            b += red[3][k];
+        }
+        partial[4 * z + 0] = s;
+        partial[4 * z + 1] = l;
+        partial[4 * z + 2] = m;
+        partial[4 * z + 3] = b;
+    }
+}
+
+// Combine the per-row partials in a fixed order: out = {Nu_3D, Nu_2D, Nu_max, bad}.
+__global__ __launch_bounds__(256) void k_nu_final(const double *partial, int n, double *out)
+{
+    double sum = 0.0, line = 0.0, mx = -1.0e300, bad = 0.0;
+    for (int z = threadIdx.x; z < n; z += blockDim.x) {
+        sum += partial[4 * z + 0];
+        line += partial[4 * z + 1];
+        mx = fmax(mx, partial[4 * z + 2]);
+        bad += partial[4 * z + 3];
+    }
+    __shared__ double red[4][16];
+    sum = wave_sum(sum);
+    line = wave_sum(line);
+    mx = wave_max(mx);
+    bad = wave_sum(bad);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = sum;
+        red[1][wv] = line;
+        red[2][wv] = mx;
+        red[3][wv] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double s = 0.0, l = 0.0, m = -1.0e300, b = 0.0;
+        for (int k = 0; k < nw; ++k) {
+            s += red[0][k];
+            l += red[1][k];
+            m = fmax(m, red[2][k]);
+            b += red[3][k];
+        }
+        out[0] = s / (double(n) * double(n));  // Eq. (40), midpoint rule
+        out[1] = l / double(n);                // Eq. (41), midpoint rule
+        out[2] = m;
+        out[3] = b;
+    }
+}
+
+}  // namespace lbmx

@@ -1,0 +1,742 @@
+// lbmx.hip -- host side of the C-ABI declared in include/lbmx.h.
+//
+// Li, Yang & Zhang (arXiv:1511.04633): parameters in lattice units from
+// Sec. 4 (Eq. 38), relaxation rates of Eq. (26) and Sec. 3.2 (Eqs. 35-36),
+// cavity types of Sec. 2 (Eqs. 6-10).  All arithmetic of the time step runs
+// in the kernels of kernels.hpp; this file validates, allocates, launches
+// and copies.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <new>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "../../include/lbmx.h"
+#include "kernels.hpp"
+
+using namespace lbmx;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+lbmx_status fail(lbmx_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+lbmx_status fail(lbmx_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(LBMX_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+size_t storage_size(int32_t s)
+{
+    switch (s) {
+    case LBMX_F64: return 8;
+    case LBMX_F32: return 4;
+    case LBMX_F16:
+    case LBMX_BF16: return 2;
+    default: return 0;
+    }
+}
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Derived {
+    double u_c, gbeta, nu, alpha, s_nu, tau_t;
+    double s[19], tau[7];
+};
+
+// Sec. 4, Eq. (38): Ma = u_c / c_s with c_s^2 = 1/3 (Eq. 13), u_c^2 = g beta dT H
+// (dT = 1 in units of theta), Ra = g beta dT H^3 Pr / nu^2, Pr = nu / alpha.
+// Eq. (26): s_nu = 1/(3 nu + 1/2).  Eq. (36): tau = 1/2 + alpha/epsilon, epsilon = 1/4.
+lbmx_status derive(const lbmx_params *p, Derived *d)
+{
+    if (!p)
+        return fail(LBMX_EINVAL, "params is NULL");
+    if (p->n < 4 || p->n > 1024)
+        return fail(LBMX_EINVAL, "n = %d outside [4, 1024]", p->n);
+    if (p->wall_type < 1 || p->wall_type > 3)
+        return fail(LBMX_EINVAL, "wall_type = %d not in {1, 2, 3}", p->wall_type);
+    if (!(p->ra > 0) || !std::isfinite(p->ra))
+        return fail(LBMX_EINVAL, "Ra must be positive and finite");
+    if (!(p->pr > 0) || !std::isfinite(p->pr))
+        return fail(LBMX_EINVAL, "Pr must be positive and finite");
+    if (!(p->ma > 0) || !(p->ma <= 0.5))
+        return fail(LBMX_EINVAL, "Ma = %g outside (0, 0.5]", p->ma);
+    if (!std::isfinite(p->theta_hot) || !std::isfinite(p->theta_cold) ||
+        !std::isfinite(p->theta_ref) || !std::isfinite(p->buoyancy_scale))
+        return fail(LBMX_EINVAL, "non-finite temperature or buoyancy parameter");
+    if (storage_size(p->storage) == 0)
+        return fail(LBMX_EINVAL, "storage = %d not a lbmx_storage", p->storage);
+    const double u_c = p->ma * std::sqrt(1.0 / 3.0);
+    d->u_c = u_c;
+    d->gbeta = u_c * u_c / p->n;
+    d->nu = u_c * p->n * std::sqrt(p->pr / p->ra);
+    d->alpha = d->nu / p->pr;
+    d->s_nu = 1.0 / (3.0 * d->nu + 0.5);
+    d->tau_t = 0.5 + 4.0 * d->alpha;
+    if (p->custom_rates) {
+        for (int k = 0; k < 19; ++k) {
+            if (!(p->s[k] >= 0.0 && p->s[k] <= 2.0))
+                return fail(LBMX_EINVAL, "custom s[%d] = %g outside [0, 2]", k, p->s[k]);
+            d->s[k] = p->s[k];
+        }
+        for (int k = 0; k < 7; ++k) {
+            if (!(p->tau[k] > 0.0) || !std::isfinite(p->tau[k]))
+                return fail(LBMX_EINVAL, "custom tau[%d] = %g not positive", k, p->tau[k]);
+            d->tau[k] = p->tau[k];
+        }
+        if (!(d->tau[1] > 0.5 && d->tau[2] > 0.5 && d->tau[3] > 0.5))
+            return fail(LBMX_EINVAL, "custom diffusion rates need tau > 1/2");
+    } else {
+        if (!(d->s_nu > 0.0 && d->s_nu < 2.0))
+            return fail(LBMX_EINVAL, "s_nu = %g outside (0, 2)", d->s_nu);
+        if (!(d->tau_t > 0.5))
+            return fail(LBMX_EINVAL, "tau_T = %g not above 1/2", d->tau_t);
+        const double sn = d->s_nu;
+        const double s[19] = {1.0, 1.19, 1.4, 1.0, 1.2, 1.0, 1.2, 1.0, 1.2, sn,
+                              1.4, sn,   1.4, sn,  sn,  sn,  1.98, 1.98, 1.98};
+        for (int k = 0; k < 19; ++k)
+            d->s[k] = s[k];
+        const double tau[7] = {1.0, d->tau_t, d->tau_t, d->tau_t, 1.0, 1.0, 1.0};
+        for (int k = 0; k < 7; ++k)
+            d->tau[k] = tau[k];
+    }
+    return LBMX_OK;
+}
+
+template <typename T>
+Rates<T> make_rates(const lbmx_params *p, const Derived &d)
+{
+    // s_k / |M_k|^2 with the squared row norms of Eq. (21) (rows orthogonal).
+    Rates<T> r;
+    r.e = T(d.s[1] / 2394.0);
+    r.eps = T(d.s[2] / 252.0);
+    r.qx = T(d.s[4] / 40.0);
+    r.qy = T(d.s[6] / 40.0);
+    r.qz = T(d.s[8] / 40.0);
+    r.pxx = T(d.s[9] / 36.0);
+    r.pixx = T(d.s[10] / 72.0);
+    r.pww = T(d.s[11] / 12.0);
+    r.piww = T(d.s[12] / 24.0);
+    r.pxy = T(d.s[13] / 4.0);
+    r.pyz = T(d.s[14] / 4.0);
+    r.pxz = T(d.s[15] / 4.0);
+    r.mx = T(d.s[16] / 8.0);
+    r.my = T(d.s[17] / 8.0);
+    r.mz = T(d.s[18] / 8.0);
+    // Q = (Q^-1)^-1 for diagonal Q^-1 (Eq. 35), over |N_k|^2 of Eq. (32).
+    r.t1 = T(1.0 / d.tau[1] / 2.0);
+    r.t2 = T(1.0 / d.tau[2] / 2.0);
+    r.t3 = T(1.0 / d.tau[3] / 2.0);
+    r.t4 = T(1.0 / d.tau[4] / 42.0);
+    r.t5 = T(1.0 / d.tau[5] / 12.0);
+    r.t6 = T(1.0 / d.tau[6] / 4.0);
+    r.gbeta = T(d.gbeta * p->buoyancy_scale);
+    r.theta_ref = T(p->theta_ref);
+    return r;
+}
+
+struct Layout {
+    size_t plane;        // elements per population plane
+    size_t lattice;      // bytes per lattice
+    size_t scratch_off;  // byte offset of the Nu scratch
+    size_t total;
+};
+
+Layout layout_of(const lbmx_params *p)
+{
+    Layout L;
+    const size_t cells = (size_t)p->n * p->n * p->n;
+    L.plane = align_up(cells, 128);
+    L.lattice = align_up(26 * L.plane * storage_size(p->storage), 256);
+    L.scratch_off = 2 * L.lattice;
+    L.total = L.scratch_off + align_up(sizeof(double) * (4 * (size_t)p->n + 8), 256);
+    return L;
+}
+
+}  // namespace
+
+struct lbmx_cavity {
+    lbmx_params p;
+    Derived d;
+    Layout L;
+    hipStream_t stream;
+    bool own_stream;
+    char *ws;
+    bool own_ws;
+    int cur;
+    int64_t t;
+    int bx, by;
+};
+
+namespace {
+
+template <typename S>
+Geometry<typename Codec<S>::T> geometry(const lbmx_cavity *h)
+{
+    using T = typename Codec<S>::T;
+    Geometry<T> g;
+    g.n = h->p.n;
+    g.wall_type = h->p.wall_type;
+    g.theta_hot = T(h->p.theta_hot);
+    g.theta_cold = T(h->p.theta_cold);
+    g.plane = h->L.plane;
+    return g;
+}
+
+template <typename S>
+S *lattice(lbmx_cavity *h, int k)
+{
+    return reinterpret_cast<S *>(h->ws + (size_t)k * h->L.lattice);
+}
+
+double *scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L.scratch_off); }
+
+void default_launch(int n, int *bx, int *by)
+{
+    *bx = n < 256 ? n : 256;
+    int b = 256 / *bx;
+    if (b < 1) b = 1;
+    if (b > n) b = n;
+    *by = b;
+}
+
+template <typename S>
+lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
+{
+    using T = typename Codec<S>::T;
+    const Geometry<T> geo = geometry<S>(h);
+    const Rates<T> rates = make_rates<T>(&h->p, h->d);
+    const int n = h->p.n;
+    dim3 block(h->bx, h->by, 1);
+    dim3 grid((n + h->bx - 1) / h->bx, (n + h->by - 1) / h->by, n);
+    for (int64_t s = 0; s < nsteps; ++s) {
+        hipLaunchKernelGGL(k_step<S>, grid, block, 0, h->stream, lattice<S>(h, h->cur),
+                           lattice<S>(h, 1 - h->cur), geo, rates);
+        h->cur = 1 - h->cur;
+        h->t += 1;
+    }
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+template <typename S, typename Src>
+lbmx_status launch_unstream(lbmx_cavity *h, const Src &src)
+{
+    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
+    const int threads = 256;
+    const unsigned blocks = (unsigned)((cells + threads - 1) / threads);
+    hipLaunchKernelGGL((k_unstream<S, Src>), dim3(blocks), dim3(threads), 0, h->stream,
+                       lattice<S>(h, h->cur), geometry<S>(h), src);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+template <typename S>
+lbmx_status launch_macro(lbmx_cavity *h, double *r, double *u, double *v, double *w, double *th)
+{
+    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
+    const unsigned blocks = (unsigned)((cells + 255) / 256);
+    hipLaunchKernelGGL(k_macro<S>, dim3(blocks), dim3(256), 0, h->stream, lattice<S>(h, h->cur),
+                       geometry<S>(h), r, u, v, w, th);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+template <typename S>
+lbmx_status launch_pops(lbmx_cavity *h, double *f, double *g)
+{
+    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
+    const unsigned blocks = (unsigned)((cells + 255) / 256);
+    hipLaunchKernelGGL(k_pops<S>, dim3(blocks), dim3(256), 0, h->stream, lattice<S>(h, h->cur),
+                       geometry<S>(h), f, g);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+template <typename S>
+lbmx_status launch_nu(lbmx_cavity *h, double *map)
+{
+    const int n = h->p.n;
+    double *part = scratch(h);
+    double *out = part + 4 * (size_t)n;
+    const int threads = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
+    hipLaunchKernelGGL(k_nu_rows<S>, dim3(n), dim3(threads), 0, h->stream, lattice<S>(h, h->cur),
+                       geometry<S>(h), h->p.theta_hot, part, map);
+    hipLaunchKernelGGL(k_nu_final, dim3(1), dim3(256), 0, h->stream, part, n, out);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+// Dispatch a templated launcher on the storage type.
+#define DISPATCH(h, fn, ...)                                                   \
+    ([&]() -> lbmx_status {                                                    \
+        switch ((h)->p.storage) {                                              \
+        case LBMX_F64: return fn<double>(__VA_ARGS__);                         \
+        case LBMX_F32: return fn<float>(__VA_ARGS__);                          \
+        case LBMX_F16: return fn<__half>(__VA_ARGS__);                         \
+        case LBMX_BF16: return fn<__hip_bfloat16>(__VA_ARGS__);                \
+        default: return fail(LBMX_EINVAL, "bad storage");                      \
+        }                                                                      \
+    }())
+
+template <typename S>
+lbmx_status unstream_rest(lbmx_cavity *h, const double *theta0)
+{
+    SourceRest s{theta0};
+    return launch_unstream<S>(h, s);
+}
+
+template <typename S>
+lbmx_status unstream_pops(lbmx_cavity *h, const double *f, const double *g)
+{
+    SourcePops s{f, g, (size_t)h->p.n * h->p.n * h->p.n};
+    return launch_unstream<S>(h, s);
+}
+
+template <typename S>
+lbmx_status unstream_fields(lbmx_cavity *h, const float *u, const float *v, const float *w,
+                            const float *th, int src_n)
+{
+    SourceFields s{u, v, w, th, src_n, h->p.n};
+    return launch_unstream<S>(h, s);
+}
+
+// Device buffer released at scope exit.
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+};
+
+lbmx_status check_handle(const lbmx_cavity *h)
+{
+    if (!h)
+        return fail(LBMX_EINVAL, "cavity handle is NULL");
+    return LBMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbmx_status lbmx_params_default(lbmx_params *p)
+{
+    if (!p)
+        return fail(LBMX_EINVAL, "params is NULL");
+    std::memset(p, 0, sizeof(*p));
+    p->n = 16;
+    p->wall_type = 1;
+    p->ra = 1e3;
+    p->pr = 0.71;
+    p->ma = 0.1;
+    p->theta_hot = 0.5;
+    p->theta_cold = -0.5;
+    p->theta_ref = 0.0;
+    p->buoyancy_scale = 1.0;
+    p->storage = LBMX_F32;
+    p->custom_rates = 0;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_derive(const lbmx_params *p, double *out)
+{
+    if (!out)
+        return fail(LBMX_EINVAL, "out is NULL");
+    Derived d;
+    lbmx_status s = derive(p, &d);
+    if (s != LBMX_OK)
+        return s;
+    out[0] = d.u_c;
+    out[1] = d.gbeta;
+    out[2] = d.nu;
+    out[3] = d.alpha;
+    out[4] = d.s_nu;
+    out[5] = d.tau_t;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_workspace_bytes(const lbmx_params *p, size_t *bytes)
+{
+    if (!bytes)
+        return fail(LBMX_EINVAL, "bytes is NULL");
+    Derived d;
+    lbmx_status s = derive(p, &d);
+    if (s != LBMX_OK)
+        return s;
+    *bytes = layout_of(p).total;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_bytes_per_cell(int32_t storage, double *bytes)
+{
+    if (!bytes)
+        return fail(LBMX_EINVAL, "bytes is NULL");
+    const size_t b = storage_size(storage);
+    if (!b)
+        return fail(LBMX_EINVAL, "storage = %d not a lbmx_storage", storage);
+    *bytes = 26.0 * 2.0 * double(b);
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_create(const lbmx_params *p, void *dev_workspace, size_t ws_bytes, void *stream,
+                        lbmx_cavity **out)
+{
+    if (!out)
+        return fail(LBMX_EINVAL, "out is NULL");
+    *out = nullptr;
+    Derived d;
+    lbmx_status s = derive(p, &d);
+    if (s != LBMX_OK)
+        return s;
+    const Layout L = layout_of(p);
+    if (dev_workspace) {
+        if (ws_bytes < L.total)
+            return fail(LBMX_EINVAL, "workspace of %zu bytes, need %zu", ws_bytes, L.total);
+        if (reinterpret_cast<uintptr_t>(dev_workspace) % 256)
+            return fail(LBMX_EINVAL, "workspace not 256-byte aligned");
+    }
+    lbmx_cavity *h = new (std::nothrow) lbmx_cavity();
+    if (!h)
+        return fail(LBMX_ENOMEM, "host allocation failed");
+    h->p = *p;
+    h->d = d;
+    h->L = L;
+    h->cur = 0;
+    h->t = 0;
+    default_launch(p->n, &h->bx, &h->by);
+    if (stream) {
+        h->stream = reinterpret_cast<hipStream_t>(stream);
+        h->own_stream = false;
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete h;
+            return fail(LBMX_EDEVICE, "hipStreamCreate failed: %s", hipGetErrorString(e));
+        }
+        h->own_stream = true;
+    }
+    if (dev_workspace) {
+        h->ws = reinterpret_cast<char *>(dev_workspace);
+        h->own_ws = false;
+    } else {
+        void *m = nullptr;
+        hipError_t e = hipMalloc(&m, L.total);
+        if (e != hipSuccess) {
+            if (h->own_stream)
+                (void)hipStreamDestroy(h->stream);
+            delete h;
+            return fail(e == hipErrorOutOfMemory ? LBMX_ENOMEM : LBMX_EDEVICE,
+                        "hipMalloc(%zu) failed: %s", L.total, hipGetErrorString(e));
+        }
+        h->ws = reinterpret_cast<char *>(m);
+        h->own_ws = true;
+    }
+    s = lbmx_init_rest(h, nullptr);
+    if (s != LBMX_OK) {
+        lbmx_destroy(h);
+        return s;
+    }
+    *out = h;
+    return LBMX_OK;
+}
+
+void lbmx_destroy(lbmx_cavity *h)
+{
+    if (!h)
+        return;
+    (void)hipStreamSynchronize(h->stream);
+    if (h->own_ws)
+        (void)hipFree(h->ws);
+    if (h->own_stream)
+        (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+lbmx_status lbmx_init_rest(lbmx_cavity *h, const double *theta0_host)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
+    DevBuf buf;
+    if (theta0_host) {
+        HIP_TRY(hipMalloc(&buf.p, cells * sizeof(double)));
+        HIP_TRY(hipMemcpyAsync(buf.p, theta0_host, cells * sizeof(double), hipMemcpyHostToDevice,
+                               h->stream));
+    }
+    h->cur = 0;
+    s = DISPATCH(h, unstream_rest, h, reinterpret_cast<const double *>(buf.p));
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->t = 0;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_set_populations(lbmx_cavity *h, const double *f_host, const double *g_host,
+                                 int64_t t)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!f_host || !g_host)
+        return fail(LBMX_EINVAL, "population arrays must not be NULL");
+    if (t < 0)
+        return fail(LBMX_EINVAL, "t must be >= 0");
+    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
+    DevBuf buf;
+    HIP_TRY(hipMalloc(&buf.p, 26 * cells * sizeof(double)));
+    double *fd = reinterpret_cast<double *>(buf.p);
+    double *gd = fd + 19 * cells;
+    HIP_TRY(hipMemcpyAsync(fd, f_host, 19 * cells * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    HIP_TRY(hipMemcpyAsync(gd, g_host, 7 * cells * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    s = DISPATCH(h, unstream_pops, h, fd, gd);
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->t = t;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
+    DevBuf buf;
+    HIP_TRY(hipMalloc(&buf.p, 26 * cells * sizeof(double)));
+    double *fd = reinterpret_cast<double *>(buf.p);
+    double *gd = fd + 19 * cells;
+    s = DISPATCH(h, launch_pops, h, f_host ? fd : nullptr, g_host ? gd : nullptr);
+    if (s != LBMX_OK)
+        return s;
+    if (f_host)
+        HIP_TRY(hipMemcpyAsync(f_host, fd, 19 * cells * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    if (g_host)
+        HIP_TRY(hipMemcpyAsync(g_host, gd, 7 * cells * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *dev_v,
+                             const float *dev_w, const float *dev_theta, int32_t src_n)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!dev_u || !dev_v || !dev_w || !dev_theta)
+        return fail(LBMX_EINVAL, "field pointers must not be NULL");
+    if (src_n < 1 || src_n > 4096)
+        return fail(LBMX_EINVAL, "src_n = %d outside [1, 4096]", src_n);
+    h->cur = 0;
+    s = DISPATCH(h, unstream_fields, h, dev_u, dev_v, dev_w, dev_theta, src_n);
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->t = 0;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_step(lbmx_cavity *h, int64_t nsteps)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (nsteps < 0)
+        return fail(LBMX_EINVAL, "nsteps must be >= 0");
+    return DISPATCH(h, launch_steps, h, nsteps);
+}
+
+lbmx_status lbmx_step_timed(lbmx_cavity *h, int64_t nsteps, double *ms)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!ms || nsteps < 0)
+        return fail(LBMX_EINVAL, "ms is NULL or nsteps < 0");
+    hipEvent_t a, b;
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    hipError_t e = hipEventRecord(a, h->stream);
+    if (e == hipSuccess) {
+        s = DISPATCH(h, launch_steps, h, nsteps);
+        e = hipEventRecord(b, h->stream);
+    }
+    if (e == hipSuccess)
+        e = hipEventSynchronize(b);
+    float msf = 0.0f;
+    if (e == hipSuccess)
+        e = hipEventElapsedTime(&msf, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (s != LBMX_OK)
+        return s;
+    if (e != hipSuccess)
+        return fail(LBMX_EDEVICE, "event timing failed: %s", hipGetErrorString(e));
+    *ms = msf;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_time(const lbmx_cavity *h, int64_t *t)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!t)
+        return fail(LBMX_EINVAL, "t is NULL");
+    *t = h->t;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_read_macro(lbmx_cavity *h, double *rho, double *ux, double *uy, double *uz,
+                            double *theta)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
+    double *host[5] = {rho, ux, uy, uz, theta};
+    DevBuf buf;
+    HIP_TRY(hipMalloc(&buf.p, 5 * cells * sizeof(double)));
+    double *dev[5];
+    for (int k = 0; k < 5; ++k)
+        dev[k] = host[k] ? reinterpret_cast<double *>(buf.p) + k * cells : nullptr;
+    s = DISPATCH(h, launch_macro, h, dev[0], dev[1], dev[2], dev[3], dev[4]);
+    if (s != LBMX_OK)
+        return s;
+    for (int k = 0; k < 5; ++k)
+        if (host[k])
+            HIP_TRY(hipMemcpyAsync(host[k], dev[k], cells * sizeof(double), hipMemcpyDeviceToHost,
+                                   h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!out)
+        return fail(LBMX_EINVAL, "out is NULL");
+    const int n = h->p.n;
+    DevBuf mbuf;
+    if (map_host)
+        HIP_TRY(hipMalloc(&mbuf.p, (size_t)n * n * sizeof(double)));
+    s = DISPATCH(h, launch_nu, h, reinterpret_cast<double *>(mbuf.p));
+    if (s != LBMX_OK)
+        return s;
+    double res[4];
+    HIP_TRY(hipMemcpyAsync(res, scratch(h) + 4 * (size_t)n, sizeof(res), hipMemcpyDeviceToHost,
+                           h->stream));
+    if (map_host)
+        HIP_TRY(hipMemcpyAsync(map_host, mbuf.p, (size_t)n * n * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    out->nu3d = res[0];
+    out->nu2d = res[1];
+    out->numax = res[2];
+    out->step = h->t;
+    out->nonfinite = (int32_t)res[3];
+    if (out->nonfinite > 0 || !std::isfinite(res[0]))
+        return fail(LBMX_EUNSTABLE, "%d non-finite local Nu values at t = %lld", out->nonfinite,
+                    (long long)h->t);
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_run_to_steady(lbmx_cavity *h, double tol, int64_t every, int64_t max_steps,
+                               lbmx_nu *out)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!out || !(tol > 0) || every < 1 || max_steps < 0)
+        return fail(LBMX_EINVAL, "need out != NULL, tol > 0, every >= 1, max_steps >= 0");
+    const int64_t t0 = h->t;
+    s = lbmx_nusselt(h, out, nullptr);
+    if (s != LBMX_OK)
+        return s;
+    double prev = out->nu3d;
+    while (h->t - t0 < max_steps) {
+        int64_t k = every;
+        if (h->t - t0 + k > max_steps)
+            k = max_steps - (h->t - t0);
+        s = lbmx_step(h, k);
+        if (s != LBMX_OK)
+            return s;
+        s = lbmx_nusselt(h, out, nullptr);
+        if (s != LBMX_OK)
+            return s;
+        if (k == every && std::fabs(out->nu3d - prev) < tol)
+            return LBMX_OK;
+        prev = out->nu3d;
+    }
+    return fail(LBMX_ENOTCONVERGED, "no steady Nu within %lld steps", (long long)max_steps);
+}
+
+lbmx_status lbmx_set_launch(lbmx_cavity *h, int32_t bx, int32_t by)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (bx == 0 && by == 0) {
+        default_launch(h->p.n, &h->bx, &h->by);
+        return LBMX_OK;
+    }
+    if (bx < 1 || by < 1 || (long)bx * by > 1024)
+        return fail(LBMX_EINVAL, "launch (%d, %d) needs 1 <= bx*by <= 1024", bx, by);
+    h->bx = bx;
+    h->by = by;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_get_launch(const lbmx_cavity *h, int32_t *bx, int32_t *by)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!bx || !by)
+        return fail(LBMX_EINVAL, "NULL output");
+    *bx = h->bx;
+    *by = h->by;
+    return LBMX_OK;
+}
+
+const char *lbmx_strerror(lbmx_status s)
+{
+    switch (s) {
+    case LBMX_OK: return "ok";
+    case LBMX_EINVAL: return "invalid argument";
+    case LBMX_ENOMEM: return "out of memory";
+    case LBMX_EDEVICE: return "HIP runtime error";
+    case LBMX_EUNSTABLE: return "non-finite values (run diverged)";
+    case LBMX_ENOTCONVERGED: return "not converged within max_steps";
+    case LBMX_ESTATE: return "invalid state for this call";
+    default: return "unknown status";
+    }
+}
+
+const char *lbmx_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+"""The C-ABI library loads and exports what include/lbmx.h declares; the
+host-only calls (parameter derivation and validation, sizes, error strings)
+work without a GPU."""
+import ctypes
+import math
+import os
+import re
+import subprocess
+
+import pytest
+
+from oracle import oracle as O
+from paper_1511_04633_amd import lbmx as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "lbmx.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbmx_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(L.SYMBOLS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r"\bT (lbmx_\w+)", out))
+    assert set(declared_functions()) <= exported
+
+
+def test_params_struct_layout_matches_header():
+    """The ctypes mirror has the C struct's size: 4+4 + 7*8 + 4+4 + 19*8 + 7*8."""
+    assert ctypes.sizeof(L.lbmx_params) == 8 + 56 + 8 + 152 + 56
+    assert ctypes.sizeof(L.lbmx_nu) == 40
+
+
+def test_derived_parameters_match_the_oracle():
+    """Host derivation in the library (Eq. 38, 26, 36) equals the oracle's."""
+    for n, ra in ((16, 1e3), (50, 1e4), (60, 1e5), (128, 1e5), (256, 1e6), (32, 1e6)):
+        got = L.derive(L.make_params(n=n, ra=ra))
+        want = O.derive(n, ra)
+        for k in want:
+            assert math.isclose(got[k], want[k], rel_tol=1e-15), (k, got[k], want[k])
+
+
+def test_invalid_parameters_rejected_on_host():
+    bad = [dict(n=3), dict(n=2048), dict(wall_type=0), dict(wall_type=4), dict(ra=0.0),
+           dict(ra=-1.0), dict(pr=0.0), dict(ma=0.0), dict(ma=0.9), dict(storage=7),
+           dict(ra=float("inf")), dict(theta_hot=float("nan"))]
+    for kw in bad:
+        p = L.make_params(**kw)
+        with pytest.raises(L.LbmxError) as e:
+            L.derive(p)
+        assert e.value.status == 1, kw
+    with pytest.raises(L.LbmxError):
+        L.derive(L.make_params(s=[1.0] * 19, tau=[1.0, 0.4, 1, 1, 1, 1, 1]))
+    with pytest.raises(L.LbmxError):
+        L.derive(L.make_params(s=[2.5] + [1.0] * 18, tau=[1.0] * 7))
+
+
+def test_sizes():
+    assert L.bytes_per_cell("f64") == 416.0
+    assert L.bytes_per_cell("f32") == 208.0
+    assert L.bytes_per_cell("f16") == 104.0 and L.bytes_per_cell("bf16") == 104.0
+    p = L.make_params(n=256, ra=1e6, storage="f32")
+    ws = L.workspace_bytes(p)
+    assert ws >= 2 * 26 * 256 ** 3 * 4
+    assert ws < 2 * 26 * 256 ** 3 * 4 * 1.01
+
+
+def test_error_strings():
+    lib = L.load()
+    for s in range(7):
+        assert lib.lbmx_strerror(s)
+    assert lib.lbmx_strerror(99) == b"unknown status"
+
+
+def test_null_arguments():
+    lib = L.load()
+    assert lib.lbmx_derive(None, None) == 1
+    assert lib.lbmx_step(None, 1) == 1
+    assert lib.lbmx_nusselt(None, None, None) == 1
+    lib.lbmx_destroy(None)

@@ -1,0 +1,196 @@
+"""GPU parity: the HIP library against the FP64 oracle, element by element.
+
+Metric (fields after a fixed number of steps, same seeded inputs):
+  u components and theta: max|X - X_ref| / max|X_ref|;  rho: max|rho - rho_ref|.
+Bars: FP64 storage 1e-10 (and 1e-13 for a single step); FP32 storage 1e-5.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1511_04633_amd import inputs
+from paper_1511_04633_amd import lbmx as L
+
+pytestmark = pytest.mark.gpu
+
+SEED = 20151115
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    L.load()
+    O.build(force=False)
+
+
+def rel_err(a, b):
+    scale = np.abs(b).max()
+    return np.abs(a - b).max() / (scale if scale > 0 else 1.0)
+
+
+def compare(gpu, ora, tol, tol_rho=None):
+    g = gpu.read_macro()
+    o = ora.macro()
+    names = ["rho", "ux", "uy", "uz", "theta"]
+    errs = {}
+    for k, name in enumerate(names):
+        if name == "rho":
+            errs[name] = np.abs(g[k] - o[k]).max()
+        else:
+            errs[name] = rel_err(g[k], o[k])
+    trho = tol if tol_rho is None else tol_rho
+    bad = {k: v for k, v in errs.items() if v > (trho if k == "rho" else tol)}
+    assert not bad, f"parity errors above {tol}: {errs}"
+    return errs
+
+
+def run_pair(n, wall_type, ra, steps, storage, seed=SEED, **kw):
+    th0 = inputs.theta_noise(n, seed)
+    ora = O.Oracle(n, wall_type, ra=ra, theta0=th0, **kw)
+    gpu = L.Cavity(n=n, wall_type=wall_type, ra=ra, storage=storage, theta0=th0, **kw)
+    ora.step(steps)
+    gpu.step(steps)
+    return gpu, ora
+
+
+def test_f64_config1_16cube_2000_steps():
+    """16^3, Type 1, Ra 1e3, rest + uniform +-1e-6 theta noise, 2000 steps, FP64."""
+    print("case: f64 16^3 T1 Ra1e3 2000 steps", flush=True)
+    gpu, ora = run_pair(16, 1, 1e3, 2000, "f64")
+    compare(gpu, ora, 1e-10, tol_rho=1e-13)
+    ng, no = gpu.nusselt(with_map=True), ora.nusselt(with_map=True)
+    for k in ("nu3d", "nu2d", "numax"):
+        assert abs(ng[k] - no[k]) <= 1e-10 * abs(no[k]), (k, ng[k], no[k])
+    assert np.abs(ng["map"] - no["map"]).max() <= 1e-10 * np.abs(no["map"]).max()
+    assert gpu.t == 2000
+
+
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
+@pytest.mark.parametrize("n", [5, 13, 33])
+def test_f64_all_types_ragged_sizes(n, wall_type):
+    """Sizes that leave ragged blocks and odd centre lines, every wall type."""
+    print(f"case: f64 n={n} T{wall_type} Ra1e5 300 steps", flush=True)
+    gpu, ora = run_pair(n, wall_type, 1e5, 300, "f64")
+    compare(gpu, ora, 1e-10, tol_rho=1e-13)
+    ng, no = gpu.nusselt(), ora.nusselt()
+    for k in ("nu3d", "nu2d", "numax"):
+        assert abs(ng[k] - no[k]) <= 1e-10 * max(1.0, abs(no[k]))
+
+
+def test_f64_custom_rates():
+    """Every relaxation rate set to a distinct value exercises each moment path."""
+    print("case: f64 custom rates 12^3 T3", flush=True)
+    rng = np.random.default_rng(11)
+    s = rng.uniform(0.6, 1.9, 19)
+    tau = np.concatenate([[1.0], rng.uniform(0.55, 1.4, 6)])
+    th0 = inputs.theta_noise(12, SEED + 1, amp=1e-2)
+    ora = O.Oracle(12, 3, ra=1e5, s19=s, tau7=tau, theta0=th0)
+    gpu = L.Cavity(n=12, wall_type=3, ra=1e5, storage="f64", s=s, tau=tau, theta0=th0)
+    ora.step(200)
+    gpu.step(200)
+    compare(gpu, ora, 1e-10, tol_rho=1e-13)
+
+
+def test_f64_single_step_from_developed_state():
+    """Load the oracle's developed state into the GPU and take one step."""
+    print("case: f64 single step from oracle state 11^3 T2", flush=True)
+    n = 11
+    ora = O.Oracle(n, 2, ra=1e5, theta0=inputs.theta_noise(n, SEED, amp=1e-2))
+    ora.step(400)
+    f, g = ora.get_state()
+    gpu = L.Cavity(n=n, wall_type=2, ra=1e5, storage="f64")
+    gpu.set_populations(f, g, t=ora.t)
+    fr, gr = gpu.get_populations()
+    assert np.abs(fr - f).max() <= 2e-16 and np.abs(gr - g).max() <= 1e-16
+    ora.step(1)
+    gpu.step(1)
+    fo, go = ora.get_state()
+    fg, gg = gpu.get_populations()
+    assert np.abs(fg - fo).max() <= 1e-15
+    assert np.abs(gg - go).max() <= 1e-15
+    assert gpu.t == ora.t
+
+
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
+@pytest.mark.parametrize("n", [16, 64])
+def test_f32_fields_after_1000_steps(n, wall_type):
+    """FP32 storage and arithmetic against the FP64 oracle: 1e-5 on fields."""
+    print(f"case: f32 n={n} T{wall_type} Ra1e5 1000 steps", flush=True)
+    gpu, ora = run_pair(n, wall_type, 1e5, 1000, "f32")
+    errs = compare(gpu, ora, 1e-5, tol_rho=1e-6)
+    print(errs)
+    ng, no = gpu.nusselt(), ora.nusselt()
+    assert abs(ng["nu3d"] - no["nu3d"]) <= 1e-5 * abs(no["nu3d"])
+
+
+def test_launch_shape_does_not_change_results():
+    """Each node's update is independent of the block shape: bitwise equal."""
+    print("case: launch shapes 24^3 f32", flush=True)
+    th0 = inputs.theta_noise(24, SEED)
+    ref = None
+    for bx, by in ((24, 8), (24, 1), (8, 8), (64, 1), (5, 7)):
+        c = L.Cavity(n=24, wall_type=2, ra=1e5, storage="f32", theta0=th0)
+        c.set_launch(bx, by)
+        assert c.get_launch() == (bx, by)
+        c.step(50)
+        f, g = c.get_populations()
+        if ref is None:
+            ref = (f, g)
+        else:
+            assert np.array_equal(f, ref[0]) and np.array_equal(g, ref[1])
+
+
+def test_zero_steps_and_reinit():
+    c = L.Cavity(n=8, wall_type=1, ra=1e4, storage="f64", theta0=inputs.theta_noise(8, 1))
+    f0, g0 = c.get_populations()
+    c.step(0)
+    f1, g1 = c.get_populations()
+    assert np.array_equal(f0, f1) and np.array_equal(g0, g1) and c.t == 0
+    c.step(5)
+    c.init_rest(inputs.theta_noise(8, 1))
+    f2, g2 = c.get_populations()
+    assert np.array_equal(f0, f2) and np.array_equal(g0, g2) and c.t == 0
+
+
+def test_minimum_size_and_rest_state():
+    """n = 4, uniform theta = theta_ref: the fluid stays exactly at rest."""
+    c = L.Cavity(n=4, wall_type=3, ra=1e4, storage="f32", theta_hot=0.0, theta_cold=0.0)
+    c.step(100)
+    rho, ux, uy, uz, th = c.read_macro()
+    assert np.abs(np.stack([ux, uy, uz])).max() == 0.0
+    assert np.abs(th).max() == 0.0
+
+
+def test_conduction_limit_gpu():
+    """No buoyancy: theta converges to the linear profile and Nu to 1 (FP64)."""
+    n = 8
+    c = L.Cavity(n=n, wall_type=2, ra=100.0, storage="f64", buoyancy_scale=0.0)
+    c.step(6000)
+    th = c.read_macro()[4]
+    lin = 0.5 - (np.arange(n) + 0.5) / n
+    assert np.abs(th - lin[None, :, None]).max() < 1e-12
+    nu = c.nusselt()
+    assert abs(nu["nu3d"] - 1) < 1e-11 and abs(nu["numax"] - 1) < 1e-11
+
+
+def test_determinism():
+    th0 = inputs.theta_noise(20, 5)
+    out = []
+    for _ in range(2):
+        c = L.Cavity(n=20, wall_type=1, ra=1e5, storage="f32", theta0=th0)
+        c.step(100)
+        out.append(c.get_populations())
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def test_invalid_parameters_raise():
+    with pytest.raises(L.LbmxError):
+        L.Cavity(n=3)
+    with pytest.raises(L.LbmxError):
+        L.Cavity(n=16, wall_type=4)
+    c = L.Cavity(n=8)
+    with pytest.raises(L.LbmxError):
+        c.step(-1)
+    with pytest.raises(L.LbmxError):
+        c.set_launch(2048, 1)
