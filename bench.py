@@ -43,6 +43,32 @@ def cpu_baseline(seconds: float, n: int = 64, ra: float = 1e6, wall_type: int = 
             "sample": f"FP64 oracle, {n}^3 Type {wall_type} Ra {ra:g}, {steps} steps in {dt:.1f} s"}
 
 
+def bpc_of(storage):
+    return {"f64": 416, "f32": 208, "f16": 104, "bf16": 104}[storage]
+
+
+def copy_probe(nbytes: int, reps: int = 20) -> float:
+    """Bandwidth of a plain device-to-device copy moving the same bytes as one
+    step (nbytes read + nbytes written), timed with events on torch's stream:
+    the practical HBM ceiling next to the 8 TB/s peak."""
+    import torch
+
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    b.synchronize()
+    ms = a.elapsed_time(b) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * nbytes / (ms / 1e3) / 1e9
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -55,6 +81,8 @@ def main():
     ap.add_argument("--launch", default="", help="bx,by override of the step kernel block")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true",
+                    help="skip timing a plain device copy of the same bytes")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -85,6 +113,7 @@ def main():
     wall = time.perf_counter() - t0
 
     nu = cav.nusselt()
+    copy_gbs = None if args.no_copy_probe else copy_probe(n * n * n * 26 * (bpc_of(args.storage) // 52))
     cells = n ** 3
     mlups = cells * args.steps / wall / 1e6
     bpc = lbmx.bytes_per_cell(args.storage)
@@ -111,7 +140,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None, "bytes_per_cell": bpc,
-                     "kernel_us": round(kernel_s * 1e6, 2)},
+                     "kernel_us": round(kernel_s * 1e6, 2),
+                     "copy_achieved": None if copy_gbs is None else round(copy_gbs, 1)},
         "nu3d_after": nu["nu3d"],
     }
     if not args.no_cpu_baseline:

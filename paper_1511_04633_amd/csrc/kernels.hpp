@@ -24,6 +24,9 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <cstdint>
+#include <type_traits>
+
 #include "collide.hpp"
 
 namespace lbmx {
@@ -36,41 +39,45 @@ namespace lbmx {
 template <typename S>
 struct Codec;
 
+// `Raw` is the bit container written with non-temporal stores; `inv_w` is
+// the exact reciprocal of the lattice weight (3, 18, 36 for D3Q19; 4, 8 for
+// D3Q7) so encoding is a multiply, not a division.
 template <>
 struct Codec<double> {
     using T = double;
-    static __device__ __forceinline__ T dec_f(double v, T) { return v; }
-    static __device__ __forceinline__ double enc_f(T v, T) { return v; }
-    static __device__ __forceinline__ T dec_g(double v, T) { return v; }
-    static __device__ __forceinline__ double enc_g(T v, T) { return v; }
+    using Raw = double;
+    static __device__ __forceinline__ T dec(double v, T) { return v; }
+    static __device__ __forceinline__ Raw enc(T v, T) { return v; }
 };
 
 template <>
 struct Codec<float> {
     using T = float;
-    static __device__ __forceinline__ T dec_f(float v, T) { return v; }
-    static __device__ __forceinline__ float enc_f(T v, T) { return v; }
-    static __device__ __forceinline__ T dec_g(float v, T) { return v; }
-    static __device__ __forceinline__ float enc_g(T v, T) { return v; }
+    using Raw = float;
+    static __device__ __forceinline__ T dec(float v, T) { return v; }
+    static __device__ __forceinline__ Raw enc(T v, T) { return v; }
 };
 
 template <>
 struct Codec<__half> {
     using T = float;
-    // w is the lattice weight of the population.
-    static __device__ __forceinline__ T dec_f(__half v, T w) { return __half2float(v) * w; }
-    static __device__ __forceinline__ __half enc_f(T v, T w) { return __float2half_rn(v / w); }
-    static __device__ __forceinline__ T dec_g(__half v, T w) { return __half2float(v) * w; }
-    static __device__ __forceinline__ __half enc_g(T v, T w) { return __float2half_rn(v / w); }
+    using Raw = unsigned short;
+    static __device__ __forceinline__ T dec(__half v, T w) { return __half2float(v) * w; }
+    static __device__ __forceinline__ Raw enc(T v, T inv_w)
+    {
+        return __half_as_ushort(__float2half_rn(v * inv_w));
+    }
 };
 
 template <>
 struct Codec<__hip_bfloat16> {
     using T = float;
-    static __device__ __forceinline__ T dec_f(__hip_bfloat16 v, T w) { return __bfloat162float(v) * w; }
-    static __device__ __forceinline__ __hip_bfloat16 enc_f(T v, T w) { return __float2bfloat16(v / w); }
-    static __device__ __forceinline__ T dec_g(__hip_bfloat16 v, T w) { return __bfloat162float(v) * w; }
-    static __device__ __forceinline__ __hip_bfloat16 enc_g(T v, T w) { return __float2bfloat16(v / w); }
+    using Raw = unsigned short;
+    static __device__ __forceinline__ T dec(__hip_bfloat16 v, T w) { return __bfloat162float(v) * w; }
+    static __device__ __forceinline__ Raw enc(T v, T inv_w)
+    {
+        return __bfloat16_as_ushort(__float2bfloat16(v * inv_w));
+    }
 };
 
 // ---------------------------------------------------------- lattice tables
@@ -102,6 +109,8 @@ __device__ __forceinline__ constexpr double w19(int i)
 }
 // Eq. (31)
 __device__ __forceinline__ constexpr double w7(int i) { return i == 0 ? 0.25 : 0.125; }
+__device__ __forceinline__ constexpr double inv_w19(int i) { return i == 0 ? 3.0 : (i < 7 ? 18.0 : 36.0); }
+__device__ __forceinline__ constexpr double inv_w7(int i) { return i == 0 ? 4.0 : 8.0; }
 
 // ---------------------------------------------------------------- arguments
 template <typename T>
@@ -124,85 +133,125 @@ __device__ __forceinline__ T theta_linear(const Geometry<T> &geo, int y)
 __device__ __forceinline__ bool x_wall_dirichlet(int wall_type) { return wall_type != 1; }
 __device__ __forceinline__ bool z_wall_dirichlet(int wall_type) { return wall_type == 2; }
 
+// ----------------------------------------------------------------- access
+// Element offsets are 32-bit when a whole lattice spans less than 4 GiB: a
+// load is then a uniform 64-bit base plus a 32-bit per-lane byte offset
+// (one VALU add per population instead of 64-bit address arithmetic).
+// Larger lattices use 64-bit offsets.  Destination writes are non-temporal:
+// the written lattice is read back only in the next step, long after it has
+// left the caches.
+template <typename S, bool kOff32>
+struct Access {
+    using I = typename std::conditional<kOff32, uint32_t, size_t>::type;
+    using Raw = typename Codec<S>::Raw;
+    static __device__ __forceinline__ S ld(const S *base, I e)
+    {
+        if constexpr (kOff32) {
+            const uint32_t b = e * uint32_t(sizeof(S));
+            return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + b);
+        } else {
+            return base[e];
+        }
+    }
+    static __device__ __forceinline__ void st(S *base, I e, Raw v)
+    {
+        Raw *p;
+        if constexpr (kOff32) {
+            const uint32_t b = e * uint32_t(sizeof(S));
+            p = reinterpret_cast<Raw *>(reinterpret_cast<char *>(base) + b);
+        } else {
+            p = reinterpret_cast<Raw *>(base) + e;
+        }
+        __builtin_nontemporal_store(v, p);
+    }
+};
+
 // ------------------------------------------------------------------- pull
 // Gather the populations of node (x, y, z) at time t from the post-collision
 // lattice `src` (time t-1): streaming plus wall conditions.
-template <typename S>
+template <typename S, bool kOff32>
 __device__ __forceinline__ void pull(const S *__restrict__ src, const Geometry<typename Codec<S>::T> &geo,
                                      int x, int y, int z, typename Codec<S>::T f[19],
                                      typename Codec<S>::T g[7])
 {
     using T = typename Codec<S>::T;
     using C = Codec<S>;
+    using A = Access<S, kOff32>;
+    using I = typename A::I;
     const int n = geo.n;
-    const size_t P = geo.plane;
-    const int idx = x + n * (y + n * z);
+    const I P = I(geo.plane);
+    const I idx = I(x) + I(n) * (I(y) + I(n) * I(z));
     const bool xl = x == 0, xh = x == n - 1;
     const bool yl = y == 0, yh = y == n - 1;
     const bool zl = z == 0, zh = z == n - 1;
-    const int sy = n, sz = n * n;
+    const I sy = I(n), sz = I(n) * I(n);
 
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
         const int ex = ex19(i), ey = ey19(i), ez = ez19(i);
         const bool out = (ex > 0 && xl) || (ex < 0 && xh) || (ey > 0 && yl) || (ey < 0 && yh) ||
                          (ez > 0 && zl) || (ez < 0 && zh);
-        const int d = ex + ey * sy + ez * sz;
+        // upstream node x - e_i (unsigned wrap-around arithmetic is exact here)
+        const I up = idx - I(ex) - I(ey) * sy - I(ez) * sz;
         // Inside: f*_i(x - e_i).  Outside: f*_ibar(x) reflected at the wall.
-        const S v = out ? src[(size_t)opp19(i) * P + idx] : src[(size_t)i * P + (idx - d)];
-        f[i] = C::dec_f(v, T(w19(i)));
+        const I e = out ? I(opp19(i)) * P + idx : I(i) * P + up;
+        f[i] = C::dec(A::ld(src, e), T(w19(i)));
     }
 
-    const S *gs = src + 19 * P;
+    const I g0 = I(19) * P;
     const T two_w = T(0.25);  // 2 w_T,i for the moving directions
     const T th_lin = theta_linear(geo, y);
     const bool xd = x_wall_dirichlet(geo.wall_type);
     const bool zd = z_wall_dirichlet(geo.wall_type);
-    g[0] = C::dec_g(gs[idx], T(w7(0)));
+    const T wg = T(w7(1));
+    g[0] = C::dec(A::ld(src, g0 + idx), T(w7(0)));
     {   // +x from x-1 | wall x = 0
-        const T v = C::dec_g(xl ? gs[2 * P + idx] : gs[1 * P + idx - 1], T(w7(1)));
+        const T v = C::dec(A::ld(src, xl ? g0 + 2 * P + idx : g0 + P + idx - 1), wg);
         g[1] = xl ? (xd ? two_w * th_lin - v : v) : v;
     }
     {   // -x from x+1 | wall x = H
-        const T v = C::dec_g(xh ? gs[1 * P + idx] : gs[2 * P + idx + 1], T(w7(2)));
+        const T v = C::dec(A::ld(src, xh ? g0 + P + idx : g0 + 2 * P + idx + 1), wg);
         g[2] = xh ? (xd ? two_w * th_lin - v : v) : v;
     }
     {   // +y from y-1 | hot wall y = 0 (Eq. 6)
-        const T v = C::dec_g(yl ? gs[4 * P + idx] : gs[3 * P + idx - sy], T(w7(3)));
+        const T v = C::dec(A::ld(src, yl ? g0 + 4 * P + idx : g0 + 3 * P + idx - sy), wg);
         g[3] = yl ? two_w * geo.theta_hot - v : v;
     }
     {   // -y from y+1 | cold wall y = H (Eq. 7)
-        const T v = C::dec_g(yh ? gs[3 * P + idx] : gs[4 * P + idx + sy], T(w7(4)));
+        const T v = C::dec(A::ld(src, yh ? g0 + 3 * P + idx : g0 + 4 * P + idx + sy), wg);
         g[4] = yh ? two_w * geo.theta_cold - v : v;
     }
     {   // +z from z-1 | wall z = 0
-        const T v = C::dec_g(zl ? gs[6 * P + idx] : gs[5 * P + idx - sz], T(w7(5)));
+        const T v = C::dec(A::ld(src, zl ? g0 + 6 * P + idx : g0 + 5 * P + idx - sz), wg);
         g[5] = zl ? (zd ? two_w * th_lin - v : v) : v;
     }
     {   // -z from z+1 | wall z = H
-        const T v = C::dec_g(zh ? gs[5 * P + idx] : gs[6 * P + idx + sz], T(w7(6)));
+        const T v = C::dec(A::ld(src, zh ? g0 + 5 * P + idx : g0 + 6 * P + idx + sz), wg);
         g[6] = zh ? (zd ? two_w * th_lin - v : v) : v;
     }
 }
 
-template <typename S>
-__device__ __forceinline__ void put(S *__restrict__ dst, size_t P, int idx,
+template <typename S, bool kOff32>
+__device__ __forceinline__ void put(S *__restrict__ dst, size_t plane, size_t node,
                                     const typename Codec<S>::T f[19],
                                     const typename Codec<S>::T g[7])
 {
     using T = typename Codec<S>::T;
     using C = Codec<S>;
+    using A = Access<S, kOff32>;
+    using I = typename A::I;
+    const I P = I(plane), idx = I(node);
 #pragma unroll
     for (int i = 0; i < 19; ++i)
-        dst[(size_t)i * P + idx] = C::enc_f(f[i], T(w19(i)));
+        A::st(dst, I(i) * P + idx, C::enc(f[i], T(inv_w19(i))));
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        dst[(size_t)(19 + i) * P + idx] = C::enc_g(g[i], T(w7(i)));
+        A::st(dst, I(19 + i) * P + idx, C::enc(g[i], T(inv_w7(i))));
 }
 
 // -------------------------------------------------------------- step kernel
 // One thread per node; block (bx, by) over (x, y), grid.z = z.
-template <typename S>
+template <typename S, bool kOff32>
 __global__ __launch_bounds__(1024) void k_step(const S *__restrict__ src, S *__restrict__ dst,
                                                Geometry<typename Codec<S>::T> geo,
                                                Rates<typename Codec<S>::T> rates)
@@ -214,9 +263,9 @@ __global__ __launch_bounds__(1024) void k_step(const S *__restrict__ src, S *__r
     if (x >= geo.n || y >= geo.n)
         return;
     T f[19], g[7];
-    pull<S>(src, geo, x, y, z, f, g);
+    pull<S, kOff32>(src, geo, x, y, z, f, g);
     collide<T>(f, g, rates);
-    put<S>(dst, geo.plane, x + geo.n * (y + geo.n * z), f, g);
+    put<S, kOff32>(dst, geo.plane, size_t(x) + size_t(geo.n) * (size_t(y) + size_t(geo.n) * z), f, g);
 }
 
 // --------------------------------------------------------- state sources
@@ -296,7 +345,7 @@ struct SourceFields {
 // "Unstream": write the post-collision lattice P whose pull reproduces S.
 // For population i at node y: if y + e_i is inside, P_i(y) = S_i(y + e_i);
 // otherwise P_i(y) is the value that the wall turns into S_ibar(y).
-template <typename S, typename Src>
+template <typename S, bool kOff32, typename Src>
 __global__ __launch_bounds__(256) void k_unstream(S *__restrict__ dst,
                                                   Geometry<typename Codec<S>::T> geo, Src srcS)
 {
@@ -313,7 +362,7 @@ __global__ __launch_bounds__(256) void k_unstream(S *__restrict__ dst,
         const int tx = x + ex19(i), ty = y + ey19(i), tz = z + ez19(i);
         const bool in = tx >= 0 && tx < n && ty >= 0 && ty < n && tz >= 0 && tz < n;
         double v = in ? srcS.f(i, tx + n * (ty + n * tz)) : srcS.f(opp19(i), int(c));
-        dst[(size_t)i * P + c] = C::enc_f(T(v), T(w19(i)));
+        Access<S, kOff32>::st(dst, (size_t)i * P + c, C::enc(T(v), T(inv_w19(i))));
     }
     const double th_lin = geo.theta_hot + (geo.theta_cold - geo.theta_hot) * (y + 0.5) / n;
     const int gx[7] = {0, 1, -1, 0, 0, 0, 0}, gy[7] = {0, 0, 0, 1, -1, 0, 0},
@@ -334,13 +383,13 @@ __global__ __launch_bounds__(256) void k_unstream(S *__restrict__ dst,
             // S_ibar = -P_i + 2 w theta_W (Dirichlet) or P_i (adiabatic)
             v = dir ? 2.0 * w7(go[i]) * tw - s_in : s_in;
         }
-        dst[(size_t)(19 + i) * P + c] = C::enc_g(T(v), T(w7(i)));
+        Access<S, kOff32>::st(dst, (size_t)(19 + i) * P + c, C::enc(T(v), T(inv_w7(i))));
     }
 }
 
 // ------------------------------------------------------------ read kernels
 // Macroscopic fields at time t: rho, u = j / rho, theta (double outputs).
-template <typename S>
+template <typename S, bool kOff32>
 __global__ __launch_bounds__(256) void k_macro(const S *__restrict__ src,
                                                Geometry<typename Codec<S>::T> geo,
                                                double *rho, double *ux, double *uy, double *uz,
@@ -354,7 +403,7 @@ __global__ __launch_bounds__(256) void k_macro(const S *__restrict__ src,
         return;
     const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
     T f[19], g[7];
-    pull<S>(src, geo, x, y, z, f, g);
+    pull<S, kOff32>(src, geo, x, y, z, f, g);
     double dr = 0.0, j[3] = {0.0, 0.0, 0.0}, th = 0.0;
     for (int i = 0; i < 19; ++i) {
         dr += double(f[i]);
@@ -373,7 +422,7 @@ __global__ __launch_bounds__(256) void k_macro(const S *__restrict__ src,
 }
 
 // Populations at time t as plain doubles, population-major.
-template <typename S>
+template <typename S, bool kOff32>
 __global__ __launch_bounds__(256) void k_pops(const S *__restrict__ src,
                                               Geometry<typename Codec<S>::T> geo, double *fo,
                                               double *go)
@@ -386,7 +435,7 @@ __global__ __launch_bounds__(256) void k_pops(const S *__restrict__ src,
         return;
     const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
     T f[19], g[7];
-    pull<S>(src, geo, x, y, z, f, g);
+    pull<S, kOff32>(src, geo, x, y, z, f, g);
     if (fo)
         for (int i = 0; i < 19; ++i)
             fo[(size_t)i * cells + c] = w19(i) + double(f[i]);
@@ -415,7 +464,7 @@ __device__ __forceinline__ double wave_max(double v)
 // One block per z row of the hot wall (y = 0).  Local Nu (Eq. 39) from the
 // two wall-adjacent nodes, second order: dtheta/dy = (9 th0 - th1 - 8 th_w)/3.
 // partial[z] = {sum over x, X = 0.5 line contribution, max, non-finite count}.
-template <typename S>
+template <typename S, bool kOff32>
 __global__ __launch_bounds__(256) void k_nu_rows(const S *__restrict__ src,
                                                  Geometry<typename Codec<S>::T> geo,
                                                  double theta_hot, double *partial, double *map)
@@ -426,8 +475,8 @@ __global__ __launch_bounds__(256) void k_nu_rows(const S *__restrict__ src,
     double sum = 0.0, line = 0.0, mx = -1.0e300, bad = 0.0;
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
         T f[19], g0[7], g1[7];
-        pull<S>(src, geo, x, 0, z, f, g0);
-        pull<S>(src, geo, x, 1, z, f, g1);
+        pull<S, kOff32>(src, geo, x, 0, z, f, g0);
+        pull<S, kOff32>(src, geo, x, 1, z, f, g1);
         double th0 = 0.0, th1 = 0.0;
         for (int i = 0; i < 7; ++i) {
             th0 += double(g0[i]);

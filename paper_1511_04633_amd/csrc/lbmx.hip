@@ -183,6 +183,7 @@ struct lbmx_cavity {
     int cur;
     int64_t t;
     int bx, by;
+    bool off32;  // a lattice spans < 4 GiB: kernels use 32-bit byte offsets
 };
 
 namespace {
@@ -208,10 +209,11 @@ S *lattice(lbmx_cavity *h, int k)
 
 double *scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L.scratch_off); }
 
+// One row of up to 256 nodes along x per block row; up to 512 threads per block.
 void default_launch(int n, int *bx, int *by)
 {
     *bx = n < 256 ? n : 256;
-    int b = 256 / *bx;
+    int b = 512 / *bx;
     if (b < 1) b = 1;
     if (b > n) b = n;
     *by = b;
@@ -227,8 +229,12 @@ lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
     dim3 block(h->bx, h->by, 1);
     dim3 grid((n + h->bx - 1) / h->bx, (n + h->by - 1) / h->by, n);
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipLaunchKernelGGL(k_step<S>, grid, block, 0, h->stream, lattice<S>(h, h->cur),
-                           lattice<S>(h, 1 - h->cur), geo, rates);
+        if (h->off32)
+            hipLaunchKernelGGL((k_step<S, true>), grid, block, 0, h->stream, lattice<S>(h, h->cur),
+                               lattice<S>(h, 1 - h->cur), geo, rates);
+        else
+            hipLaunchKernelGGL((k_step<S, false>), grid, block, 0, h->stream, lattice<S>(h, h->cur),
+                               lattice<S>(h, 1 - h->cur), geo, rates);
         h->cur = 1 - h->cur;
         h->t += 1;
     }
@@ -242,8 +248,12 @@ lbmx_status launch_unstream(lbmx_cavity *h, const Src &src)
     const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
     const int threads = 256;
     const unsigned blocks = (unsigned)((cells + threads - 1) / threads);
-    hipLaunchKernelGGL((k_unstream<S, Src>), dim3(blocks), dim3(threads), 0, h->stream,
-                       lattice<S>(h, h->cur), geometry<S>(h), src);
+    if (h->off32)
+        hipLaunchKernelGGL((k_unstream<S, true, Src>), dim3(blocks), dim3(threads), 0, h->stream,
+                           lattice<S>(h, h->cur), geometry<S>(h), src);
+    else
+        hipLaunchKernelGGL((k_unstream<S, false, Src>), dim3(blocks), dim3(threads), 0, h->stream,
+                           lattice<S>(h, h->cur), geometry<S>(h), src);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -253,8 +263,12 @@ lbmx_status launch_macro(lbmx_cavity *h, double *r, double *u, double *v, double
 {
     const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
     const unsigned blocks = (unsigned)((cells + 255) / 256);
-    hipLaunchKernelGGL(k_macro<S>, dim3(blocks), dim3(256), 0, h->stream, lattice<S>(h, h->cur),
-                       geometry<S>(h), r, u, v, w, th);
+    if (h->off32)
+        hipLaunchKernelGGL((k_macro<S, true>), dim3(blocks), dim3(256), 0, h->stream,
+                           lattice<S>(h, h->cur), geometry<S>(h), r, u, v, w, th);
+    else
+        hipLaunchKernelGGL((k_macro<S, false>), dim3(blocks), dim3(256), 0, h->stream,
+                           lattice<S>(h, h->cur), geometry<S>(h), r, u, v, w, th);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -264,8 +278,12 @@ lbmx_status launch_pops(lbmx_cavity *h, double *f, double *g)
 {
     const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
     const unsigned blocks = (unsigned)((cells + 255) / 256);
-    hipLaunchKernelGGL(k_pops<S>, dim3(blocks), dim3(256), 0, h->stream, lattice<S>(h, h->cur),
-                       geometry<S>(h), f, g);
+    if (h->off32)
+        hipLaunchKernelGGL((k_pops<S, true>), dim3(blocks), dim3(256), 0, h->stream,
+                           lattice<S>(h, h->cur), geometry<S>(h), f, g);
+    else
+        hipLaunchKernelGGL((k_pops<S, false>), dim3(blocks), dim3(256), 0, h->stream,
+                           lattice<S>(h, h->cur), geometry<S>(h), f, g);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -277,8 +295,12 @@ lbmx_status launch_nu(lbmx_cavity *h, double *map)
     double *part = scratch(h);
     double *out = part + 4 * (size_t)n;
     const int threads = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
-    hipLaunchKernelGGL(k_nu_rows<S>, dim3(n), dim3(threads), 0, h->stream, lattice<S>(h, h->cur),
-                       geometry<S>(h), h->p.theta_hot, part, map);
+    if (h->off32)
+        hipLaunchKernelGGL((k_nu_rows<S, true>), dim3(n), dim3(threads), 0, h->stream,
+                           lattice<S>(h, h->cur), geometry<S>(h), h->p.theta_hot, part, map);
+    else
+        hipLaunchKernelGGL((k_nu_rows<S, false>), dim3(n), dim3(threads), 0, h->stream,
+                           lattice<S>(h, h->cur), geometry<S>(h), h->p.theta_hot, part, map);
     hipLaunchKernelGGL(k_nu_final, dim3(1), dim3(256), 0, h->stream, part, n, out);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
@@ -423,6 +445,7 @@ lbmx_status lbmx_create(const lbmx_params *p, void *dev_workspace, size_t ws_byt
     h->L = L;
     h->cur = 0;
     h->t = 0;
+    h->off32 = 26.0 * double(L.plane) * double(storage_size(p->storage)) <= 4294967295.0;
     default_launch(p->n, &h->bx, &h->by);
     if (stream) {
         h->stream = reinterpret_cast<hipStream_t>(stream);
