@@ -43,8 +43,22 @@ def cpu_baseline(seconds: float, n: int = 64, ra: float = 1e6, wall_type: int = 
             "sample": f"FP64 oracle, {n}^3 Type {wall_type} Ra {ra:g}, {steps} steps in {dt:.1f} s"}
 
 
-def bpc_of(storage):
-    return {"f64": 416, "f32": 208, "f16": 104, "bf16": 104}[storage]
+def counter_traffic(storage: str, n: int):
+    """HBM bytes per step launch measured by rocprofv3 counters (profiles/traffic.json),
+    or None when no measurement exists or the kernel sources changed since."""
+    from paper_1511_04633_amd import profiling
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as fh:
+            entry = json.load(fh).get(f"{storage}_{n}")
+    except (OSError, ValueError):
+        return None
+    if not entry or entry.get("source_sha256") != profiling.kernel_source_hash():
+        return None
+    return entry
+
+
 
 
 def copy_probe(nbytes: int, reps: int = 20) -> float:
@@ -77,7 +91,8 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--ra", type=float, default=1e6)
     ap.add_argument("--wall-type", type=int, default=1)
-    ap.add_argument("--storage", default="f32", choices=["f64", "f32", "f16", "bf16"])
+    ap.add_argument("--storage", default="f32",
+                    choices=["f64", "f32", "f16", "bf16", "f16_f32", "bf16_f32"])
     ap.add_argument("--launch", default="", help="bx,by override of the step kernel block")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -113,13 +128,17 @@ def main():
     wall = time.perf_counter() - t0
 
     nu = cav.nusselt()
-    copy_gbs = None if args.no_copy_probe else copy_probe(n * n * n * 26 * (bpc_of(args.storage) // 52))
+    copy_gbs = None if args.no_copy_probe else copy_probe(
+        int(n ** 3 * lbmx.bytes_per_cell(args.storage)) // 2)
     cells = n ** 3
     mlups = cells * args.steps / wall / 1e6
     bpc = lbmx.bytes_per_cell(args.storage)
     kernel_s = ev_ms / 1e3 / args.steps
     achieved = cells * bpc / kernel_s / 1e9
-    dtype = {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32"}
+    tr = counter_traffic(args.storage, n)
+    dtype = {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32",
+             "f16_f32": "f16-flow+f32-energy-storage/f32",
+             "bf16_f32": "bf16-flow+f32-energy-storage/f32"}
     line = {
         "metric": "double-MRT MLUPS + % HBM roofline at 256^3; wall time to steady Nu",
         "value": round(mlups, 1),
@@ -139,7 +158,9 @@ def main():
                    "launch": list(cav.get_launch())},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "bytes_per_cell": bpc,
+                     "traffic": None if tr is None else tr["traffic_bytes"],
+                     "traffic_over_algorithmic": None if tr is None else tr["traffic_over_algorithmic"],
+                     "algorithmic_bytes": cells * bpc, "bytes_per_cell": bpc,
                      "kernel_us": round(kernel_s * 1e6, 2),
                      "copy_achieved": None if copy_gbs is None else round(copy_gbs, 1)},
         "nu3d_after": nu["nu3d"],

@@ -48,10 +48,19 @@ typedef enum {
 } lbmx_status;
 
 /* Population storage in HBM.  Collision arithmetic is FP64 for LBMX_F64 and
- * FP32 otherwise.  D3Q19 populations are stored as offsets f_i - w_i from the
- * lattice weights; LBMX_F16 / LBMX_BF16 store 16-bit offsets scaled by 1/w_i
- * (flow) and 1/w_T,i (energy). */
-typedef enum { LBMX_F64 = 0, LBMX_F32 = 1, LBMX_F16 = 2, LBMX_BF16 = 3 } lbmx_storage;
+ * FP32 otherwise.  D3Q19 (flow) populations are stored as offsets f_i - w_i
+ * from the lattice weights (Eq. 18), D3Q7 (energy) populations as g_i; in a
+ * 16-bit format a population is stored divided by its weight (1/w_i, 1/w_T,i).
+ * The mixed formats keep the flow lattice in 16 bits and the energy lattice
+ * in FP32.  Bytes moved per node update: 416, 208, 104, 104, 132, 132. */
+typedef enum {
+    LBMX_F64 = 0,       /* flow FP64, energy FP64                      */
+    LBMX_F32 = 1,       /* flow FP32, energy FP32                      */
+    LBMX_F16 = 2,       /* flow FP16, energy FP16                      */
+    LBMX_BF16 = 3,      /* flow BF16, energy BF16                      */
+    LBMX_F16_F32 = 4,   /* flow FP16, energy FP32                      */
+    LBMX_BF16_F32 = 5   /* flow BF16, energy FP32                      */
+} lbmx_storage;
 
 typedef struct {
     int32_t n;              /* cells per edge, H = n; 4 <= n <= 1024              */
@@ -93,7 +102,7 @@ lbmx_status lbmx_derive(const lbmx_params *p, double *out);
 lbmx_status lbmx_workspace_bytes(const lbmx_params *p, size_t *bytes);
 
 /* Algorithmic HBM bytes moved by one cell update of lbmx_step:
- * 26 populations read once and written once at the storage width. */
+ * 26 populations read once and written once at their storage widths. */
 lbmx_status lbmx_bytes_per_cell(int32_t storage, double *bytes);
 
 /* Create a cavity.  dev_workspace: device memory of at least

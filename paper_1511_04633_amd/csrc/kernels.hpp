@@ -1,9 +1,10 @@
 // kernels.hpp -- HIP kernels of the double-MRT cavity step for gfx950.
 //
-// Data layout in HBM: two lattices (ping-pong), each 26 population planes
-// (19 D3Q19 then 7 D3Q7) of `plane` elements; inside a plane the node
-// (x, y, z) sits at x + n*(y + n*z), x fastest, so a wavefront reads and
-// writes 64 consecutive nodes of one row per population.
+// Data layout in HBM: two lattices (ping-pong).  A lattice is 19 D3Q19
+// population planes of the flow element type followed by 7 D3Q7 planes of
+// the energy element type, each plane `plane` elements long; inside a plane
+// the node (x, y, z) sits at x + n*(y + n*z), x fastest, so a wavefront
+// reads and writes 64 consecutive nodes of one row per population.
 //
 // What a lattice holds: the post-collision populations f*(t-1), g*(t-1).
 // The step kernel gathers ("pulls") them from the upstream neighbours, which
@@ -32,52 +33,64 @@
 namespace lbmx {
 
 // ------------------------------------------------------------------ storage
-// Codec<S>: how a population is held in HBM.  T is the compute type.
-// Flow populations are stored as offsets df = f - w_i; 16-bit formats store
-// df / w_i and g / w_T,i (the ratio a population has to its weight), which
-// keeps the stored magnitudes O(u) and O(theta) for every direction.
+// Codec<S>: how one population is held in HBM.  Flow populations are stored
+// as offsets df = f - w_i, energy populations as g; the 16-bit formats store
+// df / w_i and g / w_T,i (the population relative to its weight), which keeps
+// every direction's stored value O(u) or O(theta).  `Raw` is the bit
+// container for non-temporal stores; `inv_w` is the exact reciprocal of the
+// weight (3, 18, 36; 4, 8), so encoding multiplies instead of dividing.
 template <typename S>
 struct Codec;
 
-// `Raw` is the bit container written with non-temporal stores; `inv_w` is
-// the exact reciprocal of the lattice weight (3, 18, 36 for D3Q19; 4, 8 for
-// D3Q7) so encoding is a multiply, not a division.
 template <>
 struct Codec<double> {
-    using T = double;
     using Raw = double;
-    static __device__ __forceinline__ T dec(double v, T) { return v; }
-    static __device__ __forceinline__ Raw enc(T v, T) { return v; }
+    template <typename T> static __device__ __forceinline__ T dec(double v, T) { return T(v); }
+    template <typename T> static __device__ __forceinline__ Raw enc(T v, T) { return double(v); }
 };
 
 template <>
 struct Codec<float> {
-    using T = float;
     using Raw = float;
-    static __device__ __forceinline__ T dec(float v, T) { return v; }
-    static __device__ __forceinline__ Raw enc(T v, T) { return v; }
+    template <typename T> static __device__ __forceinline__ T dec(float v, T) { return T(v); }
+    template <typename T> static __device__ __forceinline__ Raw enc(T v, T) { return float(v); }
 };
 
 template <>
 struct Codec<__half> {
-    using T = float;
     using Raw = unsigned short;
-    static __device__ __forceinline__ T dec(__half v, T w) { return __half2float(v) * w; }
-    static __device__ __forceinline__ Raw enc(T v, T inv_w)
+    template <typename T> static __device__ __forceinline__ T dec(__half v, T w)
     {
-        return __half_as_ushort(__float2half_rn(v * inv_w));
+        return T(__half2float(v)) * w;
+    }
+    template <typename T> static __device__ __forceinline__ Raw enc(T v, T inv_w)
+    {
+        return __half_as_ushort(__float2half_rn(float(v * inv_w)));
     }
 };
 
 template <>
 struct Codec<__hip_bfloat16> {
-    using T = float;
     using Raw = unsigned short;
-    static __device__ __forceinline__ T dec(__hip_bfloat16 v, T w) { return __bfloat162float(v) * w; }
-    static __device__ __forceinline__ Raw enc(T v, T inv_w)
+    template <typename T> static __device__ __forceinline__ T dec(__hip_bfloat16 v, T w)
     {
-        return __bfloat16_as_ushort(__float2bfloat16(v * inv_w));
+        return T(__bfloat162float(v)) * w;
     }
+    template <typename T> static __device__ __forceinline__ Raw enc(T v, T inv_w)
+    {
+        return __bfloat16_as_ushort(__float2bfloat16(float(v * inv_w)));
+    }
+};
+
+// Element types of the flow (SF) and energy (SG) planes; T is the
+// arithmetic type of the collision (FP64 only when both are FP64).
+template <typename SF, typename SG>
+struct Store {
+    using F = SF;
+    using G = SG;
+    using T = typename std::conditional<std::is_same<SF, double>::value &&
+                                            std::is_same<SG, double>::value,
+                                        double, float>::type;
 };
 
 // ---------------------------------------------------------- lattice tables
@@ -102,12 +115,11 @@ __device__ __forceinline__ constexpr int opp19(int i)
     constexpr int v[19] = {0, 2, 1, 4, 3, 6, 5, 10, 9, 8, 7, 14, 13, 12, 11, 18, 17, 16, 15};
     return v[i];
 }
-// Eq. (18)
+// Eq. (18) and Eq. (31), with exact reciprocals.
 __device__ __forceinline__ constexpr double w19(int i)
 {
     return i == 0 ? 1.0 / 3.0 : (i < 7 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
-// Eq. (31)
 __device__ __forceinline__ constexpr double w7(int i) { return i == 0 ? 0.25 : 0.125; }
 __device__ __forceinline__ constexpr double inv_w19(int i) { return i == 0 ? 3.0 : (i < 7 ? 18.0 : 36.0); }
 __device__ __forceinline__ constexpr double inv_w7(int i) { return i == 0 ? 4.0 : 8.0; }
@@ -134,49 +146,38 @@ __device__ __forceinline__ bool x_wall_dirichlet(int wall_type) { return wall_ty
 __device__ __forceinline__ bool z_wall_dirichlet(int wall_type) { return wall_type == 2; }
 
 // ----------------------------------------------------------------- access
-// Element offsets are 32-bit when a whole lattice spans less than 4 GiB: a
-// load is then a uniform 64-bit base plus a 32-bit per-lane byte offset
-// (one VALU add per population instead of 64-bit address arithmetic).
-// Larger lattices use 64-bit offsets.  Destination writes are non-temporal:
-// the written lattice is read back only in the next step, long after it has
-// left the caches.
-template <typename S, bool kOff32>
+// Byte offsets are 32-bit when a whole lattice spans less than 4 GiB: a load
+// is then a uniform 64-bit base plus a 32-bit per-lane offset (one VALU add
+// per population instead of 64-bit address arithmetic); larger lattices use
+// 64-bit offsets.  Stores are non-temporal: the written lattice is read back
+// only in the next step, long after it has left the caches.
+template <bool kOff32>
 struct Access {
     using I = typename std::conditional<kOff32, uint32_t, size_t>::type;
-    using Raw = typename Codec<S>::Raw;
-    static __device__ __forceinline__ S ld(const S *base, I e)
+    template <typename S>
+    static __device__ __forceinline__ S ld(const char *base, I byte)
     {
-        if constexpr (kOff32) {
-            const uint32_t b = e * uint32_t(sizeof(S));
-            return *reinterpret_cast<const S *>(reinterpret_cast<const char *>(base) + b);
-        } else {
-            return base[e];
-        }
+        return *reinterpret_cast<const S *>(base + byte);
     }
-    static __device__ __forceinline__ void st(S *base, I e, Raw v)
+    template <typename S>
+    static __device__ __forceinline__ void st(char *base, I byte, typename Codec<S>::Raw v)
     {
-        Raw *p;
-        if constexpr (kOff32) {
-            const uint32_t b = e * uint32_t(sizeof(S));
-            p = reinterpret_cast<Raw *>(reinterpret_cast<char *>(base) + b);
-        } else {
-            p = reinterpret_cast<Raw *>(base) + e;
-        }
-        __builtin_nontemporal_store(v, p);
+        __builtin_nontemporal_store(v, reinterpret_cast<typename Codec<S>::Raw *>(base + byte));
     }
 };
 
 // ------------------------------------------------------------------- pull
 // Gather the populations of node (x, y, z) at time t from the post-collision
 // lattice `src` (time t-1): streaming plus wall conditions.
-template <typename S, bool kOff32>
-__device__ __forceinline__ void pull(const S *__restrict__ src, const Geometry<typename Codec<S>::T> &geo,
-                                     int x, int y, int z, typename Codec<S>::T f[19],
-                                     typename Codec<S>::T g[7])
+template <class St, bool kOff32>
+__device__ __forceinline__ void pull(const char *__restrict__ src,
+                                     const Geometry<typename St::T> &geo, int x, int y, int z,
+                                     typename St::T f[19], typename St::T g[7])
 {
-    using T = typename Codec<S>::T;
-    using C = Codec<S>;
-    using A = Access<S, kOff32>;
+    using T = typename St::T;
+    using SF = typename St::F;
+    using SG = typename St::G;
+    using A = Access<kOff32>;
     using I = typename A::I;
     const int n = geo.n;
     const I P = I(geo.plane);
@@ -185,6 +186,7 @@ __device__ __forceinline__ void pull(const S *__restrict__ src, const Geometry<t
     const bool yl = y == 0, yh = y == n - 1;
     const bool zl = z == 0, zh = z == n - 1;
     const I sy = I(n), sz = I(n) * I(n);
+    constexpr I bF = I(sizeof(SF)), bG = I(sizeof(SG));
 
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
@@ -195,77 +197,81 @@ __device__ __forceinline__ void pull(const S *__restrict__ src, const Geometry<t
         const I up = idx - I(ex) - I(ey) * sy - I(ez) * sz;
         // Inside: f*_i(x - e_i).  Outside: f*_ibar(x) reflected at the wall.
         const I e = out ? I(opp19(i)) * P + idx : I(i) * P + up;
-        f[i] = C::dec(A::ld(src, e), T(w19(i)));
+        f[i] = Codec<SF>::dec(A::template ld<SF>(src, e * bF), T(w19(i)));
     }
 
-    const I g0 = I(19) * P;
+    const char *gs = src + size_t(19) * geo.plane * sizeof(SF);
     const T two_w = T(0.25);  // 2 w_T,i for the moving directions
     const T th_lin = theta_linear(geo, y);
     const bool xd = x_wall_dirichlet(geo.wall_type);
     const bool zd = z_wall_dirichlet(geo.wall_type);
     const T wg = T(w7(1));
-    g[0] = C::dec(A::ld(src, g0 + idx), T(w7(0)));
+    auto ldg = [&](I e) { return Codec<SG>::dec(A::template ld<SG>(gs, e * bG), wg); };
+    g[0] = Codec<SG>::dec(A::template ld<SG>(gs, idx * bG), T(w7(0)));
     {   // +x from x-1 | wall x = 0
-        const T v = C::dec(A::ld(src, xl ? g0 + 2 * P + idx : g0 + P + idx - 1), wg);
+        const T v = ldg(xl ? 2 * P + idx : P + idx - 1);
         g[1] = xl ? (xd ? two_w * th_lin - v : v) : v;
     }
     {   // -x from x+1 | wall x = H
-        const T v = C::dec(A::ld(src, xh ? g0 + P + idx : g0 + 2 * P + idx + 1), wg);
+        const T v = ldg(xh ? P + idx : 2 * P + idx + 1);
         g[2] = xh ? (xd ? two_w * th_lin - v : v) : v;
     }
     {   // +y from y-1 | hot wall y = 0 (Eq. 6)
-        const T v = C::dec(A::ld(src, yl ? g0 + 4 * P + idx : g0 + 3 * P + idx - sy), wg);
+        const T v = ldg(yl ? 4 * P + idx : 3 * P + idx - sy);
         g[3] = yl ? two_w * geo.theta_hot - v : v;
     }
     {   // -y from y+1 | cold wall y = H (Eq. 7)
-        const T v = C::dec(A::ld(src, yh ? g0 + 3 * P + idx : g0 + 4 * P + idx + sy), wg);
+        const T v = ldg(yh ? 3 * P + idx : 4 * P + idx + sy);
         g[4] = yh ? two_w * geo.theta_cold - v : v;
     }
     {   // +z from z-1 | wall z = 0
-        const T v = C::dec(A::ld(src, zl ? g0 + 6 * P + idx : g0 + 5 * P + idx - sz), wg);
+        const T v = ldg(zl ? 6 * P + idx : 5 * P + idx - sz);
         g[5] = zl ? (zd ? two_w * th_lin - v : v) : v;
     }
     {   // -z from z+1 | wall z = H
-        const T v = C::dec(A::ld(src, zh ? g0 + 5 * P + idx : g0 + 6 * P + idx + sz), wg);
+        const T v = ldg(zh ? 5 * P + idx : 6 * P + idx + sz);
         g[6] = zh ? (zd ? two_w * th_lin - v : v) : v;
     }
 }
 
-template <typename S, bool kOff32>
-__device__ __forceinline__ void put(S *__restrict__ dst, size_t plane, size_t node,
-                                    const typename Codec<S>::T f[19],
-                                    const typename Codec<S>::T g[7])
+// Write one node's 26 populations at element index `node` of every plane.
+template <class St, bool kOff32>
+__device__ __forceinline__ void put(char *__restrict__ dst, size_t plane, size_t node,
+                                    const typename St::T f[19], const typename St::T g[7])
 {
-    using T = typename Codec<S>::T;
-    using C = Codec<S>;
-    using A = Access<S, kOff32>;
+    using T = typename St::T;
+    using SF = typename St::F;
+    using SG = typename St::G;
+    using A = Access<kOff32>;
     using I = typename A::I;
     const I P = I(plane), idx = I(node);
+    constexpr I bF = I(sizeof(SF)), bG = I(sizeof(SG));
 #pragma unroll
     for (int i = 0; i < 19; ++i)
-        A::st(dst, I(i) * P + idx, C::enc(f[i], T(inv_w19(i))));
+        A::template st<SF>(dst, (I(i) * P + idx) * bF, Codec<SF>::enc(f[i], T(inv_w19(i))));
+    char *gd = dst + size_t(19) * plane * sizeof(SF);
 #pragma unroll
     for (int i = 0; i < 7; ++i)
-        A::st(dst, I(19 + i) * P + idx, C::enc(g[i], T(inv_w7(i))));
+        A::template st<SG>(gd, (I(i) * P + idx) * bG, Codec<SG>::enc(g[i], T(inv_w7(i))));
 }
 
 // -------------------------------------------------------------- step kernel
 // One thread per node; block (bx, by) over (x, y), grid.z = z.
-template <typename S, bool kOff32>
-__global__ __launch_bounds__(1024) void k_step(const S *__restrict__ src, S *__restrict__ dst,
-                                               Geometry<typename Codec<S>::T> geo,
-                                               Rates<typename Codec<S>::T> rates)
+template <class St, bool kOff32>
+__global__ __launch_bounds__(1024) void k_step(const char *__restrict__ src, char *__restrict__ dst,
+                                               Geometry<typename St::T> geo,
+                                               Rates<typename St::T> rates)
 {
-    using T = typename Codec<S>::T;
+    using T = typename St::T;
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y * blockDim.y + threadIdx.y;
     const int z = blockIdx.z;
     if (x >= geo.n || y >= geo.n)
         return;
     T f[19], g[7];
-    pull<S, kOff32>(src, geo, x, y, z, f, g);
+    pull<St, kOff32>(src, geo, x, y, z, f, g);
     collide<T>(f, g, rates);
-    put<S, kOff32>(dst, geo.plane, size_t(x) + size_t(geo.n) * (size_t(y) + size_t(geo.n) * z), f, g);
+    put<St, kOff32>(dst, geo.plane, size_t(x) + size_t(geo.n) * (size_t(y) + size_t(geo.n) * z), f, g);
 }
 
 // --------------------------------------------------------- state sources
@@ -345,26 +351,32 @@ struct SourceFields {
 // "Unstream": write the post-collision lattice P whose pull reproduces S.
 // For population i at node y: if y + e_i is inside, P_i(y) = S_i(y + e_i);
 // otherwise P_i(y) is the value that the wall turns into S_ibar(y).
-template <typename S, bool kOff32, typename Src>
-__global__ __launch_bounds__(256) void k_unstream(S *__restrict__ dst,
-                                                  Geometry<typename Codec<S>::T> geo, Src srcS)
+template <class St, bool kOff32, typename Src>
+__global__ __launch_bounds__(256) void k_unstream(char *__restrict__ dst,
+                                                  Geometry<typename St::T> geo, Src srcS)
 {
-    using T = typename Codec<S>::T;
-    using C = Codec<S>;
+    using T = typename St::T;
+    using SF = typename St::F;
+    using SG = typename St::G;
+    using A = Access<kOff32>;
+    using I = typename A::I;
     const int n = geo.n;
     const long long cells = (long long)n * n * n;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= cells)
         return;
     const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
-    const size_t P = geo.plane;
+    const I P = I(geo.plane);
     for (int i = 0; i < 19; ++i) {
         const int tx = x + ex19(i), ty = y + ey19(i), tz = z + ez19(i);
         const bool in = tx >= 0 && tx < n && ty >= 0 && ty < n && tz >= 0 && tz < n;
         double v = in ? srcS.f(i, tx + n * (ty + n * tz)) : srcS.f(opp19(i), int(c));
-        Access<S, kOff32>::st(dst, (size_t)i * P + c, C::enc(T(v), T(inv_w19(i))));
+        A::template st<SF>(dst, (I(i) * P + I(c)) * I(sizeof(SF)),
+                           Codec<SF>::enc(T(v), T(inv_w19(i))));
     }
-    const double th_lin = geo.theta_hot + (geo.theta_cold - geo.theta_hot) * (y + 0.5) / n;
+    char *gd = dst + size_t(19) * geo.plane * sizeof(SF);
+    const double th_lin = double(geo.theta_hot) +
+                          double(geo.theta_cold - geo.theta_hot) * (y + 0.5) / n;
     const int gx[7] = {0, 1, -1, 0, 0, 0, 0}, gy[7] = {0, 0, 0, 1, -1, 0, 0},
               gz[7] = {0, 0, 0, 0, 0, 1, -1}, go[7] = {0, 2, 1, 4, 3, 6, 5};
     for (int i = 0; i < 7; ++i) {
@@ -376,26 +388,26 @@ __global__ __launch_bounds__(256) void k_unstream(S *__restrict__ dst,
             const double s_in = srcS.g(go[i], int(c));
             bool dir;
             double tw = 0.0;
-            if (ty < 0) { dir = true; tw = geo.theta_hot; }
-            else if (ty >= n) { dir = true; tw = geo.theta_cold; }
+            if (ty < 0) { dir = true; tw = double(geo.theta_hot); }
+            else if (ty >= n) { dir = true; tw = double(geo.theta_cold); }
             else if (tx < 0 || tx >= n) { dir = x_wall_dirichlet(geo.wall_type); tw = th_lin; }
             else { dir = z_wall_dirichlet(geo.wall_type); tw = th_lin; }
             // S_ibar = -P_i + 2 w theta_W (Dirichlet) or P_i (adiabatic)
             v = dir ? 2.0 * w7(go[i]) * tw - s_in : s_in;
         }
-        Access<S, kOff32>::st(dst, (size_t)(19 + i) * P + c, C::enc(T(v), T(inv_w7(i))));
+        A::template st<SG>(gd, (I(i) * P + I(c)) * I(sizeof(SG)),
+                           Codec<SG>::enc(T(v), T(inv_w7(i))));
     }
 }
 
 // ------------------------------------------------------------ read kernels
 // Macroscopic fields at time t: rho, u = j / rho, theta (double outputs).
-template <typename S, bool kOff32>
-__global__ __launch_bounds__(256) void k_macro(const S *__restrict__ src,
-                                               Geometry<typename Codec<S>::T> geo,
-                                               double *rho, double *ux, double *uy, double *uz,
-                                               double *theta)
+template <class St, bool kOff32>
+__global__ __launch_bounds__(256) void k_macro(const char *__restrict__ src,
+                                               Geometry<typename St::T> geo, double *rho,
+                                               double *ux, double *uy, double *uz, double *theta)
 {
-    using T = typename Codec<S>::T;
+    using T = typename St::T;
     const int n = geo.n;
     const long long cells = (long long)n * n * n;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -403,7 +415,7 @@ __global__ __launch_bounds__(256) void k_macro(const S *__restrict__ src,
         return;
     const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
     T f[19], g[7];
-    pull<S, kOff32>(src, geo, x, y, z, f, g);
+    pull<St, kOff32>(src, geo, x, y, z, f, g);
     double dr = 0.0, j[3] = {0.0, 0.0, 0.0}, th = 0.0;
     for (int i = 0; i < 19; ++i) {
         dr += double(f[i]);
@@ -422,12 +434,11 @@ __global__ __launch_bounds__(256) void k_macro(const S *__restrict__ src,
 }
 
 // Populations at time t as plain doubles, population-major.
-template <typename S, bool kOff32>
-__global__ __launch_bounds__(256) void k_pops(const S *__restrict__ src,
-                                              Geometry<typename Codec<S>::T> geo, double *fo,
-                                              double *go)
+template <class St, bool kOff32>
+__global__ __launch_bounds__(256) void k_pops(const char *__restrict__ src,
+                                              Geometry<typename St::T> geo, double *fo, double *go)
 {
-    using T = typename Codec<S>::T;
+    using T = typename St::T;
     const int n = geo.n;
     const long long cells = (long long)n * n * n;
     const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -435,7 +446,7 @@ __global__ __launch_bounds__(256) void k_pops(const S *__restrict__ src,
         return;
     const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
     T f[19], g[7];
-    pull<S, kOff32>(src, geo, x, y, z, f, g);
+    pull<St, kOff32>(src, geo, x, y, z, f, g);
     if (fo)
         for (int i = 0; i < 19; ++i)
             fo[(size_t)i * cells + c] = w19(i) + double(f[i]);
@@ -461,22 +472,56 @@ __device__ __forceinline__ double wave_max(double v)
     return v;
 }
 
+// Combine 4 per-lane accumulators (sum, line, max, bad) across the block:
+// wavefront shuffles, then the first lane of each wave through LDS.  The
+// block-wide result is valid in thread 0.
+__device__ __forceinline__ void block_reduce4(double &sum, double &line, double &mx, double &bad)
+{
+    __shared__ double red[4][16];
+    sum = wave_sum(sum);
+    line = wave_sum(line);
+    mx = wave_max(mx);
+    bad = wave_sum(bad);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    if (lane == 0) {
+        red[0][wv] = sum;
+        red[1][wv] = line;
+        red[2][wv] = mx;
+        red[3][wv] = bad;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double s = 0.0, l = 0.0, m = -1.0e300, b = 0.0;
+        for (int k = 0; k < nw; ++k) {
+            s += red[0][k];
+            l += red[1][k];
+            m = fmax(m, red[2][k]);
+            b += red[3][k];
+        }
+        sum = s;
+        line = l;
+        mx = m;
+        bad = b;
+    }
+}
+
 // One block per z row of the hot wall (y = 0).  Local Nu (Eq. 39) from the
 // two wall-adjacent nodes, second order: dtheta/dy = (9 th0 - th1 - 8 th_w)/3.
 // partial[z] = {sum over x, X = 0.5 line contribution, max, non-finite count}.
-template <typename S, bool kOff32>
-__global__ __launch_bounds__(256) void k_nu_rows(const S *__restrict__ src,
-                                                 Geometry<typename Codec<S>::T> geo,
-                                                 double theta_hot, double *partial, double *map)
+template <class St, bool kOff32>
+__global__ __launch_bounds__(256) void k_nu_rows(const char *__restrict__ src,
+                                                 Geometry<typename St::T> geo, double theta_hot,
+                                                 double *partial, double *map)
 {
-    using T = typename Codec<S>::T;
+    using T = typename St::T;
     const int n = geo.n;
     const int z = blockIdx.x;
     double sum = 0.0, line = 0.0, mx = -1.0e300, bad = 0.0;
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
         T f[19], g0[7], g1[7];
-        pull<S, kOff32>(src, geo, x, 0, z, f, g0);
-        pull<S, kOff32>(src, geo, x, 1, z, f, g1);
+        pull<St, kOff32>(src, geo, x, 0, z, f, g0);
+        pull<St, kOff32>(src, geo, x, 1, z, f, g1);
         double th0 = 0.0, th1 = 0.0;
         for (int i = 0; i < 7; ++i) {
             th0 += double(g0[i]);
@@ -497,32 +542,12 @@ __global__ __launch_bounds__(256) void k_nu_rows(const S *__restrict__ src,
             line += 0.5 * nu;
         }
     }
-    __shared__ double red[4][16];
-    sum = wave_sum(sum);
-    line = wave_sum(line);
-    mx = wave_max(mx);
-    bad = wave_sum(bad);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][wv] = sum;
-        red[1][wv] = line;
-        red[2][wv] = mx;
-        red[3][wv] = bad;
-    }
-    __syncthreads();
+    block_reduce4(sum, line, mx, bad);
     if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        double s = 0.0, l = 0.0, m = -1.0e300, b = 0.0;
-        for (int k = 0; k < nw; ++k) {
-            s += red[0][k];
-            l += red[1][k];
-            m = fmax(m, red[2][k]);
-            b += red[3][k];
-        }
-        partial[4 * z + 0] = s;
-        partial[4 * z + 1] = l;
-        partial[4 * z + 2] = m;
-        partial[4 * z + 3] = b;
+        partial[4 * z + 0] = sum;
+        partial[4 * z + 1] = line;
+        partial[4 * z + 2] = mx;
+        partial[4 * z + 3] = bad;
     }
 }
 
@@ -536,32 +561,12 @@ __global__ __launch_bounds__(256) void k_nu_final(const double *partial, int n, 
         mx = fmax(mx, partial[4 * z + 2]);
         bad += partial[4 * z + 3];
     }
-    __shared__ double red[4][16];
-    sum = wave_sum(sum);
-    line = wave_sum(line);
-    mx = wave_max(mx);
-    bad = wave_sum(bad);
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    if (lane == 0) {
-        red[0][wv] = sum;
-        red[1][wv] = line;
-        red[2][wv] = mx;
-        red[3][wv] = bad;
-    }
-    __syncthreads();
+    block_reduce4(sum, line, mx, bad);
     if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        double s = 0.0, l = 0.0, m = -1.0e300, b = 0.0;
-        for (int k = 0; k < nw; ++k) {
-            s += red[0][k];
-            l += red[1][k];
-            m = fmax(m, red[2][k]);
-            b += red[3][k];
-        }
-        out[0] = s / (double(n) * double(n));  // Eq. (40), midpoint rule
-        out[1] = l / double(n);                // Eq. (41), midpoint rule
-        out[2] = m;
-        out[3] = b;
+        out[0] = sum / (double(n) * double(n));  // Eq. (40), midpoint rule
+        out[1] = line / double(n);               // Eq. (41), midpoint rule
+        out[2] = mx;
+        out[3] = bad;
     }
 }
 

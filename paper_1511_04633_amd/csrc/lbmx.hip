@@ -43,11 +43,26 @@ lbmx_status fail(lbmx_status s, const char *fmt, ...)
             return fail(LBMX_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-size_t storage_size(int32_t s)
+// Element bytes of the flow (D3Q19) and energy (D3Q7) planes.
+size_t flow_size(int32_t s)
 {
     switch (s) {
     case LBMX_F64: return 8;
     case LBMX_F32: return 4;
+    case LBMX_F16:
+    case LBMX_BF16:
+    case LBMX_F16_F32:
+    case LBMX_BF16_F32: return 2;
+    default: return 0;
+    }
+}
+size_t energy_size(int32_t s)
+{
+    switch (s) {
+    case LBMX_F64: return 8;
+    case LBMX_F32:
+    case LBMX_F16_F32:
+    case LBMX_BF16_F32: return 4;
     case LBMX_F16:
     case LBMX_BF16: return 2;
     default: return 0;
@@ -81,7 +96,7 @@ lbmx_status derive(const lbmx_params *p, Derived *d)
     if (!std::isfinite(p->theta_hot) || !std::isfinite(p->theta_cold) ||
         !std::isfinite(p->theta_ref) || !std::isfinite(p->buoyancy_scale))
         return fail(LBMX_EINVAL, "non-finite temperature or buoyancy parameter");
-    if (storage_size(p->storage) == 0)
+    if (flow_size(p->storage) == 0)
         return fail(LBMX_EINVAL, "storage = %d not a lbmx_storage", p->storage);
     const double u_c = p->ma * std::sqrt(1.0 / 3.0);
     d->u_c = u_c;
@@ -164,7 +179,7 @@ Layout layout_of(const lbmx_params *p)
     Layout L;
     const size_t cells = (size_t)p->n * p->n * p->n;
     L.plane = align_up(cells, 128);
-    L.lattice = align_up(26 * L.plane * storage_size(p->storage), 256);
+    L.lattice = align_up(L.plane * (19 * flow_size(p->storage) + 7 * energy_size(p->storage)), 256);
     L.scratch_off = 2 * L.lattice;
     L.total = L.scratch_off + align_up(sizeof(double) * (4 * (size_t)p->n + 8), 256);
     return L;
@@ -188,10 +203,10 @@ struct lbmx_cavity {
 
 namespace {
 
-template <typename S>
-Geometry<typename Codec<S>::T> geometry(const lbmx_cavity *h)
+template <class St>
+Geometry<typename St::T> geometry(const lbmx_cavity *h)
 {
-    using T = typename Codec<S>::T;
+    using T = typename St::T;
     Geometry<T> g;
     g.n = h->p.n;
     g.wall_type = h->p.wall_type;
@@ -201,11 +216,7 @@ Geometry<typename Codec<S>::T> geometry(const lbmx_cavity *h)
     return g;
 }
 
-template <typename S>
-S *lattice(lbmx_cavity *h, int k)
-{
-    return reinterpret_cast<S *>(h->ws + (size_t)k * h->L.lattice);
-}
+char *lattice(lbmx_cavity *h, int k) { return h->ws + (size_t)k * h->L.lattice; }
 
 double *scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L.scratch_off); }
 
@@ -219,10 +230,10 @@ void default_launch(int n, int *bx, int *by)
     *by = b;
 }
 
-template <typename S>
+template <class S>
 lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
 {
-    using T = typename Codec<S>::T;
+    using T = typename S::T;
     const Geometry<T> geo = geometry<S>(h);
     const Rates<T> rates = make_rates<T>(&h->p, h->d);
     const int n = h->p.n;
@@ -230,11 +241,11 @@ lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
     dim3 grid((n + h->bx - 1) / h->bx, (n + h->by - 1) / h->by, n);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (h->off32)
-            hipLaunchKernelGGL((k_step<S, true>), grid, block, 0, h->stream, lattice<S>(h, h->cur),
-                               lattice<S>(h, 1 - h->cur), geo, rates);
+            hipLaunchKernelGGL((k_step<S, true>), grid, block, 0, h->stream, lattice(h, h->cur),
+                               lattice(h, 1 - h->cur), geo, rates);
         else
-            hipLaunchKernelGGL((k_step<S, false>), grid, block, 0, h->stream, lattice<S>(h, h->cur),
-                               lattice<S>(h, 1 - h->cur), geo, rates);
+            hipLaunchKernelGGL((k_step<S, false>), grid, block, 0, h->stream, lattice(h, h->cur),
+                               lattice(h, 1 - h->cur), geo, rates);
         h->cur = 1 - h->cur;
         h->t += 1;
     }
@@ -250,10 +261,10 @@ lbmx_status launch_unstream(lbmx_cavity *h, const Src &src)
     const unsigned blocks = (unsigned)((cells + threads - 1) / threads);
     if (h->off32)
         hipLaunchKernelGGL((k_unstream<S, true, Src>), dim3(blocks), dim3(threads), 0, h->stream,
-                           lattice<S>(h, h->cur), geometry<S>(h), src);
+                           lattice(h, h->cur), geometry<S>(h), src);
     else
         hipLaunchKernelGGL((k_unstream<S, false, Src>), dim3(blocks), dim3(threads), 0, h->stream,
-                           lattice<S>(h, h->cur), geometry<S>(h), src);
+                           lattice(h, h->cur), geometry<S>(h), src);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -265,10 +276,10 @@ lbmx_status launch_macro(lbmx_cavity *h, double *r, double *u, double *v, double
     const unsigned blocks = (unsigned)((cells + 255) / 256);
     if (h->off32)
         hipLaunchKernelGGL((k_macro<S, true>), dim3(blocks), dim3(256), 0, h->stream,
-                           lattice<S>(h, h->cur), geometry<S>(h), r, u, v, w, th);
+                           lattice(h, h->cur), geometry<S>(h), r, u, v, w, th);
     else
         hipLaunchKernelGGL((k_macro<S, false>), dim3(blocks), dim3(256), 0, h->stream,
-                           lattice<S>(h, h->cur), geometry<S>(h), r, u, v, w, th);
+                           lattice(h, h->cur), geometry<S>(h), r, u, v, w, th);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -280,10 +291,10 @@ lbmx_status launch_pops(lbmx_cavity *h, double *f, double *g)
     const unsigned blocks = (unsigned)((cells + 255) / 256);
     if (h->off32)
         hipLaunchKernelGGL((k_pops<S, true>), dim3(blocks), dim3(256), 0, h->stream,
-                           lattice<S>(h, h->cur), geometry<S>(h), f, g);
+                           lattice(h, h->cur), geometry<S>(h), f, g);
     else
         hipLaunchKernelGGL((k_pops<S, false>), dim3(blocks), dim3(256), 0, h->stream,
-                           lattice<S>(h, h->cur), geometry<S>(h), f, g);
+                           lattice(h, h->cur), geometry<S>(h), f, g);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -297,25 +308,28 @@ lbmx_status launch_nu(lbmx_cavity *h, double *map)
     const int threads = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
     if (h->off32)
         hipLaunchKernelGGL((k_nu_rows<S, true>), dim3(n), dim3(threads), 0, h->stream,
-                           lattice<S>(h, h->cur), geometry<S>(h), h->p.theta_hot, part, map);
+                           lattice(h, h->cur), geometry<S>(h), h->p.theta_hot, part, map);
     else
         hipLaunchKernelGGL((k_nu_rows<S, false>), dim3(n), dim3(threads), 0, h->stream,
-                           lattice<S>(h, h->cur), geometry<S>(h), h->p.theta_hot, part, map);
+                           lattice(h, h->cur), geometry<S>(h), h->p.theta_hot, part, map);
     hipLaunchKernelGGL(k_nu_final, dim3(1), dim3(256), 0, h->stream, part, n, out);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
 
 // Dispatch a templated launcher on the storage type.
-#define DISPATCH(h, fn, ...)                                                   \
-    ([&]() -> lbmx_status {                                                    \
-        switch ((h)->p.storage) {                                              \
-        case LBMX_F64: return fn<double>(__VA_ARGS__);                         \
-        case LBMX_F32: return fn<float>(__VA_ARGS__);                          \
-        case LBMX_F16: return fn<__half>(__VA_ARGS__);                         \
-        case LBMX_BF16: return fn<__hip_bfloat16>(__VA_ARGS__);                \
-        default: return fail(LBMX_EINVAL, "bad storage");                      \
-        }                                                                      \
+using bf16 = __hip_bfloat16;
+#define DISPATCH(h, fn, ...)                                                           \
+    ([&]() -> lbmx_status {                                                            \
+        switch ((h)->p.storage) {                                                      \
+        case LBMX_F64: return fn<Store<double, double>>(__VA_ARGS__);                  \
+        case LBMX_F32: return fn<Store<float, float>>(__VA_ARGS__);                    \
+        case LBMX_F16: return fn<Store<__half, __half>>(__VA_ARGS__);                  \
+        case LBMX_BF16: return fn<Store<bf16, bf16>>(__VA_ARGS__);                     \
+        case LBMX_F16_F32: return fn<Store<__half, float>>(__VA_ARGS__);               \
+        case LBMX_BF16_F32: return fn<Store<bf16, float>>(__VA_ARGS__);                \
+        default: return fail(LBMX_EINVAL, "bad storage");                              \
+        }                                                                              \
     }())
 
 template <typename S>
@@ -413,10 +427,10 @@ lbmx_status lbmx_bytes_per_cell(int32_t storage, double *bytes)
 {
     if (!bytes)
         return fail(LBMX_EINVAL, "bytes is NULL");
-    const size_t b = storage_size(storage);
-    if (!b)
+    const size_t bf = flow_size(storage), bg = energy_size(storage);
+    if (!bf)
         return fail(LBMX_EINVAL, "storage = %d not a lbmx_storage", storage);
-    *bytes = 26.0 * 2.0 * double(b);
+    *bytes = 2.0 * double(19 * bf + 7 * bg);
     return LBMX_OK;
 }
 
@@ -445,7 +459,7 @@ lbmx_status lbmx_create(const lbmx_params *p, void *dev_workspace, size_t ws_byt
     h->L = L;
     h->cur = 0;
     h->t = 0;
-    h->off32 = 26.0 * double(L.plane) * double(storage_size(p->storage)) <= 4294967295.0;
+    h->off32 = double(L.lattice) <= 4294967295.0;
     default_launch(p->n, &h->bx, &h->by);
     if (stream) {
         h->stream = reinterpret_cast<hipStream_t>(stream);

@@ -70,6 +70,7 @@ def test_sizes():
     assert L.bytes_per_cell("f64") == 416.0
     assert L.bytes_per_cell("f32") == 208.0
     assert L.bytes_per_cell("f16") == 104.0 and L.bytes_per_cell("bf16") == 104.0
+    assert L.bytes_per_cell("f16_f32") == 132.0 and L.bytes_per_cell("bf16_f32") == 132.0
     p = L.make_params(n=256, ra=1e6, storage="f32")
     ws = L.workspace_bytes(p)
     assert ws >= 2 * 26 * 256 ** 3 * 4
