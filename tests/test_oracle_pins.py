@@ -435,3 +435,23 @@ def test_golden_tables_are_well_formed():
           if r["n"] == (50 if r["ra"] == 1e4 else 60)}
     for ra in (1e4, 1e5):
         assert by[(2, ra)] < by[(3, ra)] < by[(1, ra)]
+
+
+@pytest.mark.slow
+@pytest.mark.skipif(not os.environ.get("LBMX_SLOW"), reason="long CPU run; set LBMX_SLOW=1")
+def test_oracle_reproduces_table1_type1_ra1e4():
+    """The oracle itself at the paper's 50^3 grid, Type 1, Ra 1e4, run to
+    |dNu| < 1e-6 per 1000 steps, against Tables 1-3 (3 %)."""
+    with open(os.path.join(GOLDEN, "paper_tables.json")) as fh:
+        row = [r for r in json.load(fh)["cases"]
+               if r["wall_type"] == 1 and r["ra"] == 1e4 and r["n"] == 50][0]
+    o = O.Oracle(50, 1, ra=1e4)
+    prev = o.nusselt()["nu3d"]
+    for _ in range(100):
+        o.step(1000)
+        nu = o.nusselt()
+        if abs(nu["nu3d"] - prev) < 1e-6:
+            break
+        prev = nu["nu3d"]
+    for k in ("nu3d", "nu2d", "numax"):
+        assert abs(nu[k] - row[k]) <= 0.03 * row[k], (k, nu[k], row[k])
