@@ -174,6 +174,75 @@ lbmx_status lbmx_run_to_steady(lbmx_cavity *h, double tol, int64_t every, int64_
 lbmx_status lbmx_set_launch(lbmx_cavity *h, int32_t bx, int32_t by);
 lbmx_status lbmx_get_launch(const lbmx_cavity *h, int32_t *bx, int32_t *by);
 
+/* ------------------------------------------------------------------ batch
+ * Many cavities (uneven n, Ra, wall type; one storage format) advanced
+ * together: every time step is ONE kernel launch over a work list of
+ * fixed-size node tiles drawn from all active cavities (each node update as
+ * lbmx_step), replayed from a captured hipGraph of `graph_steps` launches.
+ * Cavities that reach a steady Nu are retired from the work list.  All
+ * active cavities share the batch's time step count since their last
+ * (re)initialisation.  Device memory is allocated by the library. */
+typedef struct lbmx_batch lbmx_batch;
+
+/* Cavity states reported by lbmx_batch_info. */
+enum { LBMX_ACTIVE = 0, LBMX_CONVERGED = 1, LBMX_MAXSTEPS = 2, LBMX_DIVERGED = 3 };
+
+/* Create a batch of `count` cavities from p[0..count-1] (same storage for
+ * all, 4 <= n <= 255).  Each cavity starts at rest with theta = 0.  stream
+ * as in lbmx_create. */
+lbmx_status lbmx_batch_create(const lbmx_params *p, int32_t count, void *stream, lbmx_batch **out);
+
+/* Destroy a batch (NULL-safe). */
+void lbmx_batch_destroy(lbmx_batch *b);
+
+/* (Re)initialise cavity k at rest with theta0 (host, n_k^3 doubles; NULL =
+ * 0), reset its step count, and make it active again. */
+lbmx_status lbmx_batch_init_rest(lbmx_batch *b, int32_t k, const double *theta0_host);
+
+/* Advance every active cavity by nsteps time steps (asynchronous). */
+lbmx_status lbmx_batch_step(lbmx_batch *b, int64_t nsteps);
+
+/* Step all active cavities in chunks of `every`; after each chunk evaluate
+ * each active cavity's Nu_3D (Eq. 40) and retire it when
+ * |Nu_3D(t) - Nu_3D(t - every)| < tol (LBMX_CONVERGED), when it has taken
+ * max_steps steps in this call (LBMX_MAXSTEPS) or when Nu is not finite
+ * (LBMX_DIVERGED).  Returns when no cavity is active; *n_converged (may be
+ * NULL) counts converged cavities.  ENOTCONVERGED / EUNSTABLE if any cavity
+ * ended that way. */
+lbmx_status lbmx_batch_run_to_steady(lbmx_batch *b, double tol, int64_t every, int64_t max_steps,
+                                     int32_t *n_converged);
+
+/* State, step count and last Nu evaluation of cavity k (pointers may be NULL). */
+lbmx_status lbmx_batch_info(const lbmx_batch *b, int32_t k, int32_t *state, int64_t *t,
+                            lbmx_nu *last);
+
+/* Nu (Eqs. 39-41) of cavity k now (synchronises). */
+lbmx_status lbmx_batch_nusselt(lbmx_batch *b, int32_t k, lbmx_nu *out);
+
+/* Macroscopic fields of cavity k, as lbmx_read_macro. */
+lbmx_status lbmx_batch_read_macro(lbmx_batch *b, int32_t k, double *rho, double *ux, double *uy,
+                                  double *uz, double *theta);
+
+/* u, v, w (lattice units) and theta of cavity k resampled trilinearly onto
+ * an out_n^3 node-centred grid of the same cube (clamped at the outermost
+ * node centres): host_uvwt holds 4 out_n^3 floats, field-major, x fastest. */
+lbmx_status lbmx_batch_resample(lbmx_batch *b, int32_t k, int32_t out_n, float *host_uvwt);
+
+/* Launch shape: `block` threads (= nodes per tile, multiple of 64, <= 1024),
+ * `grid` blocks striding over the tiles (0 = one block per tile), and
+ * `graph_steps` launches per captured graph (even; 0 = no graph). */
+lbmx_status lbmx_batch_set_launch(lbmx_batch *b, int32_t block, int32_t grid, int32_t graph_steps);
+lbmx_status lbmx_batch_get_launch(const lbmx_batch *b, int32_t *block, int32_t *grid,
+                                  int32_t *graph_steps);
+
+/* Time candidate (block, grid) shapes on the batch's current work list and
+ * keep the fastest; with cache_path (a JSON file, created if missing) the
+ * choice is looked up / stored under the GPU, storage, cavity count and node
+ * count.  Timing advances the cavities, so every cavity is afterwards reset
+ * to rest with theta = 0 at step 0: call it before initialising.
+ * *us_per_step (may be NULL) receives the chosen shape's time per step. */
+lbmx_status lbmx_batch_autotune(lbmx_batch *b, const char *cache_path, double *us_per_step);
+
 const char *lbmx_strerror(lbmx_status s);
 const char *lbmx_last_error(void);
 

@@ -1,0 +1,308 @@
+// host.hpp -- host-side helpers shared by the single-cavity and batch
+// entry points of the C-ABI: parameter derivation and validation (Sec. 4,
+// Eq. 38; Eqs. 26, 36), relaxation-rate tables, lattice layout, and the
+// launchers of the initialisation / readback / Nusselt kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstddef>
+#include <cstdint>
+
+#include "../../include/lbmx.h"
+#include "kernels.hpp"
+
+namespace lbmx {
+namespace host {
+
+// Record a thread-local error message (lbmx_last_error) and return s.
+lbmx_status fail(lbmx_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(LBMX_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+// Element bytes of the flow (D3Q19) and energy (D3Q7) planes.
+inline size_t flow_size(int32_t s)
+{
+    switch (s) {
+    case LBMX_F64: return 8;
+    case LBMX_F32: return 4;
+    case LBMX_F16:
+    case LBMX_BF16:
+    case LBMX_F16_F32:
+    case LBMX_BF16_F32: return 2;
+    default: return 0;
+    }
+}
+inline size_t energy_size(int32_t s)
+{
+    switch (s) {
+    case LBMX_F64: return 8;
+    case LBMX_F32:
+    case LBMX_F16_F32:
+    case LBMX_BF16_F32: return 4;
+    case LBMX_F16:
+    case LBMX_BF16: return 2;
+    default: return 0;
+    }
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+struct Derived {
+    double u_c, gbeta, nu, alpha, s_nu, tau_t;
+    double s[19], tau[7];
+};
+
+// Sec. 4, Eq. (38): Ma = u_c / c_s with c_s^2 = 1/3 (Eq. 13), u_c^2 = g beta dT H
+// (dT = 1 in units of theta), Ra = g beta dT H^3 Pr / nu^2, Pr = nu / alpha.
+// Eq. (26): s_nu = 1/(3 nu + 1/2).  Eq. (36): tau = 1/2 + alpha/epsilon, epsilon = 1/4.
+inline lbmx_status derive(const lbmx_params *p, Derived *d)
+{
+    if (!p)
+        return fail(LBMX_EINVAL, "params is NULL");
+    if (p->n < 4 || p->n > 1024)
+        return fail(LBMX_EINVAL, "n = %d outside [4, 1024]", p->n);
+    if (p->wall_type < 1 || p->wall_type > 3)
+        return fail(LBMX_EINVAL, "wall_type = %d not in {1, 2, 3}", p->wall_type);
+    if (!(p->ra > 0) || !std::isfinite(p->ra))
+        return fail(LBMX_EINVAL, "Ra must be positive and finite");
+    if (!(p->pr > 0) || !std::isfinite(p->pr))
+        return fail(LBMX_EINVAL, "Pr must be positive and finite");
+    if (!(p->ma > 0) || !(p->ma <= 0.5))
+        return fail(LBMX_EINVAL, "Ma = %g outside (0, 0.5]", p->ma);
+    if (!std::isfinite(p->theta_hot) || !std::isfinite(p->theta_cold) ||
+        !std::isfinite(p->theta_ref) || !std::isfinite(p->buoyancy_scale))
+        return fail(LBMX_EINVAL, "non-finite temperature or buoyancy parameter");
+    if (flow_size(p->storage) == 0)
+        return fail(LBMX_EINVAL, "storage = %d not a lbmx_storage", p->storage);
+    const double u_c = p->ma * std::sqrt(1.0 / 3.0);
+    d->u_c = u_c;
+    d->gbeta = u_c * u_c / p->n;
+    d->nu = u_c * p->n * std::sqrt(p->pr / p->ra);
+    d->alpha = d->nu / p->pr;
+    d->s_nu = 1.0 / (3.0 * d->nu + 0.5);
+    d->tau_t = 0.5 + 4.0 * d->alpha;
+    if (p->custom_rates) {
+        for (int k = 0; k < 19; ++k) {
+            if (!(p->s[k] >= 0.0 && p->s[k] <= 2.0))
+                return fail(LBMX_EINVAL, "custom s[%d] = %g outside [0, 2]", k, p->s[k]);
+            d->s[k] = p->s[k];
+        }
+        for (int k = 0; k < 7; ++k) {
+            if (!(p->tau[k] > 0.0) || !std::isfinite(p->tau[k]))
+                return fail(LBMX_EINVAL, "custom tau[%d] = %g not positive", k, p->tau[k]);
+            d->tau[k] = p->tau[k];
+        }
+        if (!(d->tau[1] > 0.5 && d->tau[2] > 0.5 && d->tau[3] > 0.5))
+            return fail(LBMX_EINVAL, "custom diffusion rates need tau > 1/2");
+    } else {
+        if (!(d->s_nu > 0.0 && d->s_nu < 2.0))
+            return fail(LBMX_EINVAL, "s_nu = %g outside (0, 2)", d->s_nu);
+        if (!(d->tau_t > 0.5))
+            return fail(LBMX_EINVAL, "tau_T = %g not above 1/2", d->tau_t);
+        const double sn = d->s_nu;
+        const double s[19] = {1.0, 1.19, 1.4, 1.0, 1.2, 1.0, 1.2, 1.0, 1.2, sn,
+                              1.4, sn,   1.4, sn,  sn,  sn,  1.98, 1.98, 1.98};
+        for (int k = 0; k < 19; ++k)
+            d->s[k] = s[k];
+        const double tau[7] = {1.0, d->tau_t, d->tau_t, d->tau_t, 1.0, 1.0, 1.0};
+        for (int k = 0; k < 7; ++k)
+            d->tau[k] = tau[k];
+    }
+    return LBMX_OK;
+}
+
+template <typename T>
+Rates<T> make_rates(const lbmx_params *p, const Derived &d)
+{
+    // s_k / |M_k|^2 with the squared row norms of Eq. (21) (rows orthogonal).
+    Rates<T> r;
+    r.e = T(d.s[1] / 2394.0);
+    r.eps = T(d.s[2] / 252.0);
+    r.qx = T(d.s[4] / 40.0);
+    r.qy = T(d.s[6] / 40.0);
+    r.qz = T(d.s[8] / 40.0);
+    r.pxx = T(d.s[9] / 36.0);
+    r.pixx = T(d.s[10] / 72.0);
+    r.pww = T(d.s[11] / 12.0);
+    r.piww = T(d.s[12] / 24.0);
+    r.pxy = T(d.s[13] / 4.0);
+    r.pyz = T(d.s[14] / 4.0);
+    r.pxz = T(d.s[15] / 4.0);
+    r.mx = T(d.s[16] / 8.0);
+    r.my = T(d.s[17] / 8.0);
+    r.mz = T(d.s[18] / 8.0);
+    // Q = (Q^-1)^-1 for diagonal Q^-1 (Eq. 35), over |N_k|^2 of Eq. (32).
+    r.t1 = T(1.0 / d.tau[1] / 2.0);
+    r.t2 = T(1.0 / d.tau[2] / 2.0);
+    r.t3 = T(1.0 / d.tau[3] / 2.0);
+    r.t4 = T(1.0 / d.tau[4] / 42.0);
+    r.t5 = T(1.0 / d.tau[5] / 12.0);
+    r.t6 = T(1.0 / d.tau[6] / 4.0);
+    r.gbeta = T(d.gbeta * p->buoyancy_scale);
+    r.theta_ref = T(p->theta_ref);
+    return r;
+}
+
+struct Layout {
+    size_t plane;        // elements per population plane
+    size_t lattice;      // bytes per lattice
+    size_t scratch_off;  // byte offset of the Nu scratch
+    size_t total;
+};
+
+inline Layout layout_of(const lbmx_params *p)
+{
+    Layout L;
+    const size_t cells = (size_t)p->n * p->n * p->n;
+    L.plane = align_up(cells, 128);
+    L.lattice = align_up(L.plane * (19 * flow_size(p->storage) + 7 * energy_size(p->storage)), 256);
+    L.scratch_off = 2 * L.lattice;
+    L.total = L.scratch_off + align_up(sizeof(double) * (4 * (size_t)p->n + 8), 256);
+    return L;
+}
+
+
+// A lattice pair seen by the launchers: `lat` is the lattice holding the
+// current state, `plane` its plane length, `off32` selects 32-bit offsets.
+struct View {
+    char *lat;
+    int n, wall_type;
+    double theta_hot, theta_cold;
+    size_t plane;
+    bool off32;
+    hipStream_t stream;
+};
+
+template <class St>
+Geometry<typename St::T> geometry(const View &v)
+{
+    using T = typename St::T;
+    Geometry<T> g;
+    g.n = v.n;
+    g.wall_type = v.wall_type;
+    g.theta_hot = T(v.theta_hot);
+    g.theta_cold = T(v.theta_cold);
+    g.plane = v.plane;
+    return g;
+}
+
+template <class St, typename Src>
+lbmx_status launch_unstream(const View &v, const Src &src)
+{
+    const size_t cells = (size_t)v.n * v.n * v.n;
+    const unsigned blocks = (unsigned)((cells + 255) / 256);
+    if (v.off32)
+        hipLaunchKernelGGL((k_unstream<St, true, Src>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
+                           geometry<St>(v), src);
+    else
+        hipLaunchKernelGGL((k_unstream<St, false, Src>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
+                           geometry<St>(v), src);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+template <class St>
+lbmx_status launch_macro(const View &v, double *r, double *u, double *w3, double *w, double *th)
+{
+    const size_t cells = (size_t)v.n * v.n * v.n;
+    const unsigned blocks = (unsigned)((cells + 255) / 256);
+    if (v.off32)
+        hipLaunchKernelGGL((k_macro<St, true>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
+                           geometry<St>(v), r, u, w3, w, th);
+    else
+        hipLaunchKernelGGL((k_macro<St, false>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
+                           geometry<St>(v), r, u, w3, w, th);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+template <class St>
+lbmx_status launch_pops(const View &v, double *f, double *g)
+{
+    const size_t cells = (size_t)v.n * v.n * v.n;
+    const unsigned blocks = (unsigned)((cells + 255) / 256);
+    if (v.off32)
+        hipLaunchKernelGGL((k_pops<St, true>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
+                           geometry<St>(v), f, g);
+    else
+        hipLaunchKernelGGL((k_pops<St, false>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
+                           geometry<St>(v), f, g);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+// Nusselt reduction; `scratch` holds 4 n + 4 doubles, the result {Nu_3D,
+// Nu_2D, Nu_max, non-finite count} lands at scratch + 4 n.
+template <class St>
+lbmx_status launch_nu(const View &v, double *scratch, double *map)
+{
+    const int n = v.n;
+    double *out = scratch + 4 * (size_t)n;
+    const int threads = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
+    if (v.off32)
+        hipLaunchKernelGGL((k_nu_rows<St, true>), dim3(n), dim3(threads), 0, v.stream, v.lat,
+                           geometry<St>(v), v.theta_hot, scratch, map);
+    else
+        hipLaunchKernelGGL((k_nu_rows<St, false>), dim3(n), dim3(threads), 0, v.stream, v.lat,
+                           geometry<St>(v), v.theta_hot, scratch, map);
+    hipLaunchKernelGGL(k_nu_final<0>, dim3(1), dim3(256), 0, v.stream, scratch, n, out);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+template <class St>
+lbmx_status unstream_rest(const View &v, const double *theta0)
+{
+    return launch_unstream<St>(v, SourceRest{theta0});
+}
+
+template <class St>
+lbmx_status unstream_pops(const View &v, const double *f, const double *g)
+{
+    return launch_unstream<St>(v, SourcePops{f, g, (size_t)v.n * v.n * v.n});
+}
+
+template <class St>
+lbmx_status unstream_fields(const View &v, const float *u, const float *w2, const float *w,
+                            const float *th, int src_n)
+{
+    return launch_unstream<St>(v, SourceFields{u, w2, w, th, src_n, v.n});
+}
+
+// Device buffer released at scope exit (after the work using it completed:
+// hipFree waits for the device).
+struct DevBuf {
+    void *p = nullptr;
+    DevBuf() = default;
+    DevBuf(const DevBuf &) = delete;
+    DevBuf &operator=(const DevBuf &) = delete;
+    ~DevBuf()
+    {
+        if (p)
+            (void)hipFree(p);
+    }
+};
+
+// Call fn<Store<SF, SG>>(args...) for a storage code.
+#define LBMX_DISPATCH(storage, fn, ...)                                                        \
+    ([&]() -> lbmx_status {                                                                    \
+        switch (storage) {                                                                     \
+        case LBMX_F64: return fn<Store<double, double>>(__VA_ARGS__);                          \
+        case LBMX_F32: return fn<Store<float, float>>(__VA_ARGS__);                            \
+        case LBMX_F16: return fn<Store<__half, __half>>(__VA_ARGS__);                          \
+        case LBMX_BF16: return fn<Store<__hip_bfloat16, __hip_bfloat16>>(__VA_ARGS__);         \
+        case LBMX_F16_F32: return fn<Store<__half, float>>(__VA_ARGS__);                       \
+        case LBMX_BF16_F32: return fn<Store<__hip_bfloat16, float>>(__VA_ARGS__);              \
+        default: return ::lbmx::host::fail(LBMX_EINVAL, "bad storage %d", int(storage));       \
+        }                                                                                      \
+    }())
+
+}  // namespace host
+}  // namespace lbmx

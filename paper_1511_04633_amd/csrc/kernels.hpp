@@ -154,15 +154,22 @@ __device__ __forceinline__ bool z_wall_dirichlet(int wall_type) { return wall_ty
 template <bool kOff32>
 struct Access {
     using I = typename std::conditional<kOff32, uint32_t, size_t>::type;
+    // Lattices live in device global memory; saying so lets pointers read from
+    // a table (batch kernel) use global rather than flat instructions.
     template <typename S>
-    static __device__ __forceinline__ S ld(const char *base, I byte)
+    using gptr = __attribute__((address_space(1))) S *;
+    // Loads return the storage bits (Codec<S>::Raw); Codec<S>::dec converts.
+    template <typename S>
+    static __device__ __forceinline__ typename Codec<S>::Raw ld(const char *base, I byte)
     {
-        return *reinterpret_cast<const S *>(base + byte);
+        using R = typename Codec<S>::Raw;
+        return *(gptr<const R>)((gptr<const char>)base + byte);
     }
     template <typename S>
     static __device__ __forceinline__ void st(char *base, I byte, typename Codec<S>::Raw v)
     {
-        __builtin_nontemporal_store(v, reinterpret_cast<typename Codec<S>::Raw *>(base + byte));
+        using R = typename Codec<S>::Raw;
+        __builtin_nontemporal_store(v, (gptr<R>)((gptr<char>)base + byte));
     }
 };
 
@@ -552,6 +559,8 @@ __global__ __launch_bounds__(256) void k_nu_rows(const char *__restrict__ src,
 }
 
 // Combine the per-row partials in a fixed order: out = {Nu_3D, Nu_2D, Nu_max, bad}.
+// (A template only so that every translation unit may include this header.)
+template <int kUnused = 0>
 __global__ __launch_bounds__(256) void k_nu_final(const double *partial, int n, double *out)
 {
     double sum = 0.0, line = 0.0, mx = -1.0e300, bad = 0.0;

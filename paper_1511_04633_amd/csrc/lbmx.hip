@@ -1,4 +1,4 @@
-// lbmx.hip -- host side of the C-ABI declared in include/lbmx.h.
+// lbmx.hip -- single-cavity entry points of the C-ABI in include/lbmx.h.
 //
 // Li, Yang & Zhang (arXiv:1511.04633): parameters in lattice units from
 // Sec. 4 (Eq. 38), relaxation rates of Eq. (26) and Sec. 3.2 (Eqs. 35-36),
@@ -9,22 +9,22 @@
 
 #include <cmath>
 #include <cstdarg>
-#include <new>
 #include <cstdio>
-#include <cstdlib>
 #include <cstring>
+#include <new>
 #include <string>
 
-#include "../../include/lbmx.h"
-#include "kernels.hpp"
+#include "host.hpp"
 
 using namespace lbmx;
+using namespace lbmx::host;
 
 namespace {
-
 thread_local std::string g_last_error;
+}
 
-lbmx_status fail(lbmx_status s, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+namespace lbmx {
+namespace host {
 lbmx_status fail(lbmx_status s, const char *fmt, ...)
 {
     char buf[512];
@@ -35,157 +35,8 @@ lbmx_status fail(lbmx_status s, const char *fmt, ...)
     g_last_error = buf;
     return s;
 }
-
-#define HIP_TRY(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(LBMX_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
-    } while (0)
-
-// Element bytes of the flow (D3Q19) and energy (D3Q7) planes.
-size_t flow_size(int32_t s)
-{
-    switch (s) {
-    case LBMX_F64: return 8;
-    case LBMX_F32: return 4;
-    case LBMX_F16:
-    case LBMX_BF16:
-    case LBMX_F16_F32:
-    case LBMX_BF16_F32: return 2;
-    default: return 0;
-    }
-}
-size_t energy_size(int32_t s)
-{
-    switch (s) {
-    case LBMX_F64: return 8;
-    case LBMX_F32:
-    case LBMX_F16_F32:
-    case LBMX_BF16_F32: return 4;
-    case LBMX_F16:
-    case LBMX_BF16: return 2;
-    default: return 0;
-    }
-}
-
-size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
-
-struct Derived {
-    double u_c, gbeta, nu, alpha, s_nu, tau_t;
-    double s[19], tau[7];
-};
-
-// Sec. 4, Eq. (38): Ma = u_c / c_s with c_s^2 = 1/3 (Eq. 13), u_c^2 = g beta dT H
-// (dT = 1 in units of theta), Ra = g beta dT H^3 Pr / nu^2, Pr = nu / alpha.
-// Eq. (26): s_nu = 1/(3 nu + 1/2).  Eq. (36): tau = 1/2 + alpha/epsilon, epsilon = 1/4.
-lbmx_status derive(const lbmx_params *p, Derived *d)
-{
-    if (!p)
-        return fail(LBMX_EINVAL, "params is NULL");
-    if (p->n < 4 || p->n > 1024)
-        return fail(LBMX_EINVAL, "n = %d outside [4, 1024]", p->n);
-    if (p->wall_type < 1 || p->wall_type > 3)
-        return fail(LBMX_EINVAL, "wall_type = %d not in {1, 2, 3}", p->wall_type);
-    if (!(p->ra > 0) || !std::isfinite(p->ra))
-        return fail(LBMX_EINVAL, "Ra must be positive and finite");
-    if (!(p->pr > 0) || !std::isfinite(p->pr))
-        return fail(LBMX_EINVAL, "Pr must be positive and finite");
-    if (!(p->ma > 0) || !(p->ma <= 0.5))
-        return fail(LBMX_EINVAL, "Ma = %g outside (0, 0.5]", p->ma);
-    if (!std::isfinite(p->theta_hot) || !std::isfinite(p->theta_cold) ||
-        !std::isfinite(p->theta_ref) || !std::isfinite(p->buoyancy_scale))
-        return fail(LBMX_EINVAL, "non-finite temperature or buoyancy parameter");
-    if (flow_size(p->storage) == 0)
-        return fail(LBMX_EINVAL, "storage = %d not a lbmx_storage", p->storage);
-    const double u_c = p->ma * std::sqrt(1.0 / 3.0);
-    d->u_c = u_c;
-    d->gbeta = u_c * u_c / p->n;
-    d->nu = u_c * p->n * std::sqrt(p->pr / p->ra);
-    d->alpha = d->nu / p->pr;
-    d->s_nu = 1.0 / (3.0 * d->nu + 0.5);
-    d->tau_t = 0.5 + 4.0 * d->alpha;
-    if (p->custom_rates) {
-        for (int k = 0; k < 19; ++k) {
-            if (!(p->s[k] >= 0.0 && p->s[k] <= 2.0))
-                return fail(LBMX_EINVAL, "custom s[%d] = %g outside [0, 2]", k, p->s[k]);
-            d->s[k] = p->s[k];
-        }
-        for (int k = 0; k < 7; ++k) {
-            if (!(p->tau[k] > 0.0) || !std::isfinite(p->tau[k]))
-                return fail(LBMX_EINVAL, "custom tau[%d] = %g not positive", k, p->tau[k]);
-            d->tau[k] = p->tau[k];
-        }
-        if (!(d->tau[1] > 0.5 && d->tau[2] > 0.5 && d->tau[3] > 0.5))
-            return fail(LBMX_EINVAL, "custom diffusion rates need tau > 1/2");
-    } else {
-        if (!(d->s_nu > 0.0 && d->s_nu < 2.0))
-            return fail(LBMX_EINVAL, "s_nu = %g outside (0, 2)", d->s_nu);
-        if (!(d->tau_t > 0.5))
-            return fail(LBMX_EINVAL, "tau_T = %g not above 1/2", d->tau_t);
-        const double sn = d->s_nu;
-        const double s[19] = {1.0, 1.19, 1.4, 1.0, 1.2, 1.0, 1.2, 1.0, 1.2, sn,
-                              1.4, sn,   1.4, sn,  sn,  sn,  1.98, 1.98, 1.98};
-        for (int k = 0; k < 19; ++k)
-            d->s[k] = s[k];
-        const double tau[7] = {1.0, d->tau_t, d->tau_t, d->tau_t, 1.0, 1.0, 1.0};
-        for (int k = 0; k < 7; ++k)
-            d->tau[k] = tau[k];
-    }
-    return LBMX_OK;
-}
-
-template <typename T>
-Rates<T> make_rates(const lbmx_params *p, const Derived &d)
-{
-    // s_k / |M_k|^2 with the squared row norms of Eq. (21) (rows orthogonal).
-    Rates<T> r;
-    r.e = T(d.s[1] / 2394.0);
-    r.eps = T(d.s[2] / 252.0);
-    r.qx = T(d.s[4] / 40.0);
-    r.qy = T(d.s[6] / 40.0);
-    r.qz = T(d.s[8] / 40.0);
-    r.pxx = T(d.s[9] / 36.0);
-    r.pixx = T(d.s[10] / 72.0);
-    r.pww = T(d.s[11] / 12.0);
-    r.piww = T(d.s[12] / 24.0);
-    r.pxy = T(d.s[13] / 4.0);
-    r.pyz = T(d.s[14] / 4.0);
-    r.pxz = T(d.s[15] / 4.0);
-    r.mx = T(d.s[16] / 8.0);
-    r.my = T(d.s[17] / 8.0);
-    r.mz = T(d.s[18] / 8.0);
-    // Q = (Q^-1)^-1 for diagonal Q^-1 (Eq. 35), over |N_k|^2 of Eq. (32).
-    r.t1 = T(1.0 / d.tau[1] / 2.0);
-    r.t2 = T(1.0 / d.tau[2] / 2.0);
-    r.t3 = T(1.0 / d.tau[3] / 2.0);
-    r.t4 = T(1.0 / d.tau[4] / 42.0);
-    r.t5 = T(1.0 / d.tau[5] / 12.0);
-    r.t6 = T(1.0 / d.tau[6] / 4.0);
-    r.gbeta = T(d.gbeta * p->buoyancy_scale);
-    r.theta_ref = T(p->theta_ref);
-    return r;
-}
-
-struct Layout {
-    size_t plane;        // elements per population plane
-    size_t lattice;      // bytes per lattice
-    size_t scratch_off;  // byte offset of the Nu scratch
-    size_t total;
-};
-
-Layout layout_of(const lbmx_params *p)
-{
-    Layout L;
-    const size_t cells = (size_t)p->n * p->n * p->n;
-    L.plane = align_up(cells, 128);
-    L.lattice = align_up(L.plane * (19 * flow_size(p->storage) + 7 * energy_size(p->storage)), 256);
-    L.scratch_off = 2 * L.lattice;
-    L.total = L.scratch_off + align_up(sizeof(double) * (4 * (size_t)p->n + 8), 256);
-    return L;
-}
-
-}  // namespace
+}  // namespace host
+}  // namespace lbmx
 
 struct lbmx_cavity {
     lbmx_params p;
@@ -203,22 +54,15 @@ struct lbmx_cavity {
 
 namespace {
 
-template <class St>
-Geometry<typename St::T> geometry(const lbmx_cavity *h)
-{
-    using T = typename St::T;
-    Geometry<T> g;
-    g.n = h->p.n;
-    g.wall_type = h->p.wall_type;
-    g.theta_hot = T(h->p.theta_hot);
-    g.theta_cold = T(h->p.theta_cold);
-    g.plane = h->L.plane;
-    return g;
-}
-
 char *lattice(lbmx_cavity *h, int k) { return h->ws + (size_t)k * h->L.lattice; }
 
 double *scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L.scratch_off); }
+
+View view(lbmx_cavity *h)
+{
+    return View{lattice(h, h->cur), h->p.n, h->p.wall_type, h->p.theta_hot, h->p.theta_cold,
+                h->L.plane, h->off32, h->stream};
+}
 
 // One row of up to 256 nodes along x per block row; up to 512 threads per block.
 void default_launch(int n, int *bx, int *by)
@@ -230,21 +74,21 @@ void default_launch(int n, int *bx, int *by)
     *by = b;
 }
 
-template <class S>
+template <class St>
 lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
 {
-    using T = typename S::T;
-    const Geometry<T> geo = geometry<S>(h);
+    using T = typename St::T;
+    const Geometry<T> geo = geometry<St>(view(h));
     const Rates<T> rates = make_rates<T>(&h->p, h->d);
     const int n = h->p.n;
     dim3 block(h->bx, h->by, 1);
     dim3 grid((n + h->bx - 1) / h->bx, (n + h->by - 1) / h->by, n);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (h->off32)
-            hipLaunchKernelGGL((k_step<S, true>), grid, block, 0, h->stream, lattice(h, h->cur),
+            hipLaunchKernelGGL((k_step<St, true>), grid, block, 0, h->stream, lattice(h, h->cur),
                                lattice(h, 1 - h->cur), geo, rates);
         else
-            hipLaunchKernelGGL((k_step<S, false>), grid, block, 0, h->stream, lattice(h, h->cur),
+            hipLaunchKernelGGL((k_step<St, false>), grid, block, 0, h->stream, lattice(h, h->cur),
                                lattice(h, 1 - h->cur), geo, rates);
         h->cur = 1 - h->cur;
         h->t += 1;
@@ -252,117 +96,6 @@ lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
-
-template <typename S, typename Src>
-lbmx_status launch_unstream(lbmx_cavity *h, const Src &src)
-{
-    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
-    const int threads = 256;
-    const unsigned blocks = (unsigned)((cells + threads - 1) / threads);
-    if (h->off32)
-        hipLaunchKernelGGL((k_unstream<S, true, Src>), dim3(blocks), dim3(threads), 0, h->stream,
-                           lattice(h, h->cur), geometry<S>(h), src);
-    else
-        hipLaunchKernelGGL((k_unstream<S, false, Src>), dim3(blocks), dim3(threads), 0, h->stream,
-                           lattice(h, h->cur), geometry<S>(h), src);
-    HIP_TRY(hipGetLastError());
-    return LBMX_OK;
-}
-
-template <typename S>
-lbmx_status launch_macro(lbmx_cavity *h, double *r, double *u, double *v, double *w, double *th)
-{
-    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
-    const unsigned blocks = (unsigned)((cells + 255) / 256);
-    if (h->off32)
-        hipLaunchKernelGGL((k_macro<S, true>), dim3(blocks), dim3(256), 0, h->stream,
-                           lattice(h, h->cur), geometry<S>(h), r, u, v, w, th);
-    else
-        hipLaunchKernelGGL((k_macro<S, false>), dim3(blocks), dim3(256), 0, h->stream,
-                           lattice(h, h->cur), geometry<S>(h), r, u, v, w, th);
-    HIP_TRY(hipGetLastError());
-    return LBMX_OK;
-}
-
-template <typename S>
-lbmx_status launch_pops(lbmx_cavity *h, double *f, double *g)
-{
-    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
-    const unsigned blocks = (unsigned)((cells + 255) / 256);
-    if (h->off32)
-        hipLaunchKernelGGL((k_pops<S, true>), dim3(blocks), dim3(256), 0, h->stream,
-                           lattice(h, h->cur), geometry<S>(h), f, g);
-    else
-        hipLaunchKernelGGL((k_pops<S, false>), dim3(blocks), dim3(256), 0, h->stream,
-                           lattice(h, h->cur), geometry<S>(h), f, g);
-    HIP_TRY(hipGetLastError());
-    return LBMX_OK;
-}
-
-template <typename S>
-lbmx_status launch_nu(lbmx_cavity *h, double *map)
-{
-    const int n = h->p.n;
-    double *part = scratch(h);
-    double *out = part + 4 * (size_t)n;
-    const int threads = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
-    if (h->off32)
-        hipLaunchKernelGGL((k_nu_rows<S, true>), dim3(n), dim3(threads), 0, h->stream,
-                           lattice(h, h->cur), geometry<S>(h), h->p.theta_hot, part, map);
-    else
-        hipLaunchKernelGGL((k_nu_rows<S, false>), dim3(n), dim3(threads), 0, h->stream,
-                           lattice(h, h->cur), geometry<S>(h), h->p.theta_hot, part, map);
-    hipLaunchKernelGGL(k_nu_final, dim3(1), dim3(256), 0, h->stream, part, n, out);
-    HIP_TRY(hipGetLastError());
-    return LBMX_OK;
-}
-
-// Dispatch a templated launcher on the storage type.
-using bf16 = __hip_bfloat16;
-#define DISPATCH(h, fn, ...)                                                           \
-    ([&]() -> lbmx_status {                                                            \
-        switch ((h)->p.storage) {                                                      \
-        case LBMX_F64: return fn<Store<double, double>>(__VA_ARGS__);                  \
-        case LBMX_F32: return fn<Store<float, float>>(__VA_ARGS__);                    \
-        case LBMX_F16: return fn<Store<__half, __half>>(__VA_ARGS__);                  \
-        case LBMX_BF16: return fn<Store<bf16, bf16>>(__VA_ARGS__);                     \
-        case LBMX_F16_F32: return fn<Store<__half, float>>(__VA_ARGS__);               \
-        case LBMX_BF16_F32: return fn<Store<bf16, float>>(__VA_ARGS__);                \
-        default: return fail(LBMX_EINVAL, "bad storage");                              \
-        }                                                                              \
-    }())
-
-template <typename S>
-lbmx_status unstream_rest(lbmx_cavity *h, const double *theta0)
-{
-    SourceRest s{theta0};
-    return launch_unstream<S>(h, s);
-}
-
-template <typename S>
-lbmx_status unstream_pops(lbmx_cavity *h, const double *f, const double *g)
-{
-    SourcePops s{f, g, (size_t)h->p.n * h->p.n * h->p.n};
-    return launch_unstream<S>(h, s);
-}
-
-template <typename S>
-lbmx_status unstream_fields(lbmx_cavity *h, const float *u, const float *v, const float *w,
-                            const float *th, int src_n)
-{
-    SourceFields s{u, v, w, th, src_n, h->p.n};
-    return launch_unstream<S>(h, s);
-}
-
-// Device buffer released at scope exit.
-struct DevBuf {
-    void *p = nullptr;
-    ~DevBuf()
-    {
-        if (p)
-            (void)hipFree(p);
-    }
-};
 
 lbmx_status check_handle(const lbmx_cavity *h)
 {
@@ -522,7 +255,7 @@ lbmx_status lbmx_init_rest(lbmx_cavity *h, const double *theta0_host)
                                h->stream));
     }
     h->cur = 0;
-    s = DISPATCH(h, unstream_rest, h, reinterpret_cast<const double *>(buf.p));
+    s = LBMX_DISPATCH(h->p.storage, unstream_rest, view(h), reinterpret_cast<const double *>(buf.p));
     if (s != LBMX_OK)
         return s;
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -547,7 +280,7 @@ lbmx_status lbmx_set_populations(lbmx_cavity *h, const double *f_host, const dou
     double *gd = fd + 19 * cells;
     HIP_TRY(hipMemcpyAsync(fd, f_host, 19 * cells * sizeof(double), hipMemcpyHostToDevice, h->stream));
     HIP_TRY(hipMemcpyAsync(gd, g_host, 7 * cells * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    s = DISPATCH(h, unstream_pops, h, fd, gd);
+    s = LBMX_DISPATCH(h->p.storage, unstream_pops, view(h), fd, gd);
     if (s != LBMX_OK)
         return s;
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -565,7 +298,7 @@ lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host)
     HIP_TRY(hipMalloc(&buf.p, 26 * cells * sizeof(double)));
     double *fd = reinterpret_cast<double *>(buf.p);
     double *gd = fd + 19 * cells;
-    s = DISPATCH(h, launch_pops, h, f_host ? fd : nullptr, g_host ? gd : nullptr);
+    s = LBMX_DISPATCH(h->p.storage, launch_pops, view(h), f_host ? fd : nullptr, g_host ? gd : nullptr);
     if (s != LBMX_OK)
         return s;
     if (f_host)
@@ -587,7 +320,7 @@ lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *de
     if (src_n < 1 || src_n > 4096)
         return fail(LBMX_EINVAL, "src_n = %d outside [1, 4096]", src_n);
     h->cur = 0;
-    s = DISPATCH(h, unstream_fields, h, dev_u, dev_v, dev_w, dev_theta, src_n);
+    s = LBMX_DISPATCH(h->p.storage, unstream_fields, view(h), dev_u, dev_v, dev_w, dev_theta, src_n);
     if (s != LBMX_OK)
         return s;
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -602,7 +335,7 @@ lbmx_status lbmx_step(lbmx_cavity *h, int64_t nsteps)
         return s;
     if (nsteps < 0)
         return fail(LBMX_EINVAL, "nsteps must be >= 0");
-    return DISPATCH(h, launch_steps, h, nsteps);
+    return LBMX_DISPATCH(h->p.storage, launch_steps, h, nsteps);
 }
 
 lbmx_status lbmx_step_timed(lbmx_cavity *h, int64_t nsteps, double *ms)
@@ -617,7 +350,7 @@ lbmx_status lbmx_step_timed(lbmx_cavity *h, int64_t nsteps, double *ms)
     HIP_TRY(hipEventCreate(&b));
     hipError_t e = hipEventRecord(a, h->stream);
     if (e == hipSuccess) {
-        s = DISPATCH(h, launch_steps, h, nsteps);
+        s = LBMX_DISPATCH(h->p.storage, launch_steps, h, nsteps);
         e = hipEventRecord(b, h->stream);
     }
     if (e == hipSuccess)
@@ -659,7 +392,7 @@ lbmx_status lbmx_read_macro(lbmx_cavity *h, double *rho, double *ux, double *uy,
     double *dev[5];
     for (int k = 0; k < 5; ++k)
         dev[k] = host[k] ? reinterpret_cast<double *>(buf.p) + k * cells : nullptr;
-    s = DISPATCH(h, launch_macro, h, dev[0], dev[1], dev[2], dev[3], dev[4]);
+    s = LBMX_DISPATCH(h->p.storage, launch_macro, view(h), dev[0], dev[1], dev[2], dev[3], dev[4]);
     if (s != LBMX_OK)
         return s;
     for (int k = 0; k < 5; ++k)
@@ -681,7 +414,7 @@ lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host)
     DevBuf mbuf;
     if (map_host)
         HIP_TRY(hipMalloc(&mbuf.p, (size_t)n * n * sizeof(double)));
-    s = DISPATCH(h, launch_nu, h, reinterpret_cast<double *>(mbuf.p));
+    s = LBMX_DISPATCH(h->p.storage, launch_nu, view(h), scratch(h), reinterpret_cast<double *>(mbuf.p));
     if (s != LBMX_OK)
         return s;
     double res[4];

@@ -29,7 +29,12 @@ SYMBOLS = [
     "lbmx_get_populations", "lbmx_init_fields", "lbmx_step", "lbmx_step_timed", "lbmx_time",
     "lbmx_read_macro", "lbmx_nusselt", "lbmx_run_to_steady", "lbmx_set_launch",
     "lbmx_get_launch", "lbmx_strerror", "lbmx_last_error",
+    "lbmx_batch_create", "lbmx_batch_destroy", "lbmx_batch_init_rest", "lbmx_batch_step",
+    "lbmx_batch_run_to_steady", "lbmx_batch_info", "lbmx_batch_nusselt",
+    "lbmx_batch_read_macro", "lbmx_batch_resample", "lbmx_batch_set_launch",
+    "lbmx_batch_get_launch", "lbmx_batch_autotune",
 ]
+BATCH_STATE = {0: "active", 1: "converged", 2: "max_steps", 3: "diverged"}
 
 
 class lbmx_params(ctypes.Structure):
@@ -90,6 +95,19 @@ def load() -> ctypes.CDLL:
         "lbmx_run_to_steady": [_vp, ctypes.c_double, i64, i64, ctypes.POINTER(lbmx_nu)],
         "lbmx_set_launch": [_vp, i32, i32],
         "lbmx_get_launch": [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
+        "lbmx_batch_create": [P, i32, _vp, ctypes.POINTER(_vp)],
+        "lbmx_batch_init_rest": [_vp, i32, _dp],
+        "lbmx_batch_step": [_vp, i64],
+        "lbmx_batch_run_to_steady": [_vp, ctypes.c_double, i64, i64, ctypes.POINTER(i32)],
+        "lbmx_batch_info": [_vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
+                            ctypes.POINTER(lbmx_nu)],
+        "lbmx_batch_nusselt": [_vp, i32, ctypes.POINTER(lbmx_nu)],
+        "lbmx_batch_read_macro": [_vp, i32, _dp, _dp, _dp, _dp, _dp],
+        "lbmx_batch_resample": [_vp, i32, i32, _fp],
+        "lbmx_batch_set_launch": [_vp, i32, i32, i32],
+        "lbmx_batch_get_launch": [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32),
+                                  ctypes.POINTER(i32)],
+        "lbmx_batch_autotune": [_vp, ctypes.c_char_p, _dp],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -97,6 +115,8 @@ def load() -> ctypes.CDLL:
         fn.restype = ctypes.c_int
     L.lbmx_destroy.argtypes = [_vp]
     L.lbmx_destroy.restype = None
+    L.lbmx_batch_destroy.argtypes = [_vp]
+    L.lbmx_batch_destroy.restype = None
     L.lbmx_strerror.argtypes = [ctypes.c_int]
     L.lbmx_strerror.restype = ctypes.c_char_p
     L.lbmx_last_error.argtypes = []
@@ -272,3 +292,96 @@ class Cavity:
 
     def derived(self) -> dict:
         return derive(self.params)
+
+
+class Batch:
+    """Many cavities advanced together by one launch per step (lbmx_batch_*).
+
+    cases: list of dicts with n, ra, wall_type and optional theta0 (n^3
+    array) / params overrides; all share `storage`.
+    """
+
+    def __init__(self, cases, storage="f32", stream=None):
+        import torch
+
+        L = load()
+        self.cases = [dict(c) for c in cases]
+        arr = (lbmx_params * len(cases))()
+        for k, c in enumerate(cases):
+            kw = {k2: v for k2, v in c.items() if k2 not in ("theta0", "seed")}
+            arr[k] = make_params(storage=storage, **kw)
+        self.n = [int(c["n"]) for c in cases]
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        h = _vp()
+        _check(L.lbmx_batch_create(arr, len(cases), _vp(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self._params = arr
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and _lib is not None:
+            _lib.lbmx_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __len__(self):
+        return len(self.n)
+
+    def init_rest(self, k, theta0=None):
+        th = None if theta0 is None else np.ascontiguousarray(theta0, dtype=np.float64).reshape(-1)
+        if th is not None and th.size != self.n[k] ** 3:
+            raise ValueError("theta0 needs n^3 values")
+        _check(load().lbmx_batch_init_rest(self._h, int(k), _dptr(th)))
+        return self
+
+    def step(self, nsteps=1):
+        _check(load().lbmx_batch_step(self._h, int(nsteps)))
+        return self
+
+    def run_to_steady(self, tol=1e-6, every=1000, max_steps=2_000_000):
+        nc = ctypes.c_int32()
+        st = load().lbmx_batch_run_to_steady(self._h, tol, int(every), int(max_steps),
+                                             ctypes.byref(nc))
+        _check(st, ok=(0, 4, 5))
+        return int(nc.value)
+
+    def info(self, k):
+        s, t, nu = ctypes.c_int32(), ctypes.c_int64(), lbmx_nu()
+        _check(load().lbmx_batch_info(self._h, int(k), ctypes.byref(s), ctypes.byref(t),
+                                      ctypes.byref(nu)))
+        return {"state": BATCH_STATE[s.value], "t": int(t.value), "nu3d": nu.nu3d,
+                "nu2d": nu.nu2d, "numax": nu.numax}
+
+    def nusselt(self, k):
+        out = lbmx_nu()
+        _check(load().lbmx_batch_nusselt(self._h, int(k), ctypes.byref(out)))
+        return {"nu3d": out.nu3d, "nu2d": out.nu2d, "numax": out.numax, "step": out.step}
+
+    def read_macro(self, k):
+        n = self.n[k]
+        arrs = [np.empty(n ** 3) for _ in range(5)]
+        _check(load().lbmx_batch_read_macro(self._h, int(k), *[_dptr(a) for a in arrs]))
+        return tuple(a.reshape((n,) * 3) for a in arrs)
+
+    def resample(self, k, out_n=64):
+        out = np.empty(4 * out_n ** 3, dtype=np.float32)
+        _check(load().lbmx_batch_resample(self._h, int(k), int(out_n),
+                                          out.ctypes.data_as(_fp)))
+        return out.reshape(4, out_n, out_n, out_n)
+
+    def set_launch(self, block=256, grid=0, graph_steps=64):
+        _check(load().lbmx_batch_set_launch(self._h, int(block), int(grid), int(graph_steps)))
+        return self
+
+    def get_launch(self):
+        b, g, s = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _check(load().lbmx_batch_get_launch(self._h, ctypes.byref(b), ctypes.byref(g),
+                                            ctypes.byref(s)))
+        return int(b.value), int(g.value), int(s.value)
+
+    def autotune(self, cache_path=None):
+        us = ctypes.c_double()
+        path = None if cache_path is None else os.fsencode(cache_path)
+        _check(load().lbmx_batch_autotune(self._h, path, ctypes.byref(us)))
+        return float(us.value)
