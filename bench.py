@@ -43,6 +43,24 @@ def cpu_baseline(seconds: float, n: int = 64, ra: float = 1e6, wall_type: int = 
             "sample": f"FP64 oracle, {n}^3 Type {wall_type} Ra {ra:g}, {steps} steps in {dt:.1f} s"}
 
 
+def time_to_steady(wall_type: int, n: int = 128, ra: float = 1e5, storage: str = "f32"):
+    """Wall time from rest to |dNu_3D| < 1e-6 per 1000 steps (host clock, all
+    synchronisations included) for the 128^3, Ra 1e5 cavity."""
+    import torch
+
+    from paper_1511_04633_amd import inputs, lbmx
+
+    cav = lbmx.Cavity(n=n, wall_type=wall_type, ra=ra, storage=storage,
+                      theta0=inputs.theta_noise(n, 20151115))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r = cav.run_to_steady(tol=1e-6, every=1000, max_steps=2_000_000)
+    dt = time.perf_counter() - t0
+    return {"workload": f"{n}^3 Type {wall_type} Ra {ra:g} {storage}", "seconds": round(dt, 3),
+            "steps": r["step"], "converged": r["converged"], "nu3d": r["nu3d"],
+            "nu2d": r["nu2d"], "numax": r["numax"]}
+
+
 def counter_traffic(storage: str, n: int):
     """HBM bytes per step launch measured by rocprofv3 counters (profiles/traffic.json),
     or None when no measurement exists or the kernel sources changed since."""
@@ -98,6 +116,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true",
                     help="skip timing a plain device copy of the same bytes")
+    ap.add_argument("--steady-types", default="1",
+                    help="wall types timed to steady at 128^3 Ra 1e5 (comma list; '' = skip)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -165,6 +185,13 @@ def main():
                      "copy_achieved": None if copy_gbs is None else round(copy_gbs, 1)},
         "nu3d_after": nu["nu3d"],
     }
+    del cav
+    torch.cuda.empty_cache()
+    steady = []
+    for wt in [int(v) for v in args.steady_types.split(",") if v.strip()]:
+        steady.append(time_to_steady(wt))
+    if steady:
+        line["time_to_steady"] = steady
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wall_type=args.wall_type, ra=args.ra)
     print(json.dumps(line), flush=True)
