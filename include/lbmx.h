@@ -243,6 +243,87 @@ lbmx_status lbmx_batch_get_launch(const lbmx_batch *b, int32_t *block, int32_t *
  * *us_per_step (may be NULL) receives the chosen shape's time per step. */
 lbmx_status lbmx_batch_autotune(lbmx_batch *b, const char *cache_path, double *us_per_step);
 
+/* ------------------------------------------------------------ surrogate
+ * Kernels of the 3-D convolutional U-Net that maps (log10 Ra, wall type) to
+ * steady u, v, w, theta and warm-starts a cavity (lbmx_init_fields).  Not a
+ * step of the paper's method: it is trained on steady fields the batched
+ * solver produces.  All pointers are device pointers; every call enqueues on
+ * `stream` (a hipStream_t, NULL = the null stream) and returns at once.
+ * Activations are channel-last BF16 [B][D][H][W][C], C a multiple of 16;
+ * convolution weights BF16 [Co][27][Ci], tap = (kz*3 + ky)*3 + kx at offset
+ * (kx-1, ky-1, kz-1), zero padding; biases, gradients and optimiser state
+ * FP32.  Products on the matrix cores (BF16 in, FP32 accumulate). */
+
+/* out[p][co] = bias[co] + sum_{tap,ci} w[co][tap][ci] in[p + off(tap)][ci];
+ * out is BF16 (out_f32 = 0) or FP32 [B][D][H][W][Co].  bias may be NULL.
+ * 16 <= Ci <= 1024, 16 <= Co <= 160, multiples of 16. */
+lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias, void *out,
+                               int32_t out_f32, int32_t B, int32_t D, int32_t H, int32_t W,
+                               int32_t Ci, int32_t Co, void *stream);
+
+/* wt[ci][26 - tap][co] = w[co][tap][ci]: with it, lbmx_nn_conv3d_fwd of an
+ * output gradient (Co channels) gives the input gradient (Ci channels). */
+lbmx_status lbmx_nn_conv3d_flip(const void *w, void *wt, int32_t Ci, int32_t Co, void *stream);
+
+/* gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci] and, if gb is
+ * not NULL, gb[co] += sum_p gout[p][co] (FP32, accumulated atomically, so
+ * the summation order varies between runs).  (Co/16)(Ci/16) <= 64. */
+lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, float *gb, int32_t B,
+                                 int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                                 void *stream);
+
+/* a = z sigmoid(z) elementwise (n BF16 values), and its gradient
+ * gz = ga sigmoid(z) (1 + z (1 - sigmoid(z))). */
+lbmx_status lbmx_nn_silu(const void *z, void *a, int64_t n, void *stream);
+lbmx_status lbmx_nn_silu_bwd(const void *z, const void *ga, void *gz, int64_t n, void *stream);
+
+/* 2x2x2 average pooling of in [B][D][H][W][C] (even extents) into out;
+ * backward = 1: in is the pooled gradient, out the input gradient. */
+lbmx_status lbmx_nn_pool2(const void *in, void *out, int32_t B, int32_t D, int32_t H, int32_t W,
+                          int32_t C, int32_t backward, void *stream);
+
+/* Nearest-neighbour x2 upsampling of in [B][D][H][W][C] into out
+ * [B][2D][2H][2W][C]; backward = 1: in is the upsampled gradient, out the
+ * input gradient (sum over the 8 copies). */
+lbmx_status lbmx_nn_up2(const void *in, void *out, int32_t B, int32_t D, int32_t H, int32_t W,
+                        int32_t C, int32_t backward, void *stream);
+
+/* out[p] = [a[p] | b[p]] (Ca + Cb channels, nvox voxels); backward = 1
+ * splits the gradient `out` into a and b. */
+lbmx_status lbmx_nn_concat(void *a, void *b, void *out, int64_t nvox, int32_t Ca, int32_t Cb,
+                           int32_t backward, void *stream);
+
+/* Squared error of the first K of C channels of pred [nvox][C] against
+ * target [nvox][K] (both FP32): grad [nvox][C] BF16 = 2 (pred - target) /
+ * (nvox K) (0 for channels >= K); partial[0..npartial) receives per-block
+ * sums of squared errors (their sum / (nvox K) is the loss). */
+lbmx_status lbmx_nn_mse(const float *pred, const float *target, void *grad, double *partial,
+                        int32_t npartial, int64_t nvox, int32_t C, int32_t K, void *stream);
+
+/* Adam step (bias-corrected, decoupled weight decay wd) on FP32 master
+ * weights w with gradient g (cleared afterwards) and moments m, v; writes
+ * the BF16 copy w_bf16 (may be NULL).  step >= 1 counts updates. */
+lbmx_status lbmx_nn_adam(float *w, float *g, float *m, float *v, void *w_bf16, int64_t n, float lr,
+                         float b1, float b2, float eps, int64_t step, float wd, void *stream);
+
+/* FP32 -> BF16 (round to nearest even). */
+lbmx_status lbmx_nn_to_bf16(const float *a, void *b, int64_t n, void *stream);
+
+/* Network input on an m^3 node-centred grid, BF16 [B][m][m][m][16]:
+ * channel 0 = cond[2b] (normalised log10 Ra), 1..3 = one-hot of the wall
+ * type cond[2b+1] in {1, 2, 3}, 4..6 = node coordinates in [-1, 1], rest 0. */
+lbmx_status lbmx_nn_make_input(const float *cond, void *out, int32_t B, int32_t m, void *stream);
+
+/* out = a + b for n BF16 values (sums of gradients of a tensor used twice). */
+lbmx_status lbmx_nn_add(const void *a, const void *b, void *out, int64_t n, void *stream);
+
+/* FP32 layout change between channel-first [B][K][V] (a) and channel-last
+ * [B][V][C] (b, first K of C channels, others zero): to_channel_last = 1
+ * reads a and writes b; 0 reads a as channel-last and writes b channel-first.
+ * Each of the K channels is multiplied by scale[k] (device, may be NULL). */
+lbmx_status lbmx_nn_layout(const float *a, float *b, int32_t B, int64_t V, int32_t K, int32_t C,
+                           int32_t to_channel_last, const float *scale, void *stream);
+
 const char *lbmx_strerror(lbmx_status s);
 const char *lbmx_last_error(void);
 

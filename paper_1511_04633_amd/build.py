@@ -11,7 +11,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SRCS = [os.path.join(HERE, "csrc", f) for f in ("lbmx.hip", "batch.hip")]
+SRCS = [os.path.join(HERE, "csrc", f) for f in ("lbmx.hip", "batch.hip", "nn.hip")]
 LIB = os.path.join(HERE, "liblbmx.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -1,0 +1,726 @@
+// nn.hip -- hand-written BF16 / FP32 kernels of the 3-D convolutional U-Net
+// that predicts steady cavity fields from (Ra, wall type) and warm-starts
+// the lattice Boltzmann solve.
+//
+// Tensors: activations are channel-last BF16, [B][D][H][W][C] with C a
+// multiple of 16; 3x3x3 convolution weights are BF16 [Co][27][Ci] with tap
+// t = (kz*3 + ky)*3 + kx at offset (kx-1, ky-1, kz-1); biases, weight
+// gradients, Adam state and master weights are FP32.
+//
+// Convolution = implicit GEMM on the matrix cores: out[p][co] =
+// sum_{tap, ci} W[co][tap][ci] in[p + off(tap)][ci] with M = co, N = voxels,
+// K = (tap, ci), one v_mfma_f32_16x16x16_bf16 per 16 input channels of a tap,
+// FP32 accumulation.  A wavefront owns 16 consecutive voxels and every output
+// channel; its operands are 8-byte vector loads (4 consecutive channels per
+// lane) straight from global memory, where the 27-fold re-read of a voxel
+// and the reuse of the weights by every wavefront are served by the caches.
+// MFMA operand layout (checked on the device): lane l holds A[l%16][4(l/16)+j]
+// and B[4(l/16)+j][l%16], j < 4, and gets D[4(l/16)+j][l%16].
+//
+// Backward: the data gradient is the same convolution of the output gradient
+// with the flipped, transposed weights (W'[ci][26-tap][co] = W[co][tap][ci]);
+// the weight gradient is a GEMM over voxels (K = voxels), staged through LDS
+// transposed to [channel][voxel] so that every MFMA operand is one 8-byte
+// LDS read, accumulated in FP32 and added to the global gradient atomically.
+#include <hip/hip_bf16.h>
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+
+#include "host.hpp"
+
+using namespace lbmx::host;
+
+namespace {
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+using bf = unsigned short;  // BF16 bits
+
+__device__ __forceinline__ float bf2f(bf h) { return __uint_as_float(uint32_t(h) << 16); }
+__device__ __forceinline__ bf f2bf(float f) { return __bfloat16_as_ushort(__float2bfloat16(f)); }
+
+struct Dims {
+    int B, D, H, W;  // batch and spatial extent
+    int Ci, Co;      // channels (multiples of 16)
+};
+
+__device__ __forceinline__ long long nvox_of(const Dims &d)
+{
+    return (long long)d.B * d.D * d.H * d.W;
+}
+
+// ------------------------------------------------------------- convolution
+// One wavefront: 16 consecutive voxels (flat index), all COT*16 output
+// channels.  Block = 4 wavefronts.
+template <int COT>
+__global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, const bf *__restrict__ w,
+                                                  const float *__restrict__ bias, void *__restrict__ out,
+                                                  int out_f32, Dims d)
+{
+    const int lane = threadIdx.x & 63;
+    const long long nv = nvox_of(d);
+    const long long v0 = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
+    if (v0 >= nv)
+        return;
+    const int col = lane & 15, kq = lane >> 4;
+    const long long p = v0 + col;
+    const bool pv = p < nv;
+    int x = 0, y = 0, z = 0, b = 0;
+    if (pv) {
+        long long r = p;
+        x = int(r % d.W); r /= d.W;
+        y = int(r % d.H); r /= d.H;
+        z = int(r % d.D);
+        b = int(r / d.D);
+    }
+    f4 acc[COT];
+#pragma unroll
+    for (int j = 0; j < COT; ++j)
+        acc[j] = f4{0.f, 0.f, 0.f, 0.f};
+    const size_t wrow = size_t(27) * d.Ci;  // weights per output channel
+    for (int tap = 0; tap < 27; ++tap) {
+        const int xs = x + tap % 3 - 1, ys = y + (tap / 3) % 3 - 1, zs = z + tap / 9 - 1;
+        const bool inb = pv && xs >= 0 && xs < d.W && ys >= 0 && ys < d.H && zs >= 0 && zs < d.D;
+        const long long q = (((long long)b * d.D + zs) * d.H + ys) * d.W + xs;
+        const bf *src = in + (inb ? q : 0) * d.Ci + kq * 4;
+        const bf *wt = w + size_t(col) * wrow + size_t(tap) * d.Ci + kq * 4;
+        for (int c0 = 0; c0 < d.Ci; c0 += 16) {
+            s4 bv = s4{0, 0, 0, 0};
+            if (inb)
+                bv = *reinterpret_cast<const s4 *>(src + c0);
+#pragma unroll
+            for (int j = 0; j < COT; ++j) {
+                const s4 av = *reinterpret_cast<const s4 *>(wt + size_t(j) * 16 * wrow + c0);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
+            }
+        }
+    }
+    if (!pv)
+        return;
+    const int Co = COT * 16;
+#pragma unroll
+    for (int j = 0; j < COT; ++j) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int co = j * 16 + kq * 4 + r;
+            const float v = acc[j][r] + (bias ? bias[co] : 0.f);
+            if (out_f32)
+                reinterpret_cast<float *>(out)[p * Co + co] = v;
+            else
+                reinterpret_cast<bf *>(out)[p * Co + co] = f2bf(v);
+        }
+    }
+}
+
+// W'[ci][26 - tap][co] = W[co][tap][ci]: the data gradient is a forward
+// convolution of the output gradient with W'.
+__global__ __launch_bounds__(256) void k_conv_flip(const bf *__restrict__ w, bf *__restrict__ wt, int Ci,
+                                                   int Co)
+{
+    const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const long long n = (long long)Co * 27 * Ci;
+    if (i >= n)
+        return;
+    const int ci = int(i % Ci), tap = int((i / Ci) % 27), co = int(i / (27LL * Ci));
+    wt[((long long)ci * 27 + (26 - tap)) * Co + co] = w[i];
+}
+
+// gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci].  grid.y = tap;
+// block x covers the voxel range [bx*per, (bx+1)*per) in sub-chunks of 64.
+constexpr int WG_VOX = 64;
+constexpr int WG_SLOTS = 16;  // (co tile, ci tile) pairs per wavefront
+
+__global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, const bf *__restrict__ gout,
+                                                    float *__restrict__ gw, Dims d, long long per)
+{
+    extern __shared__ bf lds[];
+    const int tap = blockIdx.y;
+    const int Ci = d.Ci, Co = d.Co;
+    bf *gT = lds;                     // [Co][64]
+    bf *iT = lds + Co * WG_VOX;       // [Ci][64]
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int col = lane & 15, kq = lane >> 4;
+    const int COT = Co / 16, CIT = Ci / 16, npair = COT * CIT;
+    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+    const long long nv = nvox_of(d);
+    const long long vb = (long long)blockIdx.x * per;
+    const long long ve = vb + per < nv ? vb + per : nv;
+    f4 acc[WG_SLOTS];
+#pragma unroll
+    for (int s = 0; s < WG_SLOTS; ++s)
+        acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+    for (long long v0 = vb; v0 < ve; v0 += WG_VOX) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < WG_VOX * Co; i += blockDim.x) {
+            const int vo = i / Co, c = i % Co;
+            const long long p = v0 + vo;
+            gT[c * WG_VOX + vo] = p < ve ? gout[p * Co + c] : bf(0);
+        }
+        for (int i = threadIdx.x; i < WG_VOX * Ci; i += blockDim.x) {
+            const int vo = i / Ci, c = i % Ci;
+            const long long p = v0 + vo;
+            bf v = 0;
+            if (p < ve) {
+                long long r = p;
+                const int x = int(r % d.W); r /= d.W;
+                const int y = int(r % d.H); r /= d.H;
+                const int z = int(r % d.D);
+                const int b = int(r / d.D);
+                const int xs = x + dx, ys = y + dy, zs = z + dz;
+                if (xs >= 0 && xs < d.W && ys >= 0 && ys < d.H && zs >= 0 && zs < d.D)
+                    v = in[((((long long)b * d.D + zs) * d.H + ys) * d.W + xs) * Ci + c];
+            }
+            iT[c * WG_VOX + vo] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int s = 0; s < WG_SLOTS; ++s) {
+            const int pr = wv + 4 * s;
+            if (pr < npair) {
+                const int ct = pr / CIT, it = pr % CIT;
+#pragma unroll
+                for (int kk = 0; kk < WG_VOX / 16; ++kk) {
+                    const s4 av = *reinterpret_cast<const s4 *>(gT + (ct * 16 + col) * WG_VOX + kk * 16 + kq * 4);
+                    const s4 bv = *reinterpret_cast<const s4 *>(iT + (it * 16 + col) * WG_VOX + kk * 16 + kq * 4);
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[s], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < WG_SLOTS; ++s) {
+        const int pr = wv + 4 * s;
+        if (pr < npair) {
+            const int ct = pr / CIT, it = pr % CIT;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = ct * 16 + kq * 4 + r, ci = it * 16 + col;
+                atomicAdd(&gw[((long long)co * 27 + tap) * Ci + ci], acc[s][r]);
+            }
+        }
+    }
+}
+
+// gb[co] += sum_p gout[p][co]
+__global__ __launch_bounds__(256) void k_bias_grad(const bf *__restrict__ gout, float *__restrict__ gb,
+                                                   long long nv, int Co)
+{
+    const int ng = blockDim.x / Co;
+    const int g = threadIdx.x / Co, co = threadIdx.x % Co;
+    if (g >= ng)
+        return;
+    float s = 0.f;
+    for (long long p = (long long)blockIdx.x * ng + g; p < nv; p += (long long)gridDim.x * ng)
+        s += bf2f(gout[p * Co + co]);
+    atomicAdd(&gb[co], s);
+}
+
+// ------------------------------------------------------------ elementwise
+// SiLU a = z sigma(z); backward dz = da sigma(z) (1 + z (1 - sigma(z))).
+__global__ __launch_bounds__(256) void k_silu_fwd(const bf *__restrict__ z, bf *__restrict__ a, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float v = bf2f(z[i]);
+        a[i] = f2bf(v / (1.f + __expf(-v)));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_silu_bwd(const bf *__restrict__ z, const bf *__restrict__ ga,
+                                                  bf *__restrict__ gz, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float v = bf2f(z[i]);
+        const float s = 1.f / (1.f + __expf(-v));
+        gz[i] = f2bf(bf2f(ga[i]) * s * (1.f + v * (1.f - s)));
+    }
+}
+
+// 2x2x2 average pooling (even D, H, W) and its gradient.
+__global__ __launch_bounds__(256) void k_pool2_fwd(const bf *__restrict__ in, bf *__restrict__ out, int B,
+                                                   int D, int H, int W, int C)
+{
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const long long n = (long long)B * Do * Ho * Wo * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        long long r = i;
+        const int c = int(r % C); r /= C;
+        const int x = int(r % Wo); r /= Wo;
+        const int y = int(r % Ho); r /= Ho;
+        const int z = int(r % Do);
+        const int b = int(r / Do);
+        float s = 0.f;
+        for (int k = 0; k < 8; ++k) {
+            const int xi = 2 * x + (k & 1), yi = 2 * y + ((k >> 1) & 1), zi = 2 * z + (k >> 2);
+            s += bf2f(in[((((long long)b * D + zi) * H + yi) * W + xi) * C + c]);
+        }
+        out[i] = f2bf(0.125f * s);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_pool2_bwd(const bf *__restrict__ gout, bf *__restrict__ gin, int B,
+                                                   int D, int H, int W, int C)
+{
+    const long long n = (long long)B * D * H * W * C;
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        long long r = i;
+        const int c = int(r % C); r /= C;
+        const int x = int(r % W); r /= W;
+        const int y = int(r % H); r /= H;
+        const int z = int(r % D);
+        const int b = int(r / D);
+        gin[i] = f2bf(0.125f * bf2f(gout[((((long long)b * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * C + c]));
+    }
+}
+
+// Nearest-neighbour x2 upsampling (out is 2D x 2H x 2W) and its gradient.
+__global__ __launch_bounds__(256) void k_up2_fwd(const bf *__restrict__ in, bf *__restrict__ out, int B,
+                                                 int D, int H, int W, int C)
+{
+    const int Do = 2 * D, Ho = 2 * H, Wo = 2 * W;
+    const long long n = (long long)B * Do * Ho * Wo * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        long long r = i;
+        const int c = int(r % C); r /= C;
+        const int x = int(r % Wo); r /= Wo;
+        const int y = int(r % Ho); r /= Ho;
+        const int z = int(r % Do);
+        const int b = int(r / Do);
+        out[i] = in[((((long long)b * D + z / 2) * H + y / 2) * W + x / 2) * C + c];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_up2_bwd(const bf *__restrict__ gout, bf *__restrict__ gin, int B,
+                                                 int D, int H, int W, int C)
+{
+    const long long n = (long long)B * D * H * W * C;
+    const int Do = 2 * D, Ho = 2 * H, Wo = 2 * W;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        long long r = i;
+        const int c = int(r % C); r /= C;
+        const int x = int(r % W); r /= W;
+        const int y = int(r % H); r /= H;
+        const int z = int(r % D);
+        const int b = int(r / D);
+        float s = 0.f;
+        for (int k = 0; k < 8; ++k) {
+            const int xo = 2 * x + (k & 1), yo = 2 * y + ((k >> 1) & 1), zo = 2 * z + (k >> 2);
+            s += bf2f(gout[((((long long)b * Do + zo) * Ho + yo) * Wo + xo) * C + c]);
+        }
+        gin[i] = f2bf(s);
+    }
+}
+
+// Channel concatenation out[p] = [a[p] (Ca) | b[p] (Cb)] and its split.
+__global__ __launch_bounds__(256) void k_concat(const bf *__restrict__ a, const bf *__restrict__ b,
+                                                bf *__restrict__ out, long long nv, int Ca, int Cb)
+{
+    const int C = Ca + Cb;
+    const long long n = nv * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / C;
+        const int c = int(i % C);
+        out[i] = c < Ca ? a[p * Ca + c] : b[p * Cb + (c - Ca)];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_split(const bf *__restrict__ g, bf *__restrict__ ga,
+                                               bf *__restrict__ gb, long long nv, int Ca, int Cb)
+{
+    const int C = Ca + Cb;
+    const long long n = nv * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / C;
+        const int c = int(i % C);
+        if (c < Ca)
+            ga[p * Ca + c] = g[i];
+        else
+            gb[p * Cb + (c - Ca)] = g[i];
+    }
+}
+
+// Mean squared error over the first K channels of pred [nv][C] (FP32)
+// against target [nv][K] (FP32); gradient written as BF16 [nv][C] (zero in
+// channels >= K); per-block partial sums of squared errors in partial[].
+__global__ __launch_bounds__(256) void k_mse(const float *__restrict__ pred, const float *__restrict__ target,
+                                             bf *__restrict__ grad, double *__restrict__ partial,
+                                             long long nv, int C, int K, float scale)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    const long long n = nv * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long p = i / C;
+        const int c = int(i % C);
+        float g = 0.f;
+        if (c < K) {
+            const float e = pred[i] - target[p * K + c];
+            s += double(e) * e;
+            g = 2.f * e * scale;
+        }
+        grad[i] = f2bf(g);
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = red[0];
+}
+
+// Adam with decoupled weight decay on FP32 master weights; refreshes the
+// BF16 copy (nullable) and clears the gradient.
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, float *__restrict__ g,
+                                              float *__restrict__ m, float *__restrict__ v,
+                                              bf *__restrict__ wb, long long n, float lr, float b1,
+                                              float b2, float eps, float c1, float c2, float wd)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.f - b1) * gi;
+        const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        const float wi = w[i] - lr * ((mi * c1) / (sqrtf(vi * c2) + eps) + wd * w[i]);
+        w[i] = wi;
+        if (wb)
+            wb[i] = f2bf(wi);
+        g[i] = 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_f32_to_bf16(const float *__restrict__ a, bf *__restrict__ b, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        b[i] = f2bf(a[i]);
+}
+
+// Network input on an m^3 node-centred grid, 16 channels per voxel:
+// normalised log10 Ra, one-hot wall type (3), node coordinates in [-1, 1]
+// (3), zeros.  cond[b] = {log-Ra feature, wall type}.
+__global__ __launch_bounds__(256) void k_make_input(const float *__restrict__ cond, bf *__restrict__ out, int B,
+                                                    int m)
+{
+    const long long n = (long long)B * m * m * m;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
+         p += (long long)gridDim.x * blockDim.x) {
+        long long r = p;
+        const int x = int(r % m); r /= m;
+        const int y = int(r % m); r /= m;
+        const int z = int(r % m);
+        const int b = int(r / m);
+        const float lra = cond[2 * b], wt = cond[2 * b + 1];
+        float ch[16] = {0.f};
+        ch[0] = lra;
+        ch[1] = wt == 1.f ? 1.f : 0.f;
+        ch[2] = wt == 2.f ? 1.f : 0.f;
+        ch[3] = wt == 3.f ? 1.f : 0.f;
+        ch[4] = (2.f * x + 1.f) / m - 1.f;
+        ch[5] = (2.f * y + 1.f) / m - 1.f;
+        ch[6] = (2.f * z + 1.f) / m - 1.f;
+        for (int c = 0; c < 16; ++c)
+            out[p * 16 + c] = f2bf(ch[c]);
+    }
+}
+
+// Channel-first [B][K][V] <-> channel-last [B][V][C] (first K of C channels), FP32.
+// (channel-last value) = (channel-first value) * scale[k] (scale may be null).
+__global__ __launch_bounds__(256) void k_cf_to_cl(const float *__restrict__ a, float *__restrict__ b, int B,
+                                                  long long V, int K, int C, const float *__restrict__ scale)
+{
+    const long long n = (long long)B * V * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C);
+        const long long v = (i / C) % V, bb = i / (C * V);
+        b[i] = c < K ? a[(bb * K + c) * V + v] * (scale ? scale[c] : 1.f) : 0.f;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cl_to_cf(const float *__restrict__ a, float *__restrict__ b, int B,
+                                                  long long V, int K, int C, const float *__restrict__ scale)
+{
+    const long long n = (long long)B * K * V;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const long long v = i % V;
+        const int k = int((i / V) % K);
+        const long long bb = i / (V * K);
+        b[i] = a[(bb * V + v) * C + k] * (scale ? scale[k] : 1.f);
+    }
+}
+
+// out = a + b (BF16, computed in FP32).
+__global__ __launch_bounds__(256) void k_add(const bf *__restrict__ a, const bf *__restrict__ b,
+                                             bf *__restrict__ out, long long n)
+{
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x)
+        out[i] = f2bf(bf2f(a[i]) + bf2f(b[i]));
+}
+
+unsigned blocks_for(long long n)
+{
+    long long b = (n + 255) / 256;
+    return unsigned(b < 8192 ? (b < 1 ? 1 : b) : 8192);
+}
+
+hipStream_t S(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+lbmx_status check_dims(int B, int D, int H, int W)
+{
+    if (B < 1 || D < 1 || H < 1 || W < 1)
+        return fail(LBMX_EINVAL, "tensor extents must be positive");
+    return LBMX_OK;
+}
+
+template <int COT>
+void launch_fwd(const bf *in, const bf *w, const float *bias, void *out, int out_f32, Dims d, hipStream_t s)
+{
+    const long long nv = (long long)d.B * d.D * d.H * d.W;
+    const unsigned blocks = unsigned((nv + 63) / 64);
+    hipLaunchKernelGGL(k_conv_fwd<COT>, dim3(blocks), dim3(256), 0, s, in, w, bias, out, out_f32, d);
+}
+
+}  // namespace
+
+extern "C" {
+
+lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias, void *out,
+                               int32_t out_f32, int32_t B, int32_t D, int32_t H, int32_t W,
+                               int32_t Ci, int32_t Co, void *stream)
+{
+    lbmx_status st = check_dims(B, D, H, W);
+    if (st != LBMX_OK)
+        return st;
+    if (!in || !w || !out)
+        return fail(LBMX_EINVAL, "conv3d: NULL tensor");
+    if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 160)
+        return fail(LBMX_EINVAL, "conv3d: need Ci, Co multiples of 16, Ci <= 1024, Co <= 160");
+    const Dims d{B, D, H, W, Ci, Co};
+    const bf *i = reinterpret_cast<const bf *>(in);
+    const bf *wb = reinterpret_cast<const bf *>(w);
+    hipStream_t s = S(stream);
+    switch (Co / 16) {
+    case 1: launch_fwd<1>(i, wb, bias, out, out_f32, d, s); break;
+    case 2: launch_fwd<2>(i, wb, bias, out, out_f32, d, s); break;
+    case 3: launch_fwd<3>(i, wb, bias, out, out_f32, d, s); break;
+    case 4: launch_fwd<4>(i, wb, bias, out, out_f32, d, s); break;
+    case 5: launch_fwd<5>(i, wb, bias, out, out_f32, d, s); break;
+    case 6: launch_fwd<6>(i, wb, bias, out, out_f32, d, s); break;
+    case 7: launch_fwd<7>(i, wb, bias, out, out_f32, d, s); break;
+    case 8: launch_fwd<8>(i, wb, bias, out, out_f32, d, s); break;
+    case 9: launch_fwd<9>(i, wb, bias, out, out_f32, d, s); break;
+    case 10: launch_fwd<10>(i, wb, bias, out, out_f32, d, s); break;
+    }
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_conv3d_flip(const void *w, void *wt, int32_t Ci, int32_t Co, void *stream)
+{
+    if (!w || !wt || Ci < 1 || Co < 1)
+        return fail(LBMX_EINVAL, "conv3d_flip: bad arguments");
+    const long long n = (long long)Co * 27 * Ci;
+    hipLaunchKernelGGL(k_conv_flip, dim3(unsigned((n + 255) / 256)), dim3(256), 0, S(stream),
+                       reinterpret_cast<const bf *>(w), reinterpret_cast<bf *>(wt), Ci, Co);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, float *gb, int32_t B,
+                                 int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co, void *stream)
+{
+    lbmx_status st = check_dims(B, D, H, W);
+    if (st != LBMX_OK)
+        return st;
+    if (!in || !gout || !gw)
+        return fail(LBMX_EINVAL, "conv3d_wgrad: NULL tensor");
+    if (Ci < 16 || Ci % 16 || Co < 16 || Co % 16 || (Co / 16) * (Ci / 16) > 4 * WG_SLOTS ||
+        Co > 256)
+        return fail(LBMX_EINVAL, "conv3d_wgrad: need Ci, Co multiples of 16 with (Co/16)(Ci/16) <= %d",
+                    4 * WG_SLOTS);
+    const Dims d{B, D, H, W, Ci, Co};
+    const long long nv = (long long)B * D * H * W;
+    long long chunks = (nv + WG_VOX - 1) / WG_VOX;
+    long long gx = chunks < 96 ? chunks : 96;
+    long long per = ((chunks + gx - 1) / gx) * WG_VOX;
+    gx = (nv + per - 1) / per;
+    const size_t lds = size_t(Ci + Co) * WG_VOX * sizeof(bf);
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned(gx), 27), dim3(256), lds, S(stream),
+                       reinterpret_cast<const bf *>(in), reinterpret_cast<const bf *>(gout), gw, d, per);
+    if (gb)
+        hipLaunchKernelGGL(k_bias_grad, dim3(512), dim3(256), 0, S(stream),
+                           reinterpret_cast<const bf *>(gout), gb, nv, Co);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_silu(const void *z, void *a, int64_t n, void *stream)
+{
+    if (!z || !a || n < 0)
+        return fail(LBMX_EINVAL, "silu: bad arguments");
+    hipLaunchKernelGGL(k_silu_fwd, dim3(blocks_for(n)), dim3(256), 0, S(stream),
+                       reinterpret_cast<const bf *>(z), reinterpret_cast<bf *>(a), (long long)n);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_silu_bwd(const void *z, const void *ga, void *gz, int64_t n, void *stream)
+{
+    if (!z || !ga || !gz || n < 0)
+        return fail(LBMX_EINVAL, "silu_bwd: bad arguments");
+    hipLaunchKernelGGL(k_silu_bwd, dim3(blocks_for(n)), dim3(256), 0, S(stream),
+                       reinterpret_cast<const bf *>(z), reinterpret_cast<const bf *>(ga),
+                       reinterpret_cast<bf *>(gz), (long long)n);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_pool2(const void *in, void *out, int32_t B, int32_t D, int32_t H, int32_t W,
+                          int32_t C, int32_t backward, void *stream)
+{
+    lbmx_status st = check_dims(B, D, H, W);
+    if (st != LBMX_OK)
+        return st;
+    if (!in || !out || C < 1 || D % 2 || H % 2 || W % 2)
+        return fail(LBMX_EINVAL, "pool2: need even extents");
+    const long long n = (long long)B * D * H * W * C;
+    if (backward)  // in = gradient of the pooled tensor, out = gradient of the input
+        hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for(n)), dim3(256), 0, S(stream),
+                           reinterpret_cast<const bf *>(in), reinterpret_cast<bf *>(out), B, D, H, W, C);
+    else
+        hipLaunchKernelGGL(k_pool2_fwd, dim3(blocks_for(n / 8)), dim3(256), 0, S(stream),
+                           reinterpret_cast<const bf *>(in), reinterpret_cast<bf *>(out), B, D, H, W, C);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_up2(const void *in, void *out, int32_t B, int32_t D, int32_t H, int32_t W,
+                        int32_t C, int32_t backward, void *stream)
+{
+    lbmx_status st = check_dims(B, D, H, W);
+    if (st != LBMX_OK)
+        return st;
+    if (!in || !out || C < 1)
+        return fail(LBMX_EINVAL, "up2: bad arguments");
+    const long long n = (long long)B * D * H * W * C;
+    if (backward)  // in = gradient of the upsampled tensor, out = gradient of the input
+        hipLaunchKernelGGL(k_up2_bwd, dim3(blocks_for(n)), dim3(256), 0, S(stream),
+                           reinterpret_cast<const bf *>(in), reinterpret_cast<bf *>(out), B, D, H, W, C);
+    else
+        hipLaunchKernelGGL(k_up2_fwd, dim3(blocks_for(8 * n)), dim3(256), 0, S(stream),
+                           reinterpret_cast<const bf *>(in), reinterpret_cast<bf *>(out), B, D, H, W, C);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_concat(void *a, void *b, void *out, int64_t nvox, int32_t Ca, int32_t Cb,
+                           int32_t backward, void *stream)
+{
+    if (!a || !b || !out || nvox < 0 || Ca < 1 || Cb < 1)
+        return fail(LBMX_EINVAL, "concat: bad arguments");
+    const long long n = (long long)nvox * (Ca + Cb);
+    if (backward)  // out = gradient of the concatenation, a / b receive the parts
+        hipLaunchKernelGGL(k_split, dim3(blocks_for(n)), dim3(256), 0, S(stream),
+                           reinterpret_cast<const bf *>(out), reinterpret_cast<bf *>(a),
+                           reinterpret_cast<bf *>(b), (long long)nvox, Ca, Cb);
+    else
+        hipLaunchKernelGGL(k_concat, dim3(blocks_for(n)), dim3(256), 0, S(stream),
+                           reinterpret_cast<const bf *>(a), reinterpret_cast<const bf *>(b),
+                           reinterpret_cast<bf *>(out), (long long)nvox, Ca, Cb);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_mse(const float *pred, const float *target, void *grad, double *partial,
+                        int32_t npartial, int64_t nvox, int32_t C, int32_t K, void *stream)
+{
+    if (!pred || !target || !grad || !partial || npartial < 1 || npartial > 4096 || K < 1 || K > C)
+        return fail(LBMX_EINVAL, "mse: bad arguments");
+    const float scale = 1.0f / float(double(nvox) * K);
+    hipLaunchKernelGGL(k_mse, dim3(npartial), dim3(256), 0, S(stream), pred, target,
+                       reinterpret_cast<bf *>(grad), partial, (long long)nvox, C, K, scale);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_adam(float *w, float *g, float *m, float *v, void *w_bf16, int64_t n, float lr,
+                         float b1, float b2, float eps, int64_t step, float wd, void *stream)
+{
+    if (!w || !g || !m || !v || n < 0 || step < 1)
+        return fail(LBMX_EINVAL, "adam: bad arguments");
+    const float c1 = float(1.0 / (1.0 - std::pow(double(b1), double(step))));
+    const float c2 = float(1.0 / (1.0 - std::pow(double(b2), double(step))));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, S(stream), w, g, m, v,
+                       reinterpret_cast<bf *>(w_bf16), (long long)n, lr, b1, b2, eps, c1, c2, wd);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_to_bf16(const float *a, void *b, int64_t n, void *stream)
+{
+    if (!a || !b || n < 0)
+        return fail(LBMX_EINVAL, "to_bf16: bad arguments");
+    hipLaunchKernelGGL(k_f32_to_bf16, dim3(blocks_for(n)), dim3(256), 0, S(stream), a,
+                       reinterpret_cast<bf *>(b), (long long)n);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_make_input(const float *cond, void *out, int32_t B, int32_t m, void *stream)
+{
+    if (!cond || !out || B < 1 || m < 1)
+        return fail(LBMX_EINVAL, "make_input: bad arguments");
+    const long long n = (long long)B * m * m * m;
+    hipLaunchKernelGGL(k_make_input, dim3(blocks_for(n)), dim3(256), 0, S(stream), cond,
+                       reinterpret_cast<bf *>(out), B, m);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_add(const void *a, const void *b, void *out, int64_t n, void *stream)
+{
+    if (!a || !b || !out || n < 0)
+        return fail(LBMX_EINVAL, "add: bad arguments");
+    hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(256), 0, S(stream), reinterpret_cast<const bf *>(a),
+                       reinterpret_cast<const bf *>(b), reinterpret_cast<bf *>(out), (long long)n);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_layout(const float *a, float *b, int32_t B, int64_t V, int32_t K, int32_t C,
+                           int32_t to_channel_last, const float *scale, void *stream)
+{
+    if (!a || !b || B < 1 || V < 1 || K < 1 || K > C)
+        return fail(LBMX_EINVAL, "layout: bad arguments");
+    if (to_channel_last) {
+        const long long n = (long long)B * V * C;
+        hipLaunchKernelGGL(k_cf_to_cl, dim3(blocks_for(n)), dim3(256), 0, S(stream), a, b, B,
+                           (long long)V, K, C, scale);
+    } else {
+        const long long n = (long long)B * V * K;
+        hipLaunchKernelGGL(k_cl_to_cf, dim3(blocks_for(n)), dim3(256), 0, S(stream), a, b, B,
+                           (long long)V, K, C, scale);
+    }
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,347 @@
+"""3-D convolutional U-Net surrogate: (log10 Ra, wall type) -> steady
+u/u_c, v/u_c, w/u_c, theta on a 64^3 grid, used to warm-start the cavity.
+
+Every arithmetic step runs in the library's HIP kernels (``lbmx_nn_*``):
+this module only sequences them and holds device buffers, which PyTorch
+allocates (memory only).  Weights are BF16 for the matrix cores with FP32
+master copies, FP32 gradients and Adam state.
+
+Architecture (channels per level; two 3x3x3 convolutions + SiLU per block):
+  64^3: 16 -> 16 -> 16      (input: 7 features padded to 16)
+  32^3: 16 -> 32 -> 32      (2x2x2 average pooling between levels)
+  16^3: 32 -> 64 -> 64
+   8^3: 64 -> 96 -> 96
+  up (nearest x2) + skip concatenation: 96+64 -> 64 -> 64, 64+32 -> 32 -> 32,
+  32+16 -> 16 -> 16; head 16 -> 16 (linear, FP32; the first 4 are the fields)
+about 1.16 M parameters.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+
+import numpy as np
+
+from . import lbmx
+
+_vp = ctypes.c_void_p
+_i32, _i64, _f32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_float
+_NN = None
+
+NFEAT = 16       # padded input channels
+NOUT = 4         # u, v, w, theta
+LOG_RA_MID, LOG_RA_HALF = 4.5, 1.5  # log10 Ra in [3, 6] -> [-1, 1]
+
+
+def nn():
+    global _NN
+    if _NN is None:
+        L = lbmx.load()
+        sig = {
+            "lbmx_nn_conv3d_fwd": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_conv3d_flip": [_vp, _vp, _i32, _i32, _vp],
+            "lbmx_nn_conv3d_wgrad": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_silu": [_vp, _vp, _i64, _vp],
+            "lbmx_nn_silu_bwd": [_vp, _vp, _vp, _i64, _vp],
+            "lbmx_nn_pool2": [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_up2": [_vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_concat": [_vp, _vp, _vp, _i64, _i32, _i32, _i32, _vp],
+            "lbmx_nn_mse": [_vp, _vp, _vp, _vp, _i32, _i64, _i32, _i32, _vp],
+            "lbmx_nn_adam": [_vp, _vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i64, _f32, _vp],
+            "lbmx_nn_to_bf16": [_vp, _vp, _i64, _vp],
+            "lbmx_nn_make_input": [_vp, _vp, _i32, _i32, _vp],
+            "lbmx_nn_add": [_vp, _vp, _vp, _i64, _vp],
+            "lbmx_nn_layout": [_vp, _vp, _i32, _i64, _i32, _i32, _i32, _vp, _vp],
+        }
+        for name, args in sig.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = ctypes.c_int
+        _NN = L
+    return _NN
+
+
+def P(t):
+    """Device pointer of a torch tensor (None -> NULL)."""
+    return None if t is None else _vp(t.data_ptr())
+
+
+def call(name, *args):
+    st = getattr(nn(), name)(*args)
+    if st != 0:
+        raise lbmx.LbmxError(st, lbmx.load().lbmx_last_error().decode())
+
+
+def stream_ptr():
+    import torch
+    return _vp(torch.cuda.current_stream().cuda_stream)
+
+
+class Conv:
+    """3x3x3 convolution with bias: BF16 weights, FP32 master / grads / Adam."""
+
+    def __init__(self, ci, co, rng, act=True):
+        import torch
+
+        self.ci, self.co, self.act = ci, co, act
+        std = math.sqrt(2.0 / (27 * ci)) if act else math.sqrt(1.0 / (27 * ci))
+        w0 = (rng.standard_normal((co, 27, ci)) * std).astype(np.float32)
+        dev = "cuda"
+        self.w = torch.tensor(w0, device=dev)                         # master FP32
+        self.b = torch.zeros(co, dtype=torch.float32, device=dev)
+        self.wb = torch.empty((co, 27, ci), dtype=torch.bfloat16, device=dev)
+        self.wflip = torch.empty((ci, 27, co), dtype=torch.bfloat16, device=dev)
+        self.gw = torch.zeros_like(self.w)
+        self.gb = torch.zeros_like(self.b)
+        self.mw, self.vw = torch.zeros_like(self.w), torch.zeros_like(self.w)
+        self.mb, self.vb = torch.zeros_like(self.b), torch.zeros_like(self.b)
+        self.sync_bf16()
+
+    def nparams(self):
+        return self.w.numel() + self.b.numel()
+
+    def sync_bf16(self):
+        call("lbmx_nn_to_bf16", P(self.w), P(self.wb), self.w.numel(), stream_ptr())
+        call("lbmx_nn_conv3d_flip", P(self.wb), P(self.wflip), self.ci, self.co, stream_ptr())
+
+    def adam(self, lr, step, b1=0.9, b2=0.999, eps=1e-8, wd=0.0):
+        s = stream_ptr()
+        call("lbmx_nn_adam", P(self.w), P(self.gw), P(self.mw), P(self.vw), P(self.wb),
+             self.w.numel(), lr, b1, b2, eps, step, wd, s)
+        call("lbmx_nn_adam", P(self.b), P(self.gb), P(self.mb), P(self.vb), None,
+             self.b.numel(), lr, b1, b2, eps, step, 0.0, s)
+        call("lbmx_nn_conv3d_flip", P(self.wb), P(self.wflip), self.ci, self.co, s)
+
+
+class UNet:
+    LEVELS = (16, 32, 64, 96)
+
+    def __init__(self, seed=0, m=64):
+        rng = np.random.default_rng(seed)
+        c0, c1, c2, c3 = self.LEVELS
+        self.m = m
+        self.enc = [(Conv(NFEAT, c0, rng), Conv(c0, c0, rng)),
+                    (Conv(c0, c1, rng), Conv(c1, c1, rng)),
+                    (Conv(c1, c2, rng), Conv(c2, c2, rng)),
+                    (Conv(c2, c3, rng), Conv(c3, c3, rng))]
+        self.dec = [(Conv(c3 + c2, c2, rng), Conv(c2, c2, rng)),
+                    (Conv(c2 + c1, c1, rng), Conv(c1, c1, rng)),
+                    (Conv(c1 + c0, c0, rng), Conv(c0, c0, rng))]
+        self.head = Conv(c0, 16, rng, act=False)
+        self.step_count = 0
+        self.scale = None  # per-output-channel target scale (device FP32 [4])
+
+    def convs(self):
+        out = []
+        for a, b in self.enc + self.dec:
+            out += [a, b]
+        return out + [self.head]
+
+    def nparams(self):
+        return sum(c.nparams() for c in self.convs())
+
+    # ---- buffers -------------------------------------------------------------
+    @staticmethod
+    def _bf(*shape):
+        import torch
+        return torch.empty(shape, dtype=torch.bfloat16, device="cuda")
+
+    # ---- forward -------------------------------------------------------------
+    def _conv(self, conv, x, B, r, cache):
+        """conv + SiLU on a [B, r, r, r, ci] BF16 tensor; returns the activation."""
+        s = stream_ptr()
+        z = self._bf(B, r, r, r, conv.co)
+        call("lbmx_nn_conv3d_fwd", P(x), P(conv.wb), P(conv.b), P(z), 0, B, r, r, r, conv.ci,
+             conv.co, s)
+        a = self._bf(B, r, r, r, conv.co)
+        call("lbmx_nn_silu", P(z), P(a), z.numel(), s)
+        cache.append((conv, x, z, r))
+        return a
+
+    def forward(self, cond, B, train=False):
+        """cond: device FP32 [B, 2] = (normalised log10 Ra, wall type).
+        Returns FP32 predictions [B, m^3, 16] (channel-last)."""
+        import torch
+
+        s = stream_ptr()
+        m = self.m
+        cache = []
+        x = self._bf(B, m, m, m, NFEAT)
+        call("lbmx_nn_make_input", P(cond), P(x), B, m, s)
+        skips = []
+        r = m
+        h = x
+        for lvl, (ca, cb) in enumerate(self.enc):
+            h = self._conv(ca, h, B, r, cache)
+            h = self._conv(cb, h, B, r, cache)
+            if lvl < len(self.enc) - 1:
+                skips.append((h, r))
+                p = self._bf(B, r // 2, r // 2, r // 2, cb.co)
+                call("lbmx_nn_pool2", P(h), P(p), B, r, r, r, cb.co, 0, s)
+                cache.append(("pool", h, p, r))
+                h = p
+                r //= 2
+        for (ca, cb) in self.dec:
+            sk, rs = skips.pop()
+            cu = h.shape[-1]
+            u = self._bf(B, 2 * r, 2 * r, 2 * r, cu)
+            call("lbmx_nn_up2", P(h), P(u), B, r, r, r, cu, 0, s)
+            r *= 2
+            cat = self._bf(B, r, r, r, cu + sk.shape[-1])
+            call("lbmx_nn_concat", P(u), P(sk), P(cat), B * r ** 3, cu, sk.shape[-1], 0, s)
+            cache.append(("upcat", h, sk, r, cu))
+            h = self._conv(ca, cat, B, r, cache)
+            h = self._conv(cb, h, B, r, cache)
+        pred = torch.empty((B, m ** 3, 16), dtype=torch.float32, device="cuda")
+        call("lbmx_nn_conv3d_fwd", P(h), P(self.head.wb), P(self.head.b), P(pred), 1, B, m, m, m,
+             self.head.ci, 16, s)
+        self._cache = (cache, h, B) if train else None
+        return pred
+
+    # ---- backward ------------------------------------------------------------
+    def _conv_bwd(self, conv, x, z, r, B, ga):
+        s = stream_ptr()
+        gz = self._bf(B, r, r, r, conv.co)
+        call("lbmx_nn_silu_bwd", P(z), P(ga), P(gz), z.numel(), s)
+        call("lbmx_nn_conv3d_wgrad", P(x), P(gz), P(conv.gw), P(conv.gb), B, r, r, r, conv.ci,
+             conv.co, s)
+        gx = self._bf(B, r, r, r, conv.ci)
+        call("lbmx_nn_conv3d_fwd", P(gz), P(conv.wflip), None, P(gx), 0, B, r, r, r, conv.co,
+             conv.ci, s)
+        return gx
+
+    def backward(self, gpred):
+        """gpred: BF16 [B, m^3, 16] gradient of the loss w.r.t. the predictions."""
+        s = stream_ptr()
+        cache, hlast, B = self._cache
+        m = self.m
+        call("lbmx_nn_conv3d_wgrad", P(hlast), P(gpred), P(self.head.gw), P(self.head.gb), B, m,
+             m, m, self.head.ci, 16, s)
+        g = self._bf(B, m, m, m, self.head.ci)
+        call("lbmx_nn_conv3d_fwd", P(gpred), P(self.head.wflip), None, P(g), 0, B, m, m, m, 16,
+             self.head.ci, s)
+        skip_grads = []   # gradients reaching the skip tensors, deepest first
+        for item in reversed(cache):
+            if isinstance(item[0], Conv):
+                conv, x, z, r = item
+                g = self._conv_bwd(conv, x, z, r, B, g)
+            elif item[0] == "upcat":
+                _, hprev, sk, r, cu = item
+                cs = sk.shape[-1]
+                gu = self._bf(B, r, r, r, cu)
+                gs = self._bf(B, r, r, r, cs)
+                call("lbmx_nn_concat", P(gu), P(gs), P(g), B * r ** 3, cu, cs, 1, s)
+                skip_grads.append(gs)
+                g = self._bf(B, r // 2, r // 2, r // 2, cu)
+                call("lbmx_nn_up2", P(gu), P(g), B, r // 2, r // 2, r // 2, cu, 1, s)
+            else:  # pool
+                _, h, p, r = item
+                gh = self._bf(B, r, r, r, h.shape[-1])
+                call("lbmx_nn_pool2", P(g), P(gh), B, r, r, r, h.shape[-1], 1, s)
+                gsk = skip_grads.pop()
+                call("lbmx_nn_add", P(gh), P(gsk), P(gh), gh.numel(), s)
+                g = gh
+        self._cache = None
+
+    def adam(self, lr, wd=0.0):
+        self.step_count += 1
+        for c in self.convs():
+            c.adam(lr, self.step_count, wd=wd)
+
+    # ---- persistence -----------------------------------------------------------
+    def state(self):
+        d = {}
+        for k, c in enumerate(self.convs()):
+            d[f"w{k}"] = c.w.cpu().numpy()
+            d[f"b{k}"] = c.b.cpu().numpy()
+        if self.scale is not None:
+            d["scale"] = self.scale.cpu().numpy()
+        return d
+
+    def load_state(self, d):
+        import torch
+        for k, c in enumerate(self.convs()):
+            c.w.copy_(torch.tensor(d[f"w{k}"]))
+            c.b.copy_(torch.tensor(d[f"b{k}"]))
+            c.sync_bf16()
+        if "scale" in d:
+            self.scale = torch.tensor(np.asarray(d["scale"], np.float32), device="cuda")
+
+
+def cond_tensor(log10_ra, wall_type):
+    """Device FP32 [B, 2] conditioning: ((log10 Ra - 4.5)/1.5, wall type)."""
+    import torch
+    lr = (np.asarray(log10_ra, np.float64) - LOG_RA_MID) / LOG_RA_HALF
+    c = np.stack([lr, np.asarray(wall_type, np.float64)], axis=1).astype(np.float32)
+    return torch.tensor(c, device="cuda")
+
+
+def mse_loss(pred, target_cl, partial, K=NOUT):
+    """BF16 gradient of the squared error of pred [B, V, 16] (FP32) against
+    target [B, V, K] (FP32); per-block partial sums go to `partial` (device
+    FP64 [1024]).  Returns (gradient, element count)."""
+    import torch
+    nv = pred.shape[0] * pred.shape[1]
+    grad = torch.empty(pred.shape, dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_mse", P(pred), P(target_cl), P(grad), P(partial), 1024, nv, pred.shape[2], K,
+         stream_ptr())
+    return grad, nv * K
+
+
+def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=2e-3, seed=0, log=None):
+    """Fit the network to steady fields [N, 4, m, m, m] (channel-first FP32;
+    velocities already divided by u_c).  Per-channel target scales are the
+    fields' standard deviations; the learning rate follows a cosine decay."""
+    import time
+
+    import torch
+
+    N = fields.shape[0]
+    m = net.m
+    V = m ** 3
+    std = fields.reshape(N, NOUT, -1).std(axis=(0, 2)).astype(np.float32)
+    std = np.maximum(std, 1e-3)
+    net.scale = torch.tensor(std, device="cuda")
+    inv = torch.tensor(1.0 / std, device="cuda")
+    dev_fields = torch.tensor(np.ascontiguousarray(fields.reshape(N, NOUT, V), np.float32),
+                              device="cuda")
+    sample_bytes = NOUT * V * 4
+    target = torch.empty((batch, V, NOUT), dtype=torch.float32, device="cuda")
+    per_epoch = N // batch
+    partials = torch.zeros((per_epoch, 1024), dtype=torch.float64, device="cuda")
+    rng = np.random.default_rng(seed)
+    nsteps = epochs * per_epoch
+    hist = []
+    t0 = time.perf_counter()
+    step = 0
+    for ep in range(epochs):
+        order = rng.permutation(N)
+        for k in range(per_epoch):
+            idx = order[k * batch:(k + 1) * batch]
+            for j, i in enumerate(idx):
+                call("lbmx_nn_layout", _vp(dev_fields.data_ptr() + int(i) * sample_bytes),
+                     _vp(target.data_ptr() + j * sample_bytes), 1, V, NOUT, NOUT, 1, P(inv),
+                     stream_ptr())
+            cond = cond_tensor(log10_ra[idx], wall_type[idx])
+            pred = net.forward(cond, batch, train=True)
+            grad, cnt = mse_loss(pred, target, partials[k])
+            net.backward(grad)
+            lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(nsteps, 1)))
+            net.adam(lr_t)
+            step += 1
+        hist.append(float(partials.cpu().numpy().sum()) / (cnt * per_epoch))
+        if log and (ep % 10 == 0 or ep == epochs - 1):
+            log(f"epoch {ep} loss {hist[-1]:.5f} ({time.perf_counter() - t0:.1f} s)")
+    torch.cuda.synchronize()
+    return {"loss": hist, "seconds": time.perf_counter() - t0, "steps": step}
+
+
+def predict_fields(net, log10_ra, wall_type):
+    """Predicted u/u_c, v/u_c, w/u_c, theta on the m^3 grid: device FP32 [4, m^3]."""
+    import torch
+    m = net.m
+    cond = cond_tensor([log10_ra], [wall_type])
+    pred = net.forward(cond, 1)
+    out = torch.empty((NOUT, m ** 3), dtype=torch.float32, device="cuda")
+    call("lbmx_nn_layout", P(pred), P(out), 1, m ** 3, NOUT, 16, 0, P(net.scale), stream_ptr())
+    return out

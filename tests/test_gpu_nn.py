@@ -1,0 +1,327 @@
+"""Surrogate-network kernels on the GPU against the FP64 numpy oracle.
+
+Inputs are drawn in FP64, rounded to BF16 and given to both sides, so the
+only differences are FP32 accumulation order and the rounding of BF16
+outputs.  Accumulation bound: |gpu - ref| <= 2e-5 * (same sum of absolute
+terms) + 1e-6, the sum of absolute terms coming from the oracle applied to
+|x| and |w|."""
+import numpy as np
+import pytest
+
+from oracle import nn_oracle as N
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_1511_04633_amd import unet
+    unet.nn()
+
+
+def bits_of(a):
+    f = N.bf16_round(a).astype(np.float32)
+    return (f.view(np.uint32) >> 16).astype(np.uint16)
+
+
+def to_bf(a):
+    import torch
+    return torch.tensor(bits_of(a).view(np.int16)).view(torch.bfloat16).cuda()
+
+
+def from_bf(t):
+    import torch
+    b = t.view(torch.int16).cpu().numpy().view(np.uint16).astype(np.uint32) << 16
+    return b.view(np.float32).astype(np.float64)
+
+
+def to_f32(a):
+    import torch
+    return torch.tensor(np.asarray(a, np.float32)).cuda()
+
+
+def rnd(shape, seed, scale=1.0):
+    return N.bf16_round(np.random.default_rng(seed).standard_normal(shape) * scale)
+
+
+def S():
+    from paper_1511_04633_amd import unet
+    return unet.stream_ptr()
+
+
+def call(name, *a):
+    from paper_1511_04633_amd import unet
+    unet.call(name, *a)
+    import torch
+    torch.cuda.synchronize()
+
+
+def P(t):
+    from paper_1511_04633_amd import unet
+    return unet.P(t)
+
+
+SHAPES = [(2, 6, 6, 6), (1, 5, 4, 7)]
+CHANNELS = [(16, 16), (48, 16), (16, 32), (32, 96), (160, 64), (16, 160)]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("ci,co", CHANNELS)
+def test_conv_forward(shape, ci, co):
+    import torch
+    print(f"case: conv fwd {shape} {ci}->{co}", flush=True)
+    B, D, H, W = shape
+    x, w, b = rnd((B, D, H, W, ci), 1), rnd((co, 27, ci), 2, 0.1), rnd((co,), 3)
+    ref = N.conv3d(x, w, b)
+    bound = 2e-5 * (N.conv3d(np.abs(x), np.abs(w), np.abs(b))) + 1e-6
+    out = torch.empty((B, D, H, W, co), dtype=torch.float32, device="cuda")
+    call("lbmx_nn_conv3d_fwd", P(to_bf(x)), P(to_bf(w)), P(to_f32(b)), P(out), 1, B, D, H, W, ci,
+         co, S())
+    assert np.all(np.abs(out.cpu().numpy() - ref) <= bound)
+    ob = torch.empty((B, D, H, W, co), dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_conv3d_fwd", P(to_bf(x)), P(to_bf(w)), P(to_f32(b)), P(ob), 0, B, D, H, W, ci,
+         co, S())
+    assert np.all(np.abs(from_bf(ob) - ref) <= 2 ** -8 * np.abs(ref) + bound)
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("ci,co", [(16, 16), (48, 16), (32, 96), (160, 64)])
+def test_conv_data_gradient(shape, ci, co):
+    import torch
+    print(f"case: conv dgrad {shape} {ci}->{co}", flush=True)
+    B, D, H, W = shape
+    g, w = rnd((B, D, H, W, co), 4), rnd((co, 27, ci), 5, 0.1)
+    ref = N.conv3d_dgrad(g, w)
+    bound = 2e-5 * N.conv3d_dgrad(np.abs(g), np.abs(w)) + 1e-6
+    wt = torch.empty((ci, 27, co), dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_conv3d_flip", P(to_bf(w)), P(wt), ci, co, S())
+    out = torch.empty((B, D, H, W, ci), dtype=torch.float32, device="cuda")
+    call("lbmx_nn_conv3d_fwd", P(to_bf(g)), P(wt), None, P(out), 1, B, D, H, W, co, ci, S())
+    assert np.all(np.abs(out.cpu().numpy() - ref) <= bound)
+
+
+@pytest.mark.parametrize("shape", SHAPES + [(2, 16, 16, 16)])
+@pytest.mark.parametrize("ci,co", [(16, 16), (48, 16), (32, 96), (160, 64), (96, 96)])
+def test_conv_weight_gradient(shape, ci, co):
+    import torch
+    print(f"case: conv wgrad {shape} {ci}->{co}", flush=True)
+    B, D, H, W = shape
+    x, g = rnd((B, D, H, W, ci), 6), rnd((B, D, H, W, co), 7)
+    gw_ref, gb_ref = N.conv3d_wgrad(x, g)
+    bw, bb = N.conv3d_wgrad(np.abs(x), np.abs(g))
+    gw = torch.full((co, 27, ci), 0.5, dtype=torch.float32, device="cuda")  # accumulates
+    gb = torch.full((co,), -0.25, dtype=torch.float32, device="cuda")
+    call("lbmx_nn_conv3d_wgrad", P(to_bf(x)), P(to_bf(g)), P(gw), P(gb), B, D, H, W, ci, co, S())
+    assert np.all(np.abs(gw.cpu().numpy() - 0.5 - gw_ref) <= 2e-5 * bw + 1e-5)
+    assert np.all(np.abs(gb.cpu().numpy() + 0.25 - gb_ref) <= 2e-5 * bb + 1e-5)
+
+
+def test_pool_upsample_concat():
+    import torch
+    B, D, H, W, C = 2, 4, 6, 8, 32
+    x = rnd((B, D, H, W, C), 8)
+    p = torch.empty((B, D // 2, H // 2, W // 2, C), dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_pool2", P(to_bf(x)), P(p), B, D, H, W, C, 0, S())
+    ref = N.pool2(x)
+    assert np.all(np.abs(from_bf(p) - ref) <= 2 ** -8 * np.abs(ref) + 1e-7)
+    gy = rnd((B, D // 2, H // 2, W // 2, C), 9)
+    gx = torch.empty((B, D, H, W, C), dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_pool2", P(to_bf(gy)), P(gx), B, D, H, W, C, 1, S())
+    assert np.array_equal(from_bf(gx), N.pool2_bwd(gy))  # division by 8 is exact
+    u = torch.empty((B, 2 * D, 2 * H, 2 * W, C), dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_up2", P(to_bf(x)), P(u), B, D, H, W, C, 0, S())
+    assert np.array_equal(from_bf(u), N.up2(x))
+    gu = rnd((B, 2 * D, 2 * H, 2 * W, C), 10)
+    gd = torch.empty((B, D, H, W, C), dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_up2", P(to_bf(gu)), P(gd), B, D, H, W, C, 1, S())
+    ref = N.up2_bwd(gu)
+    assert np.all(np.abs(from_bf(gd) - ref) <= 2 ** -8 * np.abs(ref) + 1e-6)
+    a, b = rnd((B, D, H, W, 16), 11), rnd((B, D, H, W, 32), 12)
+    cat = torch.empty((B, D, H, W, 48), dtype=torch.bfloat16, device="cuda")
+    ta, tb = to_bf(a), to_bf(b)
+    call("lbmx_nn_concat", P(ta), P(tb), P(cat), B * D * H * W, 16, 32, 0, S())
+    assert np.array_equal(from_bf(cat), np.concatenate([a, b], axis=-1))
+    ga = torch.empty_like(ta)
+    gb = torch.empty_like(tb)
+    call("lbmx_nn_concat", P(ga), P(gb), P(cat), B * D * H * W, 16, 32, 1, S())
+    assert np.array_equal(from_bf(ga), a) and np.array_equal(from_bf(gb), b)
+
+
+def test_silu_add_mse_adam_layout_input():
+    import torch
+    z, ga = rnd((5000,), 13, 3.0), rnd((5000,), 14)
+    a = torch.empty(5000, dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_silu", P(to_bf(z)), P(a), 5000, S())
+    ref = N.silu(z)
+    assert np.all(np.abs(from_bf(a) - ref) <= 2 ** -8 * np.abs(ref) + 1e-6)
+    gz = torch.empty(5000, dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_silu_bwd", P(to_bf(z)), P(to_bf(ga)), P(gz), 5000, S())
+    ref = N.silu_bwd(z, ga)
+    assert np.all(np.abs(from_bf(gz) - ref) <= 2 ** -8 * np.abs(ref) + 1e-5)
+    s = torch.empty(5000, dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_add", P(to_bf(z)), P(to_bf(ga)), P(s), 5000, S())
+    ref = z + ga
+    assert np.all(np.abs(from_bf(s) - ref) <= 2 ** -8 * np.abs(ref) + 1e-7)
+    # squared error
+    V = 3000
+    pred, tgt = np.random.default_rng(15).standard_normal((V, 16)), np.random.default_rng(16).standard_normal((V, 4))
+    grad = torch.empty((V, 16), dtype=torch.bfloat16, device="cuda")
+    part = torch.zeros(64, dtype=torch.float64, device="cuda")
+    call("lbmx_nn_mse", P(to_f32(pred)), P(to_f32(tgt)), P(grad), P(part), 64, V, 16, 4, S())
+    p32, t32 = pred.astype(np.float32).astype(np.float64), tgt.astype(np.float32).astype(np.float64)
+    loss, g = N.mse(p32, t32, 4)
+    assert abs(part.cpu().numpy().sum() / (V * 4) - loss) <= 1e-6 * loss
+    assert np.all(np.abs(from_bf(grad) - g) <= 2 ** -8 * np.abs(g) + 1e-12)
+    # Adam
+    n = 1000
+    rng = np.random.default_rng(17)
+    w, gr = rng.standard_normal(n).astype(np.float32), rng.standard_normal(n).astype(np.float32)
+    tw, tg = to_f32(w), to_f32(gr)
+    tm, tv = torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+    wb = torch.empty(n, dtype=torch.bfloat16, device="cuda")
+    wr, mr, vr = w.astype(np.float64), np.zeros(n), np.zeros(n)
+    for step in (1, 2, 3):
+        tg.copy_(torch.tensor(gr * step))
+        call("lbmx_nn_adam", P(tw), P(tg), P(tm), P(tv), P(wb), n, 1e-2, 0.9, 0.999, 1e-8, step,
+             1e-3, S())
+        wr, mr, vr = N.adam(wr, gr.astype(np.float64) * step, mr, vr, 1e-2, 0.9, 0.999, 1e-8, step, 1e-3)
+    assert np.abs(tw.cpu().numpy() - wr).max() < 1e-6
+    assert np.array_equal(from_bf(wb), N.bf16_round(tw.cpu().numpy()))
+    assert np.abs(tg.cpu().numpy()).max() == 0  # gradient cleared
+    # layout with scale
+    B, K, C, V = 2, 4, 16, 50
+    a = np.random.default_rng(18).standard_normal((B, K, V))
+    sc = np.array([1.0, 2.0, 0.5, 4.0], np.float32)
+    cl = torch.empty((B, V, C), dtype=torch.float32, device="cuda")
+    call("lbmx_nn_layout", P(to_f32(a)), P(cl), B, V, K, C, 1, P(to_f32(sc)), S())
+    ref = np.zeros((B, V, C))
+    ref[..., :K] = np.transpose(a.astype(np.float32), (0, 2, 1)) * sc
+    assert np.abs(cl.cpu().numpy() - ref).max() < 1e-6
+    back = torch.empty((B, K, V), dtype=torch.float32, device="cuda")
+    call("lbmx_nn_layout", P(cl), P(back), B, V, K, C, 0, P(to_f32(1 / sc)), S())
+    assert np.abs(back.cpu().numpy() - a).max() < 1e-6
+    # network input
+    m = 8
+    cond = to_f32(np.array([[0.25, 2.0], [-1.0, 3.0]]))
+    x = torch.empty((2, m, m, m, 16), dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_make_input", P(cond), P(x), 2, m, S())
+    xv = from_bf(x)
+    assert np.all(xv[0, ..., 0] == 0.25) and np.all(xv[1, ..., 0] == -1.0)
+    assert np.all(xv[0, ..., 2] == 1) and np.all(xv[0, ..., 1] == 0) and np.all(xv[1, ..., 3] == 1)
+    c = N.bf16_round((2 * np.arange(m) + 1.0) / m - 1.0)
+    assert np.array_equal(xv[0, 0, 0, :, 4], c) and np.array_equal(xv[1, :, 0, 0, 6], c)
+    assert np.all(xv[..., 7:] == 0)
+
+
+def _oracle_unet_grads(net, cond_np, target, m):
+    """The same network evaluated with the oracle in FP64, rounding to BF16
+    wherever the GPU stores BF16; returns the loss and weight gradients."""
+    from paper_1511_04633_amd.unet import Conv
+
+    r16 = N.bf16_round
+    convs = net.convs()
+    W = {id(c): r16(c.w.cpu().numpy()) for c in convs}
+    Bv = {id(c): c.b.cpu().numpy().astype(np.float64) for c in convs}
+    B = cond_np.shape[0]
+    ax = (2 * np.arange(m) + 1.0) / m - 1.0
+    x = np.zeros((B, m, m, m, 16))
+    for b in range(B):
+        x[b, ..., 0] = cond_np[b, 0]
+        x[b, ..., int(cond_np[b, 1])] = 1.0
+        x[b, ..., 4] = ax[None, None, :]
+        x[b, ..., 5] = ax[None, :, None]
+        x[b, ..., 6] = ax[:, None, None]
+    x = r16(x)
+    tape = []
+
+    def conv_act(c, h):
+        z = r16(N.conv3d(h, W[id(c)], Bv[id(c)]))
+        a = r16(N.silu(z))
+        tape.append(("conv", c, h, z))
+        return a
+
+    h, skips = x, []
+    for lvl, (ca, cb) in enumerate(net.enc):
+        h = conv_act(ca, h)
+        h = conv_act(cb, h)
+        if lvl < 3:
+            skips.append(h)
+            tape.append(("pool", h.shape))
+            h = r16(N.pool2(h))
+    for ca, cb in net.dec:
+        sk = skips.pop()
+        cu = h.shape[-1]
+        h = np.concatenate([N.up2(h), sk], axis=-1)
+        tape.append(("upcat", cu))
+        h = conv_act(ca, h)
+        h = conv_act(cb, h)
+    pred = N.conv3d(h, W[id(net.head)], Bv[id(net.head)]).astype(np.float32).astype(np.float64)
+    loss, g = N.mse(pred.reshape(B, -1, 16), target, 4)
+    g = r16(g.reshape(pred.shape))
+    grads = {}
+    grads[id(net.head)] = N.conv3d_wgrad(h, g)
+    g = r16(N.conv3d_dgrad(g, W[id(net.head)]))
+    sg = []
+    for item in reversed(tape):
+        if item[0] == "conv":
+            _, c, hin, z = item
+            gz = r16(N.silu_bwd(z, g))
+            grads[id(c)] = N.conv3d_wgrad(hin, gz)
+            g = r16(N.conv3d_dgrad(gz, W[id(c)]))
+        elif item[0] == "upcat":
+            cu = item[1]
+            sg.append(g[..., cu:])
+            g = r16(N.up2_bwd(g[..., :cu]))
+        else:
+            g = r16(r16(N.pool2_bwd(g)) + sg.pop())
+    return loss, grads
+
+
+def test_unet_gradients_against_oracle():
+    """End to end: loss and every layer's weight gradient of a small U-Net
+    (16^3 input, batch 2) against the oracle-composed network."""
+    import torch
+    from paper_1511_04633_amd import unet
+
+    print("case: unet gradients 16^3 batch 2", flush=True)
+    m, B = 16, 2
+    net = unet.UNet(seed=3, m=m)
+    cond_np = np.array([[0.3, 1.0], [-0.6, 3.0]])
+    cond = to_f32(cond_np)
+    rng = np.random.default_rng(21)
+    target = rng.standard_normal((B, m ** 3, 4)) * 0.5
+    pred = net.forward(cond, B, train=True)
+    part = torch.zeros(1024, dtype=torch.float64, device="cuda")
+    grad, cnt = unet.mse_loss(pred, to_f32(target), part)
+    net.backward(grad)
+    torch.cuda.synchronize()
+    loss_gpu = part.cpu().numpy().sum() / cnt
+    loss_ref, grads = _oracle_unet_grads(net, cond_np, target.astype(np.float32).astype(np.float64), m)
+    assert abs(loss_gpu - loss_ref) <= 2e-3 * loss_ref
+    for c in net.convs():
+        gw_ref, gb_ref = grads[id(c)]
+        gw = c.gw.cpu().numpy()
+        rel = np.linalg.norm(gw - gw_ref) / np.linalg.norm(gw_ref)
+        cos = (gw * gw_ref).sum() / (np.linalg.norm(gw) * np.linalg.norm(gw_ref))
+        assert rel < 3e-2 and cos > 0.999, (c.ci, c.co, rel, cos)
+        gb = c.gb.cpu().numpy()
+        assert np.linalg.norm(gb - gb_ref) <= 3e-2 * np.linalg.norm(gb_ref) + 1e-9
+
+
+def test_unet_training_reduces_loss():
+    """A few Adam steps on one synthetic sample lower the loss (the training
+    loop runs entirely through the library kernels)."""
+    from paper_1511_04633_amd import unet
+
+    m = 16
+    net = unet.UNet(seed=1, m=m)
+    yy = (np.arange(m) + 0.5) / m
+    th = np.broadcast_to((0.5 - yy)[None, :, None], (m, m, m))
+    fields = np.zeros((4, 4, m, m, m), np.float32)
+    fields[:, 3] = th
+    fields[:, 2] = 0.1 * np.sin(np.pi * yy)[None, :, None]
+    hist = unet.train(net, fields, np.array([3.5, 4.0, 5.0, 5.5]), np.array([1, 2, 3, 1]),
+                      epochs=30, batch=2, lr=3e-3)["loss"]
+    assert hist[-1] < 0.2 * hist[0], hist
