@@ -33,6 +33,9 @@ SYMBOLS = [
     "lbmx_batch_run_to_steady", "lbmx_batch_info", "lbmx_batch_nusselt",
     "lbmx_batch_read_macro", "lbmx_batch_resample", "lbmx_batch_set_launch",
     "lbmx_batch_get_launch", "lbmx_batch_autotune",
+    "lbmx_nn_conv3d_fwd", "lbmx_nn_conv3d_flip", "lbmx_nn_conv3d_wgrad", "lbmx_nn_silu",
+    "lbmx_nn_silu_bwd", "lbmx_nn_pool2", "lbmx_nn_up2", "lbmx_nn_concat", "lbmx_nn_mse",
+    "lbmx_nn_adam", "lbmx_nn_to_bf16", "lbmx_nn_make_input", "lbmx_nn_add", "lbmx_nn_layout",
 ]
 BATCH_STATE = {0: "active", 1: "converged", 2: "max_steps", 3: "diverged"}
 

@@ -76,13 +76,13 @@ def test_conv_forward(shape, ci, co):
     x, w, b = rnd((B, D, H, W, ci), 1), rnd((co, 27, ci), 2, 0.1), rnd((co,), 3)
     ref = N.conv3d(x, w, b)
     bound = 2e-5 * (N.conv3d(np.abs(x), np.abs(w), np.abs(b))) + 1e-6
+    tx, tw, tb = to_bf(x), to_bf(w), to_f32(b)  # keep the device buffers alive
     out = torch.empty((B, D, H, W, co), dtype=torch.float32, device="cuda")
-    call("lbmx_nn_conv3d_fwd", P(to_bf(x)), P(to_bf(w)), P(to_f32(b)), P(out), 1, B, D, H, W, ci,
-         co, S())
-    assert np.all(np.abs(out.cpu().numpy() - ref) <= bound)
+    call("lbmx_nn_conv3d_fwd", P(tx), P(tw), P(tb), P(out), 1, B, D, H, W, ci, co, S())
+    err = np.abs(out.cpu().numpy() - ref)
+    assert np.all(err <= bound), (err.max(), (err / bound).max())
     ob = torch.empty((B, D, H, W, co), dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_conv3d_fwd", P(to_bf(x)), P(to_bf(w)), P(to_f32(b)), P(ob), 0, B, D, H, W, ci,
-         co, S())
+    call("lbmx_nn_conv3d_fwd", P(tx), P(tw), P(tb), P(ob), 0, B, D, H, W, ci, co, S())
     assert np.all(np.abs(from_bf(ob) - ref) <= 2 ** -8 * np.abs(ref) + bound)
 
 
@@ -95,11 +95,13 @@ def test_conv_data_gradient(shape, ci, co):
     g, w = rnd((B, D, H, W, co), 4), rnd((co, 27, ci), 5, 0.1)
     ref = N.conv3d_dgrad(g, w)
     bound = 2e-5 * N.conv3d_dgrad(np.abs(g), np.abs(w)) + 1e-6
+    tw, tg = to_bf(w), to_bf(g)
     wt = torch.empty((ci, 27, co), dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_conv3d_flip", P(to_bf(w)), P(wt), ci, co, S())
+    call("lbmx_nn_conv3d_flip", P(tw), P(wt), ci, co, S())
     out = torch.empty((B, D, H, W, ci), dtype=torch.float32, device="cuda")
-    call("lbmx_nn_conv3d_fwd", P(to_bf(g)), P(wt), None, P(out), 1, B, D, H, W, co, ci, S())
-    assert np.all(np.abs(out.cpu().numpy() - ref) <= bound)
+    call("lbmx_nn_conv3d_fwd", P(tg), P(wt), None, P(out), 1, B, D, H, W, co, ci, S())
+    err = np.abs(out.cpu().numpy() - ref)
+    assert np.all(err <= bound), (err.max(), (err / bound).max())
 
 
 @pytest.mark.parametrize("shape", SHAPES + [(2, 16, 16, 16)])
@@ -113,8 +115,10 @@ def test_conv_weight_gradient(shape, ci, co):
     bw, bb = N.conv3d_wgrad(np.abs(x), np.abs(g))
     gw = torch.full((co, 27, ci), 0.5, dtype=torch.float32, device="cuda")  # accumulates
     gb = torch.full((co,), -0.25, dtype=torch.float32, device="cuda")
-    call("lbmx_nn_conv3d_wgrad", P(to_bf(x)), P(to_bf(g)), P(gw), P(gb), B, D, H, W, ci, co, S())
-    assert np.all(np.abs(gw.cpu().numpy() - 0.5 - gw_ref) <= 2e-5 * bw + 1e-5)
+    tx, tg = to_bf(x), to_bf(g)
+    call("lbmx_nn_conv3d_wgrad", P(tx), P(tg), P(gw), P(gb), B, D, H, W, ci, co, S())
+    err = np.abs(gw.cpu().numpy() - 0.5 - gw_ref)
+    assert np.all(err <= 2e-5 * bw + 1e-5), (err.max(), (err / (2e-5 * bw + 1e-5)).max())
     assert np.all(np.abs(gb.cpu().numpy() + 0.25 - gb_ref) <= 2e-5 * bb + 1e-5)
 
 
@@ -123,19 +127,22 @@ def test_pool_upsample_concat():
     B, D, H, W, C = 2, 4, 6, 8, 32
     x = rnd((B, D, H, W, C), 8)
     p = torch.empty((B, D // 2, H // 2, W // 2, C), dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_pool2", P(to_bf(x)), P(p), B, D, H, W, C, 0, S())
+    tx = to_bf(x)
+    call("lbmx_nn_pool2", P(tx), P(p), B, D, H, W, C, 0, S())
     ref = N.pool2(x)
     assert np.all(np.abs(from_bf(p) - ref) <= 2 ** -8 * np.abs(ref) + 1e-7)
     gy = rnd((B, D // 2, H // 2, W // 2, C), 9)
     gx = torch.empty((B, D, H, W, C), dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_pool2", P(to_bf(gy)), P(gx), B, D, H, W, C, 1, S())
+    tgy = to_bf(gy)
+    call("lbmx_nn_pool2", P(tgy), P(gx), B, D, H, W, C, 1, S())
     assert np.array_equal(from_bf(gx), N.pool2_bwd(gy))  # division by 8 is exact
     u = torch.empty((B, 2 * D, 2 * H, 2 * W, C), dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_up2", P(to_bf(x)), P(u), B, D, H, W, C, 0, S())
+    call("lbmx_nn_up2", P(tx), P(u), B, D, H, W, C, 0, S())
     assert np.array_equal(from_bf(u), N.up2(x))
     gu = rnd((B, 2 * D, 2 * H, 2 * W, C), 10)
     gd = torch.empty((B, D, H, W, C), dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_up2", P(to_bf(gu)), P(gd), B, D, H, W, C, 1, S())
+    tgu = to_bf(gu)
+    call("lbmx_nn_up2", P(tgu), P(gd), B, D, H, W, C, 1, S())
     ref = N.up2_bwd(gu)
     assert np.all(np.abs(from_bf(gd) - ref) <= 2 ** -8 * np.abs(ref) + 1e-6)
     a, b = rnd((B, D, H, W, 16), 11), rnd((B, D, H, W, 32), 12)
@@ -153,15 +160,16 @@ def test_silu_add_mse_adam_layout_input():
     import torch
     z, ga = rnd((5000,), 13, 3.0), rnd((5000,), 14)
     a = torch.empty(5000, dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_silu", P(to_bf(z)), P(a), 5000, S())
+    tz, tga = to_bf(z), to_bf(ga)
+    call("lbmx_nn_silu", P(tz), P(a), 5000, S())
     ref = N.silu(z)
     assert np.all(np.abs(from_bf(a) - ref) <= 2 ** -8 * np.abs(ref) + 1e-6)
     gz = torch.empty(5000, dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_silu_bwd", P(to_bf(z)), P(to_bf(ga)), P(gz), 5000, S())
+    call("lbmx_nn_silu_bwd", P(tz), P(tga), P(gz), 5000, S())
     ref = N.silu_bwd(z, ga)
     assert np.all(np.abs(from_bf(gz) - ref) <= 2 ** -8 * np.abs(ref) + 1e-5)
     s = torch.empty(5000, dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_add", P(to_bf(z)), P(to_bf(ga)), P(s), 5000, S())
+    call("lbmx_nn_add", P(tz), P(tga), P(s), 5000, S())
     ref = z + ga
     assert np.all(np.abs(from_bf(s) - ref) <= 2 ** -8 * np.abs(ref) + 1e-7)
     # squared error
@@ -169,7 +177,8 @@ def test_silu_add_mse_adam_layout_input():
     pred, tgt = np.random.default_rng(15).standard_normal((V, 16)), np.random.default_rng(16).standard_normal((V, 4))
     grad = torch.empty((V, 16), dtype=torch.bfloat16, device="cuda")
     part = torch.zeros(64, dtype=torch.float64, device="cuda")
-    call("lbmx_nn_mse", P(to_f32(pred)), P(to_f32(tgt)), P(grad), P(part), 64, V, 16, 4, S())
+    tp, tt = to_f32(pred), to_f32(tgt)
+    call("lbmx_nn_mse", P(tp), P(tt), P(grad), P(part), 64, V, 16, 4, S())
     p32, t32 = pred.astype(np.float32).astype(np.float64), tgt.astype(np.float32).astype(np.float64)
     loss, g = N.mse(p32, t32, 4)
     assert abs(part.cpu().numpy().sum() / (V * 4) - loss) <= 1e-6 * loss
@@ -195,12 +204,13 @@ def test_silu_add_mse_adam_layout_input():
     a = np.random.default_rng(18).standard_normal((B, K, V))
     sc = np.array([1.0, 2.0, 0.5, 4.0], np.float32)
     cl = torch.empty((B, V, C), dtype=torch.float32, device="cuda")
-    call("lbmx_nn_layout", P(to_f32(a)), P(cl), B, V, K, C, 1, P(to_f32(sc)), S())
+    ta, tsc, tinv = to_f32(a), to_f32(sc), to_f32(1 / sc)
+    call("lbmx_nn_layout", P(ta), P(cl), B, V, K, C, 1, P(tsc), S())
     ref = np.zeros((B, V, C))
     ref[..., :K] = np.transpose(a.astype(np.float32), (0, 2, 1)) * sc
     assert np.abs(cl.cpu().numpy() - ref).max() < 1e-6
     back = torch.empty((B, K, V), dtype=torch.float32, device="cuda")
-    call("lbmx_nn_layout", P(cl), P(back), B, V, K, C, 0, P(to_f32(1 / sc)), S())
+    call("lbmx_nn_layout", P(cl), P(back), B, V, K, C, 0, P(tinv), S())
     assert np.abs(back.cpu().numpy() - a).max() < 1e-6
     # network input
     m = 8
@@ -294,7 +304,8 @@ def test_unet_gradients_against_oracle():
     target = rng.standard_normal((B, m ** 3, 4)) * 0.5
     pred = net.forward(cond, B, train=True)
     part = torch.zeros(1024, dtype=torch.float64, device="cuda")
-    grad, cnt = unet.mse_loss(pred, to_f32(target), part)
+    ttarget = to_f32(target)
+    grad, cnt = unet.mse_loss(pred, ttarget, part)
     net.backward(grad)
     torch.cuda.synchronize()
     loss_gpu = part.cpu().numpy().sum() / cnt
