@@ -288,10 +288,13 @@ def mse_loss(pred, target_cl, partial, K=NOUT):
     return grad, nv * K
 
 
-def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=2e-3, seed=0, log=None):
+def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=1e-3, seed=0, log=None,
+          warmup=None):
     """Fit the network to steady fields [N, 4, m, m, m] (channel-first FP32;
     velocities already divided by u_c).  Per-channel target scales are the
-    fields' standard deviations; the learning rate follows a cosine decay."""
+    fields' standard deviations; the learning rate rises linearly over
+    `warmup` steps (default 5 % of the run, at least 10) and then follows a
+    cosine decay."""
     import time
 
     import torch
@@ -311,6 +314,8 @@ def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=2e-3, seed=0
     partials = torch.zeros((per_epoch, 1024), dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(seed)
     nsteps = epochs * per_epoch
+    if warmup is None:
+        warmup = max(10, nsteps // 20)
     hist = []
     t0 = time.perf_counter()
     step = 0
@@ -326,7 +331,10 @@ def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=2e-3, seed=0
             pred = net.forward(cond, batch, train=True)
             grad, cnt = mse_loss(pred, target, partials[k])
             net.backward(grad)
-            lr_t = lr * 0.5 * (1 + math.cos(math.pi * step / max(nsteps, 1)))
+            if step < warmup:
+                lr_t = lr * (step + 1) / warmup
+            else:
+                lr_t = lr * 0.5 * (1 + math.cos(math.pi * (step - warmup) / max(nsteps - warmup, 1)))
             net.adam(lr_t)
             step += 1
         hist.append(float(partials.cpu().numpy().sum()) / (cnt * per_epoch))
@@ -336,12 +344,17 @@ def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=2e-3, seed=0
     return {"loss": hist, "seconds": time.perf_counter() - t0, "steps": step}
 
 
-def predict_fields(net, log10_ra, wall_type):
-    """Predicted u/u_c, v/u_c, w/u_c, theta on the m^3 grid: device FP32 [4, m^3]."""
+def predict_fields(net, log10_ra, wall_type, u_c=1.0):
+    """Predicted fields on the m^3 grid, device FP32 [4, m^3]: u, v, w
+    multiplied by u_c (u_c = 1 gives u/u_c; the cavity's u_c gives lattice
+    units) and theta."""
     import torch
     m = net.m
     cond = cond_tensor([log10_ra], [wall_type])
     pred = net.forward(cond, 1)
+    sc = torch.tensor(net.scale.cpu().numpy() * np.array([u_c, u_c, u_c, 1.0], np.float32),
+                      device="cuda")
     out = torch.empty((NOUT, m ** 3), dtype=torch.float32, device="cuda")
-    call("lbmx_nn_layout", P(pred), P(out), 1, m ** 3, NOUT, 16, 0, P(net.scale), stream_ptr())
+    call("lbmx_nn_layout", P(pred), P(out), 1, m ** 3, NOUT, 16, 0, P(sc), stream_ptr())
+    torch.cuda.current_stream().synchronize()
     return out

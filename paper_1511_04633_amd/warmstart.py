@@ -1,0 +1,125 @@
+"""Learned warm start: train the U-Net on the batched solver's steady fields,
+then solve 192^3 cavities from the network's prediction (trilinearly
+upsampled from 64^3 inside ``lbmx_init_fields``) and from rest, and compare
+steps, wall time (inference and initialisation included) and the steady
+Nusselt numbers.
+
+CLI:
+  python -m paper_1511_04633_amd.warmstart train --out weights.npz [--epochs 300]
+      generates the 64-cavity training set with the batched solver, trains,
+      saves the weights and prints the loss history summary;
+  python -m paper_1511_04633_amd.warmstart eval --weights weights.npz
+      [--ra 2e4,3e5,8e5] [--types 1,2,3] [--n 192]
+      prints one JSON line per case.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import sys
+import time
+
+import numpy as np
+
+from . import dataset, inputs, lbmx, unet
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def train_main(a):
+    t0 = time.perf_counter()
+    ds = dataset.generate(seed=a.seed, count=a.count, out_n=64, max_steps=a.max_steps,
+                          tune_cache=a.tune_cache, log=log)
+    t_data = time.perf_counter() - t0
+    log(f"dataset: {ds['summary']}")
+    net = unet.UNet(seed=a.net_seed, m=64)
+    log(f"U-Net parameters: {net.nparams()}")
+    res = unet.train(net, ds["fields"], ds["log10_ra"], ds["wall_type"], epochs=a.epochs,
+                     batch=a.batch, lr=a.lr, log=log)
+    st = net.state()
+    st["log10_ra"] = ds["log10_ra"]
+    st["wall_type"] = ds["wall_type"]
+    st["loss"] = np.array(res["loss"])
+    np.savez_compressed(a.out, **st)
+    print(json.dumps({"dataset_s": round(t_data, 2), "dataset": ds["summary"],
+                      "params": net.nparams(), "epochs": a.epochs, "batch": a.batch,
+                      "train_s": round(res["seconds"], 2), "steps": res["steps"],
+                      "loss_first": res["loss"][0], "loss_last": res["loss"][-1]}), flush=True)
+
+
+def load_net(path):
+    net = unet.UNet(seed=0, m=64)
+    z = np.load(path, allow_pickle=False)
+    net.load_state({k: z[k] for k in z.files})
+    return net
+
+
+def solve(n, ra, wt, net=None, tol=1e-6, every=1000, max_steps=400_000):
+    """Run one cavity to steady from rest (net None) or from the network's fields."""
+    import torch
+
+    cav = lbmx.Cavity(n=n, wall_type=wt, ra=ra, storage="f32",
+                      theta0=inputs.theta_noise(n, 20151115))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    t_init = 0.0
+    if net is not None:
+        u_c = cav.derived()["u_c"]
+        f = unet.predict_fields(net, np.log10(ra), wt, u_c=u_c)
+        m = net.m
+        fv = f.view(4, m, m, m)
+        cav.init_fields(fv[0], fv[1], fv[2], fv[3])
+        torch.cuda.synchronize()
+        t_init = time.perf_counter() - t0
+    r = cav.run_to_steady(tol=tol, every=every, max_steps=max_steps)
+    dt = time.perf_counter() - t0
+    out = {"steps": r["step"], "seconds": round(dt, 3), "init_s": round(t_init, 4),
+           "converged": r["converged"], "nu3d": r["nu3d"], "nu2d": r["nu2d"], "numax": r["numax"]}
+    cav.close()
+    return out
+
+
+def eval_main(a):
+    net = load_net(a.weights)
+    for ra in [float(v) for v in a.ra.split(",")]:
+        for wt in [int(v) for v in a.types.split(",")]:
+            log(f"case n={a.n} Ra={ra:g} type={wt}")
+            rest = solve(a.n, ra, wt, None, max_steps=a.max_steps)
+            warm = solve(a.n, ra, wt, net, max_steps=a.max_steps)
+            line = {"n": a.n, "ra": ra, "wall_type": wt, "rest": rest, "warm": warm,
+                    "step_ratio": warm["steps"] / max(rest["steps"], 1),
+                    "time_ratio": warm["seconds"] / rest["seconds"],
+                    "nu_rel_diff": abs(warm["nu3d"] - rest["nu3d"]) / rest["nu3d"]}
+            print(json.dumps(line), flush=True)
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--out", required=True)
+    t.add_argument("--epochs", type=int, default=300)
+    t.add_argument("--batch", type=int, default=4)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--count", type=int, default=64)
+    t.add_argument("--seed", type=int, default=1511)
+    t.add_argument("--net-seed", type=int, default=0)
+    t.add_argument("--max-steps", type=int, default=300_000)
+    t.add_argument("--tune-cache", default=None)
+    e = sub.add_parser("eval")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--ra", default="2e4,3e5,8e5")
+    e.add_argument("--types", default="1,2,3")
+    e.add_argument("--n", type=int, default=192)
+    e.add_argument("--max-steps", type=int, default=400_000)
+    a = ap.parse_args(argv)
+    if a.cmd == "train":
+        train_main(a)
+    else:
+        eval_main(a)
+
+
+if __name__ == "__main__":
+    main()
