@@ -56,8 +56,11 @@ def load_net(path):
     return net
 
 
-def solve(n, ra, wt, net=None, tol=1e-6, every=1000, max_steps=400_000):
-    """Run one cavity to steady from rest (net None) or from the network's fields."""
+def solve(n, ra, wt, net=None, tol=1e-6, every=1000, max_steps=400_000, history=False):
+    """Run one cavity to steady from rest (net None) or from the network's
+    fields.  With history, step in chunks of `every` from Python (same
+    criterion as lbmx_run_to_steady) and also report the first step after
+    which Nu_3D stays within 1e-3 of its final value."""
     import torch
 
     cav = lbmx.Cavity(n=n, wall_type=wt, ra=ra, storage="f32",
@@ -73,10 +76,34 @@ def solve(n, ra, wt, net=None, tol=1e-6, every=1000, max_steps=400_000):
         cav.init_fields(fv[0], fv[1], fv[2], fv[3])
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t0
-    r = cav.run_to_steady(tol=tol, every=every, max_steps=max_steps)
+    hist = None
+    if history:
+        nu = cav.nusselt()
+        hist = [(0, nu["nu3d"])]
+        prev, conv = nu["nu3d"], False
+        while cav.t < max_steps:
+            cav.step(every)
+            nu = cav.nusselt()
+            hist.append((cav.t, nu["nu3d"]))
+            if abs(nu["nu3d"] - prev) < tol:
+                conv = True
+                break
+            prev = nu["nu3d"]
+        r = dict(nu, converged=conv)
+    else:
+        r = cav.run_to_steady(tol=tol, every=every, max_steps=max_steps)
     dt = time.perf_counter() - t0
     out = {"steps": r["step"], "seconds": round(dt, 3), "init_s": round(t_init, 4),
            "converged": r["converged"], "nu3d": r["nu3d"], "nu2d": r["nu2d"], "numax": r["numax"]}
+    if hist is not None:
+        final = hist[-1][1]
+        within = 0
+        for k in range(len(hist) - 1, -1, -1):
+            if abs(hist[k][1] - final) > 1e-3 * abs(final):
+                within = hist[min(k + 1, len(hist) - 1)][0]
+                break
+        out["steps_within_1e-3"] = within
+        out["nu_history"] = [[t, round(v, 7)] for t, v in hist[::5]]
     cav.close()
     return out
 
@@ -86,8 +113,8 @@ def eval_main(a):
     for ra in [float(v) for v in a.ra.split(",")]:
         for wt in [int(v) for v in a.types.split(",")]:
             log(f"case n={a.n} Ra={ra:g} type={wt}")
-            rest = solve(a.n, ra, wt, None, max_steps=a.max_steps)
-            warm = solve(a.n, ra, wt, net, max_steps=a.max_steps)
+            rest = solve(a.n, ra, wt, None, max_steps=a.max_steps, history=a.history)
+            warm = solve(a.n, ra, wt, net, max_steps=a.max_steps, history=a.history)
             line = {"n": a.n, "ra": ra, "wall_type": wt, "rest": rest, "warm": warm,
                     "step_ratio": warm["steps"] / max(rest["steps"], 1),
                     "time_ratio": warm["seconds"] / rest["seconds"],
@@ -114,6 +141,8 @@ def main(argv=None):
     e.add_argument("--types", default="1,2,3")
     e.add_argument("--n", type=int, default=192)
     e.add_argument("--max-steps", type=int, default=400_000)
+    e.add_argument("--history", action="store_true",
+                   help="log Nu every 1000 steps and report steps to within 1e-3 of the final Nu")
     a = ap.parse_args(argv)
     if a.cmd == "train":
         train_main(a)
