@@ -37,31 +37,32 @@ namespace lbmx {
 // as offsets df = f - w_i, energy populations as g; the 16-bit formats store
 // df / w_i and g / w_T,i (the population relative to its weight), which keeps
 // every direction's stored value O(u) or O(theta).  `Raw` is the bit
-// container for non-temporal stores; `inv_w` is the exact reciprocal of the
-// weight (3, 18, 36; 4, 8), so encoding multiplies instead of dividing.
+// container: loads return it and dec() reinterprets its bits; `inv_w` is the
+// exact reciprocal of the weight (3, 18, 36; 4, 8), so encoding multiplies
+// instead of dividing.
 template <typename S>
 struct Codec;
 
 template <>
 struct Codec<double> {
     using Raw = double;
-    template <typename T> static __device__ __forceinline__ T dec(double v, T) { return T(v); }
+    template <typename T> static __device__ __forceinline__ T dec(Raw v, T) { return T(v); }
     template <typename T> static __device__ __forceinline__ Raw enc(T v, T) { return double(v); }
 };
 
 template <>
 struct Codec<float> {
     using Raw = float;
-    template <typename T> static __device__ __forceinline__ T dec(float v, T) { return T(v); }
+    template <typename T> static __device__ __forceinline__ T dec(Raw v, T) { return T(v); }
     template <typename T> static __device__ __forceinline__ Raw enc(T v, T) { return float(v); }
 };
 
 template <>
 struct Codec<__half> {
     using Raw = unsigned short;
-    template <typename T> static __device__ __forceinline__ T dec(__half v, T w)
+    template <typename T> static __device__ __forceinline__ T dec(Raw v, T w)
     {
-        return T(__half2float(v)) * w;
+        return T(__half2float(__ushort_as_half(v))) * w;
     }
     template <typename T> static __device__ __forceinline__ Raw enc(T v, T inv_w)
     {
@@ -72,9 +73,9 @@ struct Codec<__half> {
 template <>
 struct Codec<__hip_bfloat16> {
     using Raw = unsigned short;
-    template <typename T> static __device__ __forceinline__ T dec(__hip_bfloat16 v, T w)
+    template <typename T> static __device__ __forceinline__ T dec(Raw v, T w)
     {
-        return T(__bfloat162float(v)) * w;
+        return T(__bfloat162float(__ushort_as_bfloat16(v))) * w;
     }
     template <typename T> static __device__ __forceinline__ Raw enc(T v, T inv_w)
     {

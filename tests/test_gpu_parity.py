@@ -194,3 +194,33 @@ def test_invalid_parameters_raise():
         c.step(-1)
     with pytest.raises(L.LbmxError):
         c.set_launch(2048, 1)
+
+
+@pytest.mark.parametrize("storage,flow_eps,energy_eps", [
+    ("f32", 2 ** -24, 2 ** -24), ("f16", 2 ** -11, 2 ** -11), ("bf16", 2 ** -8, 2 ** -8),
+    ("f16_f32", 2 ** -11, 2 ** -24), ("bf16_f32", 2 ** -8, 2 ** -24)])
+def test_storage_codec_round_trip(storage, flow_eps, energy_eps):
+    """Populations written and read back through a storage format differ from
+    the input by at most half an ulp of the stored value: (f_i - w_i)/w_i for
+    the 16-bit flow planes, g_i/w_T,i for the 16-bit energy planes."""
+    print(f"case: codec round trip {storage}", flush=True)
+    n = 10
+    ora = O.Oracle(n, 3, ra=1e5, theta0=inputs.theta_noise(n, SEED, amp=1e-2))
+    ora.step(300)
+    f, g = ora.get_state()
+    e19, w19, e7, w7 = O.velocities()
+    c = L.Cavity(n=n, wall_type=3, ra=1e5, storage=storage)
+    c.set_populations(f, g, t=300)
+    fr, gr = c.get_populations()
+    wf, wg = w19[:, None], w7[:, None]
+    if storage == "f32":
+        assert np.abs(fr - f).max() <= 4 * flow_eps * np.abs(f - wf).max() + 1e-16
+        assert np.abs(gr - g).max() <= 4 * energy_eps * np.abs(g).max()
+        return
+    sf = np.abs((f - wf) / wf)
+    assert np.all(np.abs(fr - f) / wf <= flow_eps * sf * 1.0001 + 1e-12)
+    sg = np.abs(g / wg)
+    assert np.all(np.abs(gr - g) / wg <= energy_eps * sg * 1.0001 + 1e-12)
+    # and the stored state is a usable cavity: one step keeps everything finite
+    c.step(1)
+    assert all(np.isfinite(a).all() for a in c.read_macro())
