@@ -196,31 +196,34 @@ def test_invalid_parameters_raise():
         c.set_launch(2048, 1)
 
 
-@pytest.mark.parametrize("storage,flow_eps,energy_eps", [
-    ("f32", 2 ** -24, 2 ** -24), ("f16", 2 ** -11, 2 ** -11), ("bf16", 2 ** -8, 2 ** -8),
-    ("f16_f32", 2 ** -11, 2 ** -24), ("bf16_f32", 2 ** -8, 2 ** -24)])
-def test_storage_codec_round_trip(storage, flow_eps, energy_eps):
+@pytest.mark.parametrize("storage,flow_fmt,energy_fmt", [
+    ("f32", "f32", "f32"), ("f16", "f16", "f16"), ("bf16", "bf16", "bf16"),
+    ("f16_f32", "f16", "f32"), ("bf16_f32", "bf16", "f32")])
+def test_storage_codec_round_trip(storage, flow_fmt, energy_fmt):
     """Populations written and read back through a storage format differ from
-    the input by at most half an ulp of the stored value: (f_i - w_i)/w_i for
-    the 16-bit flow planes, g_i/w_T,i for the 16-bit energy planes."""
+    the input by at most half an ulp of the stored value ((f_i - w_i)/w_i for
+    16-bit flow planes, g_i/w_T,i for 16-bit energy planes, f_i - w_i and g_i
+    for FP32), the value first being rounded to FP32 (factor 1.001), with the
+    FP16 subnormal spacing 2^-24 as the floor."""
     print(f"case: codec round trip {storage}", flush=True)
+    eps = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8}
+    floor = {"f32": 1e-45, "f16": 2.0 ** -25, "bf16": 1e-38}
     n = 10
     ora = O.Oracle(n, 3, ra=1e5, theta0=inputs.theta_noise(n, SEED, amp=1e-2))
     ora.step(300)
     f, g = ora.get_state()
-    e19, w19, e7, w7 = O.velocities()
+    _, w19, _, w7 = O.velocities()
     c = L.Cavity(n=n, wall_type=3, ra=1e5, storage=storage)
     c.set_populations(f, g, t=300)
     fr, gr = c.get_populations()
     wf, wg = w19[:, None], w7[:, None]
-    if storage == "f32":
-        assert np.abs(fr - f).max() <= 4 * flow_eps * np.abs(f - wf).max() + 1e-16
-        assert np.abs(gr - g).max() <= 4 * energy_eps * np.abs(g).max()
-        return
-    sf = np.abs((f - wf) / wf)
-    assert np.all(np.abs(fr - f) / wf <= flow_eps * sf * 1.0001 + 1e-12)
-    sg = np.abs(g / wg)
-    assert np.all(np.abs(gr - g) / wg <= energy_eps * sg * 1.0001 + 1e-12)
+    # stored quantity and its scale back to population units
+    sf, kf = ((f - wf) / wf, wf) if flow_fmt != "f32" else (f - wf, 1.0)
+    sg, kg = (g / wg, wg) if energy_fmt != "f32" else (g, 1.0)
+    bf = (eps[flow_fmt] * np.abs(sf) * 1.001 + floor[flow_fmt]) * kf + 1e-16
+    bg = (eps[energy_fmt] * np.abs(sg) * 1.001 + floor[energy_fmt]) * kg + 1e-17
+    assert np.all(np.abs(fr - f) <= bf), (np.abs(fr - f) / bf).max()
+    assert np.all(np.abs(gr - g) <= bg), (np.abs(gr - g) / bg).max()
     # and the stored state is a usable cavity: one step keeps everything finite
     c.step(1)
     assert all(np.isfinite(a).all() for a in c.read_macro())
