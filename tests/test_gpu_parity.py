@@ -221,7 +221,7 @@ def test_storage_codec_round_trip(storage, flow_fmt, energy_fmt):
     sf, kf = ((f - wf) / wf, wf) if flow_fmt != "f32" else (f - wf, 1.0)
     sg, kg = (g / wg, wg) if energy_fmt != "f32" else (g, 1.0)
     bf = (eps[flow_fmt] * np.abs(sf) * 1.001 + floor[flow_fmt]) * kf + 1e-16
-    bg = (eps[energy_fmt] * np.abs(sg) * 1.001 + floor[energy_fmt]) * kg + 1e-17
+    bg = (eps[energy_fmt] * np.abs(sg) * 1.001 + floor[energy_fmt]) * kg + 2.0 ** -22 * 0.125
     assert np.all(np.abs(fr - f) <= bf), (np.abs(fr - f) / bf).max()
     assert np.all(np.abs(gr - g) <= bg), (np.abs(gr - g) / bg).max()
     # and the stored state is a usable cavity: one step keeps everything finite
