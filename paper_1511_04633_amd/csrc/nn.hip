@@ -21,7 +21,8 @@
 // with the flipped, transposed weights (W'[ci][26-tap][co] = W[co][tap][ci]);
 // the weight gradient is a GEMM over voxels (K = voxels), staged through LDS
 // transposed to [channel][voxel] so that every MFMA operand is one 8-byte
-// LDS read, accumulated in FP32 and added to the global gradient atomically.
+// LDS read, accumulated in FP32 and added to the global gradient atomically
+// (the bias gradient rides along in the centre-tap blocks).
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
@@ -129,52 +130,82 @@ __global__ __launch_bounds__(256) void k_conv_flip(const bf *__restrict__ w, bf 
 
 // gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci].  grid.y = tap;
 // block x covers the voxel range [bx*per, (bx+1)*per) in sub-chunks of 64.
+// Per sub-chunk the 64 voxels' neighbours at this tap are decoded once into
+// LDS, then gout and the shifted input are staged transposed ([channel][voxel])
+// with 8-byte loads; each wavefront then runs its (co tile, ci tile) MFMAs.
+// The centre-tap blocks also accumulate the bias gradient sum_p gout[p][co].
+// Voxel and element indices are 32-bit (the host checks B D H W C < 2^31).
 constexpr int WG_VOX = 64;
 constexpr int WG_SLOTS = 16;  // (co tile, ci tile) pairs per wavefront
 
 __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, const bf *__restrict__ gout,
-                                                    float *__restrict__ gw, Dims d, long long per)
+                                                    float *__restrict__ gw, float *__restrict__ gb, Dims d,
+                                                    int per)
 {
     extern __shared__ bf lds[];
     const int tap = blockIdx.y;
     const int Ci = d.Ci, Co = d.Co;
-    bf *gT = lds;                     // [Co][64]
-    bf *iT = lds + Co * WG_VOX;       // [Ci][64]
+    bf *gT = lds;                                   // [Co][64]
+    bf *iT = lds + Co * WG_VOX;                     // [Ci][64]
+    int *nb = reinterpret_cast<int *>(lds + (Ci + Co) * WG_VOX);  // [64] neighbour voxel or -1
+    int *pv = nb + WG_VOX;                                         // [64] voxel or -1
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int COT = Co / 16, CIT = Ci / 16, npair = COT * CIT;
     const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-    const long long nv = nvox_of(d);
-    const long long vb = (long long)blockIdx.x * per;
-    const long long ve = vb + per < nv ? vb + per : nv;
+    const int nv = d.B * d.D * d.H * d.W;
+    const int vb = blockIdx.x * per;
+    const int ve = min(vb + per, nv);
+    const bool do_bias = gb != nullptr && tap == 13;
+    const int cq_o = Co / 4, cq_i = Ci / 4;        // 4-channel groups
+    float bsum = 0.f;
     f4 acc[WG_SLOTS];
 #pragma unroll
     for (int s = 0; s < WG_SLOTS; ++s)
         acc[s] = f4{0.f, 0.f, 0.f, 0.f};
-    for (long long v0 = vb; v0 < ve; v0 += WG_VOX) {
+    for (int v0 = vb; v0 < ve; v0 += WG_VOX) {
         __syncthreads();
-        for (int i = threadIdx.x; i < WG_VOX * Co; i += blockDim.x) {
-            const int vo = i / Co, c = i % Co;
-            const long long p = v0 + vo;
-            gT[c * WG_VOX + vo] = p < ve ? gout[p * Co + c] : bf(0);
-        }
-        for (int i = threadIdx.x; i < WG_VOX * Ci; i += blockDim.x) {
-            const int vo = i / Ci, c = i % Ci;
-            const long long p = v0 + vo;
-            bf v = 0;
+        if (threadIdx.x < WG_VOX) {
+            const int p = v0 + threadIdx.x;
+            int q = -1;
             if (p < ve) {
-                long long r = p;
-                const int x = int(r % d.W); r /= d.W;
-                const int y = int(r % d.H); r /= d.H;
-                const int z = int(r % d.D);
-                const int b = int(r / d.D);
+                int r = p;
+                const int x = r % d.W; r /= d.W;
+                const int y = r % d.H; r /= d.H;
+                const int z = r % d.D;
+                const int b = r / d.D;
                 const int xs = x + dx, ys = y + dy, zs = z + dz;
                 if (xs >= 0 && xs < d.W && ys >= 0 && ys < d.H && zs >= 0 && zs < d.D)
-                    v = in[((((long long)b * d.D + zs) * d.H + ys) * d.W + xs) * Ci + c];
+                    q = ((b * d.D + zs) * d.H + ys) * d.W + xs;
             }
-            iT[c * WG_VOX + vo] = v;
+            nb[threadIdx.x] = q;
+            pv[threadIdx.x] = p < ve ? p : -1;
         }
         __syncthreads();
+        for (int i = threadIdx.x; i < WG_VOX * cq_o; i += blockDim.x) {
+            const int vo = i / cq_o, c = (i - vo * cq_o) * 4;
+            const int p = pv[vo];
+            s4 v = s4{0, 0, 0, 0};
+            if (p >= 0)
+                v = *reinterpret_cast<const s4 *>(gout + p * Co + c);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                gT[(c + k) * WG_VOX + vo] = bf(v[k]);
+        }
+        for (int i = threadIdx.x; i < WG_VOX * cq_i; i += blockDim.x) {
+            const int vo = i / cq_i, c = (i - vo * cq_i) * 4;
+            const int q = nb[vo];
+            s4 v = s4{0, 0, 0, 0};
+            if (q >= 0)
+                v = *reinterpret_cast<const s4 *>(in + q * Ci + c);
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+                iT[(c + k) * WG_VOX + vo] = bf(v[k]);
+        }
+        __syncthreads();
+        if (do_bias && threadIdx.x < Co)
+            for (int vo = 0; vo < WG_VOX; ++vo)
+                bsum += bf2f(gT[threadIdx.x * WG_VOX + vo]);
 #pragma unroll
         for (int s = 0; s < WG_SLOTS; ++s) {
             const int pr = wv + 4 * s;
@@ -197,24 +228,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int co = ct * 16 + kq * 4 + r, ci = it * 16 + col;
-                atomicAdd(&gw[((long long)co * 27 + tap) * Ci + ci], acc[s][r]);
+                atomicAdd(&gw[(co * 27 + tap) * Ci + ci], acc[s][r]);
             }
         }
     }
-}
-
-// gb[co] += sum_p gout[p][co]
-__global__ __launch_bounds__(256) void k_bias_grad(const bf *__restrict__ gout, float *__restrict__ gb,
-                                                   long long nv, int Co)
-{
-    const int ng = blockDim.x / Co;
-    const int g = threadIdx.x / Co, co = threadIdx.x % Co;
-    if (g >= ng)
-        return;
-    float s = 0.f;
-    for (long long p = (long long)blockIdx.x * ng + g; p < nv; p += (long long)gridDim.x * ng)
-        s += bf2f(gout[p * Co + co]);
-    atomicAdd(&gb[co], s);
+    if (do_bias && threadIdx.x < Co)
+        atomicAdd(&gb[threadIdx.x], bsum);
 }
 
 // ------------------------------------------------------------ elementwise
@@ -558,16 +577,16 @@ lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, fl
                     4 * WG_SLOTS);
     const Dims d{B, D, H, W, Ci, Co};
     const long long nv = (long long)B * D * H * W;
-    long long chunks = (nv + WG_VOX - 1) / WG_VOX;
+    if (nv * (Ci > Co ? Ci : Co) >= (1LL << 31))
+        return fail(LBMX_EINVAL, "conv3d_wgrad: tensor of %lld voxels too large", nv);
+    const long long chunks = (nv + WG_VOX - 1) / WG_VOX;
     long long gx = chunks < 96 ? chunks : 96;
-    long long per = ((chunks + gx - 1) / gx) * WG_VOX;
+    const long long per = ((chunks + gx - 1) / gx) * WG_VOX;
     gx = (nv + per - 1) / per;
-    const size_t lds = size_t(Ci + Co) * WG_VOX * sizeof(bf);
+    const size_t lds = size_t(Ci + Co) * WG_VOX * sizeof(bf) + 2 * WG_VOX * sizeof(int);
     hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned(gx), 27), dim3(256), lds, S(stream),
-                       reinterpret_cast<const bf *>(in), reinterpret_cast<const bf *>(gout), gw, d, per);
-    if (gb)
-        hipLaunchKernelGGL(k_bias_grad, dim3(512), dim3(256), 0, S(stream),
-                           reinterpret_cast<const bf *>(gout), gb, nv, Co);
+                       reinterpret_cast<const bf *>(in), reinterpret_cast<const bf *>(gout), gw, gb, d,
+                       int(per));
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
