@@ -189,7 +189,8 @@ enum { LBMX_ACTIVE = 0, LBMX_CONVERGED = 1, LBMX_MAXSTEPS = 2, LBMX_DIVERGED = 3
 
 /* Create a batch of `count` cavities from p[0..count-1] (same storage for
  * all, 4 <= n <= 255).  Each cavity starts at rest with theta = 0.  stream
- * as in lbmx_create. */
+ * as in lbmx_create.  Size and parameter errors return LBMX_EINVAL before
+ * any device call. */
 lbmx_status lbmx_batch_create(const lbmx_params *p, int32_t count, void *stream, lbmx_batch **out);
 
 /* Destroy a batch (NULL-safe). */

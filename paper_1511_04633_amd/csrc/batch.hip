@@ -65,7 +65,7 @@ View view_of(lbmx_batch *b, int k)
 {
     const lbmx_params &p = b->p[k];
     return View{b->ws + b->off[k] + (size_t)b->cur[k] * b->L[k].lattice, p.n, p.wall_type,
-                p.theta_hot, p.theta_cold, b->L[k].plane, true, b->stream};
+                p.theta_hot, p.theta_cold, true, b->stream};
 }
 
 double *scratch_of(lbmx_batch *b, int k) { return reinterpret_cast<double *>(b->ws + b->scr[k]); }
@@ -89,7 +89,7 @@ lbmx_status upload_cavs(lbmx_batch *b)
         c.lat[0] = b->ws + b->off[k];
         c.lat[1] = b->ws + b->off[k] + b->L[k].lattice;
         View v{c.lat[0], b->p[k].n, b->p[k].wall_type, b->p[k].theta_hot, b->p[k].theta_cold,
-               b->L[k].plane, true, b->stream};
+               true, b->stream};
         c.geo = geometry<St>(v);
         c.rates = make_rates<T>(&b->p[k], b->d[k]);
         c.cells = uint32_t(b->p[k].n) * b->p[k].n * b->p[k].n;
@@ -344,6 +344,8 @@ lbmx_status lbmx_batch_create(const lbmx_params *p, int32_t count, void *stream,
         }
         b->p.push_back(p[k]);
         b->d.push_back(d);
+        // n <= 255 keeps every lattice under 4 GiB (FP64: 255^3 x 208 B),
+        // as the 32-bit byte offsets of k_step_batch require.
         Layout L = layout_of(&p[k]);
         b->L.push_back(L);
         b->off.push_back(total);

@@ -7,10 +7,10 @@
 // block takes tiles blockIdx.x, blockIdx.x + gridDim.x, ... (grid-stride
 // "persistent" blocks when gridDim.x is smaller than the tile count, one
 // tile per block when equal).  Consecutive nodes of a tile are consecutive
-// in every population plane, so loads and stores stay coalesced across row
-// and plane boundaries, and every wavefront is full except at the end of a
-// cavity.  The per-cavity table (lattice pointers, geometry, relaxation
-// rates) is read with wavefront-uniform loads.
+// in every population segment (up to a slab boundary), so loads and stores
+// stay coalesced across row boundaries, and every wavefront is full except
+// at the end of a cavity.  The per-cavity table (lattice pointers, geometry,
+// relaxation rates) is read with wavefront-uniform loads.
 #pragma once
 
 #include "kernels.hpp"
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(1024) void k_step_batch(const BatchCav<typename St:
         T f[19], g[7];
         pull<St, true>(cv->lat[parity], geo, x, y, int(z), f, g);
         collide<T>(f, g, cv->rates);
-        put<St, true>(cv->lat[parity ^ 1], geo.plane, c, f, g);
+        put<St, true>(cv->lat[parity ^ 1], c, f, g);
     }
 }
 

@@ -151,7 +151,7 @@ Rates<T> make_rates(const lbmx_params *p, const Derived &d)
 }
 
 struct Layout {
-    size_t plane;        // elements per population plane
+    size_t slab_nodes;   // nodes per slab, 2^slab_shift_for(flow element bytes)
     size_t lattice;      // bytes per lattice
     size_t scratch_off;  // byte offset of the Nu scratch
     size_t total;
@@ -161,21 +161,21 @@ inline Layout layout_of(const lbmx_params *p)
 {
     Layout L;
     const size_t cells = (size_t)p->n * p->n * p->n;
-    L.plane = align_up(cells, 128);
-    L.lattice = align_up(L.plane * (19 * flow_size(p->storage) + 7 * energy_size(p->storage)), 256);
+    L.slab_nodes = size_t(1) << slab_shift_for(flow_size(p->storage));
+    const size_t slabs = (cells + L.slab_nodes - 1) / L.slab_nodes;
+    L.lattice = slabs * L.slab_nodes * (19 * flow_size(p->storage) + 7 * energy_size(p->storage));
     L.scratch_off = 2 * L.lattice;
     L.total = L.scratch_off + align_up(sizeof(double) * (4 * (size_t)p->n + 8), 256);
     return L;
 }
 
 
-// A lattice pair seen by the launchers: `lat` is the lattice holding the
-// current state, `plane` its plane length, `off32` selects 32-bit offsets.
+// A lattice seen by the launchers: `lat` is the lattice holding the current
+// state, `off32` selects 32-bit offsets.
 struct View {
     char *lat;
     int n, wall_type;
     double theta_hot, theta_cold;
-    size_t plane;
     bool off32;
     hipStream_t stream;
 };
@@ -189,7 +189,6 @@ Geometry<typename St::T> geometry(const View &v)
     g.wall_type = v.wall_type;
     g.theta_hot = T(v.theta_hot);
     g.theta_cold = T(v.theta_cold);
-    g.plane = v.plane;
     return g;
 }
 

@@ -61,7 +61,7 @@ double *scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L
 View view(lbmx_cavity *h)
 {
     return View{lattice(h, h->cur), h->p.n, h->p.wall_type, h->p.theta_hot, h->p.theta_cold,
-                h->L.plane, h->off32, h->stream};
+                h->off32, h->stream};
 }
 
 // One row of up to 256 nodes along x per block row; up to 512 threads per block.

@@ -90,3 +90,20 @@ def test_null_arguments():
     assert lib.lbmx_step(None, 1) == 1
     assert lib.lbmx_nusselt(None, None, None) == 1
     lib.lbmx_destroy(None)
+
+
+def test_batch_create_rejects_sizes_before_any_device_call():
+    """lbmx_batch_create validates sizes on the host: n > 255 fails with
+    LBMX_EINVAL and no handle.  The largest admitted lattice (FP64, n = 255)
+    stays under 4 GiB, which the batch kernel's 32-bit byte offsets need."""
+    lib = L.load()
+    arr = (L.lbmx_params * 2)()
+    arr[0] = L.make_params(n=16, storage="f32")
+    arr[1] = L.make_params(n=256, storage="f32")
+    h = ctypes.c_void_p(123)
+    assert lib.lbmx_batch_create(arr, 2, None, ctypes.byref(h)) == 1
+    assert not h.value
+    assert b"cavity 1" in lib.lbmx_last_error()
+    for storage in ("f64", "f32", "f16_f32"):
+        ws = L.workspace_bytes(L.make_params(n=255, storage=storage))
+        assert ws // 2 < 2 ** 32, storage
