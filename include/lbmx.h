@@ -170,7 +170,8 @@ lbmx_status lbmx_run_to_steady(lbmx_cavity *h, double tol, int64_t every, int64_
 
 /* Launch shape of the step kernel: block = (bx, by) threads over (x, y),
  * grid covers the cube; bx*by must be a multiple of 64 (one wavefront) and
- * at most 1024, unless bx = n and by = 1.  0, 0 restores the default. */
+ * at most 1024, unless bx = n and by = 1.  0, 0 restores the default
+ * (bx = min(n, 256), by = min(n, max(1, 256 / bx))). */
 lbmx_status lbmx_set_launch(lbmx_cavity *h, int32_t bx, int32_t by);
 lbmx_status lbmx_get_launch(const lbmx_cavity *h, int32_t *bx, int32_t *by);
 

@@ -64,11 +64,13 @@ View view(lbmx_cavity *h)
                 h->off32, h->stream};
 }
 
-// One row of up to 256 nodes along x per block row; up to 512 threads per block.
+// One row of up to 256 nodes along x per block row; up to 256 threads per
+// block (at 256^3, 256 x 1 blocks measured 1% faster than 256 x 2 and 5%
+// faster than half-row 128 x 2 blocks).
 void default_launch(int n, int *bx, int *by)
 {
     *bx = n < 256 ? n : 256;
-    int b = 512 / *bx;
+    int b = 256 / *bx;
     if (b < 1) b = 1;
     if (b > n) b = n;
     *by = b;
