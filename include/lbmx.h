@@ -44,7 +44,8 @@ typedef enum {
     LBMX_EDEVICE = 3,        /* a HIP runtime call failed                    */
     LBMX_EUNSTABLE = 4,      /* non-finite values found (run diverged)       */
     LBMX_ENOTCONVERGED = 5,  /* run_to_steady hit max_steps                  */
-    LBMX_ESTATE = 6          /* call not valid in the handle's current state */
+    LBMX_ESTATE = 6,         /* call not valid in the handle's current state */
+    LBMX_EIO = 7             /* a checkpoint file could not be read/written  */
 } lbmx_status;
 
 /* Population storage in HBM.  Collision arithmetic is FP64 for LBMX_F64 and
@@ -128,6 +129,23 @@ lbmx_status lbmx_set_populations(lbmx_cavity *h, const double *f_host, const dou
 /* Copy the populations of the current state to host (19 n^3 and 7 n^3
  * doubles; either pointer may be NULL). */
 lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host);
+
+/* Checkpoints, for callers that resume long runs (the paper's runs to a
+ * steady state take up to ~10^6 steps).  lbmx_save writes the cavity's
+ * parameter set, its time t and its current lattice (the post-collision
+ * populations of t - 1, in the storage format, bit for bit) to `path`;
+ * lbmx_load reads such a file into a cavity created with the same parameter
+ * set (the custom s, tau arrays are compared only when custom_rates = 1), so
+ * that stepping on continues bitwise as the saved cavity would.  The file is
+ * a 320-byte header (magic "LBMXCKPT", version 1, sizeof(lbmx_params), the
+ * parameters, t, lattice bytes, nodes per slab; host byte order) followed by
+ * the lattice; it is tied to this library's lattice layout and is not meant
+ * to be portable across versions.  Both calls synchronise the stream.
+ * Errors: EIO when the file cannot be opened, written or read in full;
+ * EINVAL when it is not a checkpoint, has another version, size, layout or
+ * parameter set (checked before the cavity's state is touched). */
+lbmx_status lbmx_save(lbmx_cavity *h, const char *path);
+lbmx_status lbmx_load(lbmx_cavity *h, const char *path);
 
 /* Set the state at t = 0 from velocity and temperature fields given on a
  * src_n^3 grid of node-centred device FP32 arrays (x fastest): each cavity

@@ -7,6 +7,8 @@
 // and copies.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cerrno>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -105,6 +107,63 @@ lbmx_status check_handle(const lbmx_cavity *h)
         return fail(LBMX_EINVAL, "cavity handle is NULL");
     return LBMX_OK;
 }
+
+// Checkpoint file header (no padding: 8 + 4 + 4 + 280 + 3 x 8 bytes).
+constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'X', 'C', 'K', 'P', 'T'};
+constexpr uint32_t kCkptVersion = 1;
+constexpr size_t kCkptChunk = size_t(64) << 20;  // staging buffer bytes
+struct CkptHeader {
+    char magic[8];
+    uint32_t version;
+    uint32_t params_bytes;
+    lbmx_params p;
+    int64_t t;
+    uint64_t lattice_bytes;
+    uint64_t slab_nodes;
+};
+static_assert(sizeof(lbmx_params) == 280, "lbmx_params is expected to have no padding");
+static_assert(sizeof(CkptHeader) == 320, "checkpoint header layout");
+
+// The parameter set as it matters to the state: custom rates only if used.
+lbmx_params canonical(const lbmx_params &p)
+{
+    lbmx_params q = p;
+    if (!q.custom_rates) {
+        std::memset(q.s, 0, sizeof q.s);
+        std::memset(q.tau, 0, sizeof q.tau);
+    }
+    return q;
+}
+
+struct File {
+    FILE *f;
+    explicit File(FILE *x) : f(x) {}
+    File(const File &) = delete;
+    File &operator=(const File &) = delete;
+    ~File()
+    {
+        if (f)
+            std::fclose(f);
+    }
+    FILE *release()
+    {
+        FILE *x = f;
+        f = nullptr;
+        return x;
+    }
+};
+
+struct HostBuf {
+    void *p = nullptr;
+    HostBuf() = default;
+    HostBuf(const HostBuf &) = delete;
+    HostBuf &operator=(const HostBuf &) = delete;
+    ~HostBuf()
+    {
+        if (p)
+            (void)hipHostFree(p);
+    }
+};
 
 }  // namespace
 
@@ -311,6 +370,92 @@ lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host)
     return LBMX_OK;
 }
 
+lbmx_status lbmx_save(lbmx_cavity *h, const char *path)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!path)
+        return fail(LBMX_EINVAL, "path is NULL");
+    CkptHeader hd;
+    std::memset(&hd, 0, sizeof hd);
+    std::memcpy(hd.magic, kCkptMagic, sizeof hd.magic);
+    hd.version = kCkptVersion;
+    hd.params_bytes = sizeof(lbmx_params);
+    hd.p = canonical(h->p);
+    hd.t = h->t;
+    hd.lattice_bytes = h->L.lattice;
+    hd.slab_nodes = h->L.slab_nodes;
+    File f(std::fopen(path, "wb"));
+    if (!f.f)
+        return fail(LBMX_EIO, "cannot open %s for writing: %s", path, std::strerror(errno));
+    if (std::fwrite(&hd, sizeof hd, 1, f.f) != 1)
+        return fail(LBMX_EIO, "writing the header of %s failed", path);
+    HostBuf stage;
+    const size_t chunk = std::min<size_t>(h->L.lattice, kCkptChunk);
+    HIP_TRY(hipHostMalloc(&stage.p, chunk, hipHostMallocDefault));
+    const char *lat = lattice(h, h->cur);
+    for (size_t off = 0; off < h->L.lattice; off += chunk) {
+        const size_t len = std::min(chunk, h->L.lattice - off);
+        HIP_TRY(hipMemcpyAsync(stage.p, lat + off, len, hipMemcpyDeviceToHost, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        if (std::fwrite(stage.p, 1, len, f.f) != len)
+            return fail(LBMX_EIO, "writing %s failed at byte %zu", path, sizeof hd + off);
+    }
+    if (std::fclose(f.release()) != 0)
+        return fail(LBMX_EIO, "closing %s failed: %s", path, std::strerror(errno));
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_load(lbmx_cavity *h, const char *path)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!path)
+        return fail(LBMX_EINVAL, "path is NULL");
+    File f(std::fopen(path, "rb"));
+    if (!f.f)
+        return fail(LBMX_EIO, "cannot open %s: %s", path, std::strerror(errno));
+    CkptHeader hd;
+    if (std::fread(&hd, sizeof hd, 1, f.f) != 1)
+        return fail(LBMX_EIO, "%s is shorter than a checkpoint header", path);
+    if (std::memcmp(hd.magic, kCkptMagic, sizeof hd.magic) != 0)
+        return fail(LBMX_EINVAL, "%s is not a checkpoint", path);
+    if (hd.version != kCkptVersion || hd.params_bytes != sizeof(lbmx_params))
+        return fail(LBMX_EINVAL, "%s: checkpoint version %u / parameter size %u, need %u / %zu", path,
+                    hd.version, hd.params_bytes, kCkptVersion, sizeof(lbmx_params));
+    const lbmx_params mine = canonical(h->p);
+    if (std::memcmp(&hd.p, &mine, sizeof mine) != 0)
+        return fail(LBMX_EINVAL, "%s was written for another parameter set", path);
+    if (hd.lattice_bytes != h->L.lattice || hd.slab_nodes != h->L.slab_nodes || hd.t < 0)
+        return fail(LBMX_EINVAL, "%s: lattice of %llu bytes in slabs of %llu nodes at t = %lld, "
+                    "need %zu bytes in slabs of %zu", path, (unsigned long long)hd.lattice_bytes,
+                    (unsigned long long)hd.slab_nodes, (long long)hd.t, h->L.lattice, h->L.slab_nodes);
+    if (std::fseek(f.f, 0, SEEK_END) != 0)
+        return fail(LBMX_EIO, "cannot seek in %s", path);
+    const long end = std::ftell(f.f);
+    if (end < 0 || (unsigned long)end != sizeof hd + h->L.lattice)
+        return fail(LBMX_EIO, "%s holds %ld bytes, a checkpoint of this cavity %zu", path, end,
+                    sizeof hd + h->L.lattice);
+    if (std::fseek(f.f, (long)sizeof hd, SEEK_SET) != 0)
+        return fail(LBMX_EIO, "cannot seek in %s", path);
+    HostBuf stage;
+    const size_t chunk = std::min<size_t>(h->L.lattice, kCkptChunk);
+    HIP_TRY(hipHostMalloc(&stage.p, chunk, hipHostMallocDefault));
+    char *lat = lattice(h, 0);
+    for (size_t off = 0; off < h->L.lattice; off += chunk) {
+        const size_t len = std::min(chunk, h->L.lattice - off);
+        if (std::fread(stage.p, 1, len, f.f) != len)
+            return fail(LBMX_EIO, "reading %s failed at byte %zu", path, sizeof hd + off);
+        HIP_TRY(hipMemcpyAsync(lat + off, stage.p, len, hipMemcpyHostToDevice, h->stream));
+        HIP_TRY(hipStreamSynchronize(h->stream));
+    }
+    h->cur = 0;
+    h->t = hd.t;
+    return LBMX_OK;
+}
+
 lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *dev_v,
                              const float *dev_w, const float *dev_theta, int32_t src_n)
 {
@@ -505,6 +650,7 @@ const char *lbmx_strerror(lbmx_status s)
     case LBMX_EUNSTABLE: return "non-finite values (run diverged)";
     case LBMX_ENOTCONVERGED: return "not converged within max_steps";
     case LBMX_ESTATE: return "invalid state for this call";
+    case LBMX_EIO: return "checkpoint file I/O error";
     default: return "unknown status";
     }
 }

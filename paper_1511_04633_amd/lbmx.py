@@ -20,13 +20,13 @@ F64, F32, F16, BF16, F16_F32, BF16_F32 = 0, 1, 2, 3, 4, 5
 STORAGE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f16_f32": F16_F32,
            "bf16_f32": BF16_F32}
 STATUS = {0: "LBMX_OK", 1: "LBMX_EINVAL", 2: "LBMX_ENOMEM", 3: "LBMX_EDEVICE",
-          4: "LBMX_EUNSTABLE", 5: "LBMX_ENOTCONVERGED", 6: "LBMX_ESTATE"}
+          4: "LBMX_EUNSTABLE", 5: "LBMX_ENOTCONVERGED", 6: "LBMX_ESTATE", 7: "LBMX_EIO"}
 
 # Every symbol include/lbmx.h declares.
 SYMBOLS = [
     "lbmx_params_default", "lbmx_derive", "lbmx_workspace_bytes", "lbmx_bytes_per_cell",
     "lbmx_create", "lbmx_destroy", "lbmx_init_rest", "lbmx_set_populations",
-    "lbmx_get_populations", "lbmx_init_fields", "lbmx_step", "lbmx_step_timed", "lbmx_time",
+    "lbmx_get_populations", "lbmx_save", "lbmx_load", "lbmx_init_fields", "lbmx_step", "lbmx_step_timed", "lbmx_time",
     "lbmx_read_macro", "lbmx_nusselt", "lbmx_run_to_steady", "lbmx_set_launch",
     "lbmx_get_launch", "lbmx_strerror", "lbmx_last_error",
     "lbmx_batch_create", "lbmx_batch_destroy", "lbmx_batch_init_rest", "lbmx_batch_step",
@@ -89,6 +89,8 @@ def load() -> ctypes.CDLL:
         "lbmx_init_rest": [_vp, _dp],
         "lbmx_set_populations": [_vp, _dp, _dp, i64],
         "lbmx_get_populations": [_vp, _dp, _dp],
+        "lbmx_save": [_vp, ctypes.c_char_p],
+        "lbmx_load": [_vp, ctypes.c_char_p],
         "lbmx_init_fields": [_vp, _vp, _vp, _vp, _vp, i32],
         "lbmx_step": [_vp, i64],
         "lbmx_step_timed": [_vp, i64, _dp],
@@ -242,6 +244,16 @@ class Cavity:
         g = np.empty(7 * self.cells)
         _check(load().lbmx_get_populations(self._h, _dptr(f), _dptr(g)))
         return f.reshape(19, self.cells), g.reshape(7, self.cells)
+
+    def save(self, path):
+        """Write a checkpoint (parameters, t, current lattice) to `path`."""
+        _check(load().lbmx_save(self._h, os.fsencode(path)))
+        return self
+
+    def load(self, path):
+        """Restore a checkpoint written by save() for the same parameter set."""
+        _check(load().lbmx_load(self._h, os.fsencode(path)))
+        return self
 
     # ---- time stepping ------------------------------------------------------
     def step(self, nsteps: int = 1):

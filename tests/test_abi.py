@@ -79,8 +79,8 @@ def test_sizes():
 
 def test_error_strings():
     lib = L.load()
-    for s in range(7):
-        assert lib.lbmx_strerror(s)
+    for s in range(8):
+        assert lib.lbmx_strerror(s) and lib.lbmx_strerror(s) != b"unknown status"
     assert lib.lbmx_strerror(99) == b"unknown status"
 
 
