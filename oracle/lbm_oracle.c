@@ -49,6 +49,20 @@
  *   R18 Nu_2D (Eq. 41) on the X = 0.5 line: the centre column for odd N, the
  *       mean of the two central columns for even N; Nu_max without interpolation.
  *
+ * Variants beyond the paper's own choices (ablations of the readings above):
+ *   force model 1: the other reading of Eq. (15), division by rho c_s^2, so that
+ *       sum_i e_i F_i = G (force density G instead of rho G);
+ *   force model 2: Guo-type forcing written in moment space (Guo, Zheng & Shi,
+ *       Phys. Rev. E 65, 046308 (2002), in its MRT form): V = (sum_i e_i f_i +
+ *       rho G / 2) / rho, m^eq of Eq. (24) with j = rho V, and
+ *       M^-1 (I - S/2) M Fbar added, Fbar_i = w_i rho [3 (e_i - V) + 9 (e_i . V) e_i] . G;
+ *       the energy equilibrium and the reported velocity use the same V;
+ *   anisotropic diffusion: D = alpha A for a symmetric positive definite A,
+ *       the full tau-bar block of Eq. (35) from Eq. (36);
+ *   Nu stencils: 0 = R17; 1 = first order, dtheta/dy|_0 = 2 (th_0 - th_w);
+ *       2 = energy flux of the wall links, q = g_in - g*_out through the hot
+ *       wall, Nu = H q / D_yy (the conductive flux that crosses the wall).
+ *
  * A fully periodic mode (wall_type 0) exists only here, for the transport
  * coefficient checks (decay of a shear wave and of a temperature sine mode).
  */
@@ -126,6 +140,8 @@ static const double N7[Q7][Q7] = {
 
 typedef struct oracle {
     int n, wall_type;
+    int force_model;           /* 0, 1, 2: see the header */
+    double tau_wall;           /* tau-bar_yy of Q^-1, for the wall-flux Nu */
     double theta_hot, theta_cold, theta_ref;
     double gbeta;              /* g beta per unit theta, lattice units */
     double u_c, nu, alpha, s_nu, tau_t;
@@ -300,6 +316,21 @@ void oracle_force(double rho, const double *v, double gz, double *force)
     }
 }
 
+/* Guo's forcing term (force model 2): Fbar_i = w_i rho [3 (e_i - V) + 9 (e_i . V) e_i] . G,
+ * G = (0, 0, gz); c_s^2 = 1/3. */
+void oracle_guo_force(double rho, const double *v, double gz, double *fbar)
+{
+    const double gvec[3] = {0.0, 0.0, gz};
+    for (int i = 0; i < Q19; ++i) {
+        double ev = 0.0, t = 0.0;
+        for (int d = 0; d < 3; ++d)
+            ev += E19[i][d] * v[d];
+        for (int d = 0; d < 3; ++d)
+            t += ((E19[i][d] - v[d]) / CS2 + ev * E19[i][d] / (CS2 * CS2)) * gvec[d];
+        fbar[i] = W19[i] * rho * t;
+    }
+}
+
 /* One node's collision: Eqs. (19)-(20), (14)-(17) for f; Eqs. (29)-(35) for g. */
 static void collide_node(const oracle *o, const double *f, const double *g,
                          double *fo, double *go)
@@ -311,11 +342,16 @@ static void collide_node(const oracle *o, const double *f, const double *g,
         for (int d = 0; d < 3; ++d)
             j[d] += E19[i][d] * f[i];
     }
-    double v[3] = {j[0] / rho, j[1] / rho, j[2] / rho};
-    /* Eq. (30): temperature. */
+    /* Eq. (30): temperature; Eq. (16): buoyancy along +z (reading R7). */
     double theta = 0.0;
     for (int i = 0; i < Q7; ++i)
         theta += g[i];
+    const double gz = o->gbeta * (theta - o->theta_ref);
+    /* Momentum of the equilibrium: j itself, or j + rho G / 2 (force model 2). */
+    double jeq[3] = {j[0], j[1], j[2]};
+    if (o->force_model == 2)
+        jeq[2] += 0.5 * rho * gz;
+    double v[3] = {jeq[0] / rho, jeq[1] / rho, jeq[2] / rho};
 
     /* Eq. (20): m = M f;  Eq. (24): m^eq;  Eq. (19): Omega = -M^-1 S (m - m^eq). */
     double m[Q19], meq[Q19], dm[Q19];
@@ -324,13 +360,30 @@ static void collide_node(const oracle *o, const double *f, const double *g,
         for (int i = 0; i < Q19; ++i)
             m[k] += M19[k][i] * f[i];
     }
-    oracle_meq(rho, j[0], j[1], j[2], meq);
+    oracle_meq(rho, jeq[0], jeq[1], jeq[2], meq);
     for (int k = 0; k < Q19; ++k)
         dm[k] = o->s[k] * (m[k] - meq[k]);
 
-    /* Eqs. (15)-(17): Boussinesq force, G along +z (reading R7). */
     double force[Q19];
-    oracle_force(rho, v, o->gbeta * (theta - o->theta_ref), force);
+    if (o->force_model == 2) {
+        /* Guo: the source (I - S/2) M Fbar joins the moment-space update. */
+        double fbar[Q19], mf[Q19];
+        oracle_guo_force(rho, v, gz, fbar);
+        for (int k = 0; k < Q19; ++k) {
+            mf[k] = 0.0;
+            for (int i = 0; i < Q19; ++i)
+                mf[k] += M19[k][i] * fbar[i];
+            dm[k] -= (1.0 - 0.5 * o->s[k]) * mf[k];
+        }
+        for (int i = 0; i < Q19; ++i)
+            force[i] = 0.0;
+    } else {
+        /* Eqs. (15)-(17); force model 1 divides by rho as well. */
+        oracle_force(rho, v, gz, force);
+        if (o->force_model == 1)
+            for (int i = 0; i < Q19; ++i)
+                force[i] /= rho;
+    }
 
     /* Eq. (14): post-collision value f + Omega + F. */
     for (int i = 0; i < Q19; ++i) {
@@ -399,15 +452,17 @@ static int thermal_wall(const oracle *o, int axis, int side, int y, double *thet
 oracle *oracle_create(int n, int wall_type, double ra, double pr, double ma,
                       double theta_hot, double theta_cold, double theta_ref,
                       double buoyancy_scale, const double *s19, const double *tau7,
-                      const double *theta0)
+                      const double *aniso6, int force_model, const double *theta0)
 {
-    if (n < 2 || wall_type < 0 || wall_type > 3 || ra <= 0 || pr <= 0 || ma <= 0)
+    if (n < 2 || wall_type < 0 || wall_type > 3 || ra <= 0 || pr <= 0 || ma <= 0 ||
+        force_model < 0 || force_model > 2)
         return NULL;
     oracle *o = (oracle *)calloc(1, sizeof(oracle));
     if (!o)
         return NULL;
     o->n = n;
     o->wall_type = wall_type;
+    o->force_model = force_model;
     o->theta_hot = theta_hot;
     o->theta_cold = theta_cold;
     o->theta_ref = theta_ref;
@@ -433,12 +488,23 @@ oracle *oracle_create(int n, int wall_type, double ra, double pr, double ma,
     memcpy(o->minv, mi, sizeof(mi));
     memcpy(o->ninv, ni, sizeof(ni));
 
-    /* Eq. (35) with reading R16; Q is the inverse of Q^-1. */
+    /* Eq. (35) with reading R16; Q is the inverse of Q^-1.  With aniso6 =
+     * (A_xx, A_yy, A_zz, A_xy, A_xz, A_yz), D = alpha A and the tau-bar block
+     * of rows/columns 2..4 is Eq. (36): 1/2 delta_ij + D_ij / epsilon. */
     double qinv[Q7 * Q7], qm[Q7 * Q7];
     memset(qinv, 0, sizeof(qinv));
     double tau_default[Q7] = {1.0, o->tau_t, o->tau_t, o->tau_t, 1.0, 1.0, 1.0};
     for (int k = 0; k < Q7; ++k)
         qinv[k * Q7 + k] = tau7 ? tau7[k] : tau_default[k];
+    if (aniso6) {
+        const int ia[6] = {0, 1, 2, 0, 0, 1}, ib[6] = {0, 1, 2, 1, 2, 2};
+        for (int q = 0; q < 6; ++q) {
+            double t = (ia[q] == ib[q] ? 0.5 : 0.0) + o->alpha * aniso6[q] / EPS_T;
+            qinv[(1 + ia[q]) * Q7 + (1 + ib[q])] = t;
+            qinv[(1 + ib[q]) * Q7 + (1 + ia[q])] = t;
+        }
+    }
+    o->tau_wall = qinv[2 * Q7 + 2];
     if (invert(Q7, qinv, qm) != 0) {
         free(o);
         return NULL;
@@ -567,8 +633,9 @@ void oracle_step(oracle *o, long nsteps)
     }
 }
 
-/* Macroscopic fields of the current state: Eqs. (20), (25), (30).
- * Arrays hold n^3 values, x fastest; any pointer may be NULL. */
+/* Macroscopic fields of the current state: Eqs. (20), (25), (30) (with the
+ * half-force velocity of force model 2).  Arrays hold n^3 values, x fastest;
+ * any pointer may be NULL. */
 void oracle_macro(const oracle *o, double *rho, double *ux, double *uy, double *uz, double *theta)
 {
     const int n = o->n;
@@ -583,6 +650,8 @@ void oracle_macro(const oracle *o, double *rho, double *ux, double *uy, double *
         }
         for (int i = 0; i < Q7; ++i)
             th += o->g[i * cells + c];
+        if (o->force_model == 2) /* V = (j + rho G / 2) / rho */
+            j[2] += 0.5 * r * o->gbeta * (th - o->theta_ref);
         if (rho) rho[c] = r;
         if (ux) ux[c] = j[0] / r;
         if (uy) uy[c] = j[1] / r;
@@ -591,12 +660,15 @@ void oracle_macro(const oracle *o, double *rho, double *ux, double *uy, double *
     }
 }
 
-/* Hot-wall Nusselt numbers, Eqs. (39)-(41) with readings R17, R18.
+/* Hot-wall Nusselt numbers, Eqs. (39)-(41) with readings R17, R18 and the
+ * stencil choice of the header (theta_h - theta_c = 1, as in Eq. 38).
  * out = {Nu_3D, Nu_2D, Nu_max}; map (n*n, x fastest then z) may be NULL. */
-void oracle_nusselt(const oracle *o, double *out, double *map)
+void oracle_nusselt(const oracle *o, int stencil, double *out, double *map)
 {
     const int n = o->n;
     const size_t cells = (size_t)n * n * n;
+    /* D_yy from the tau-bar actually used (Eq. 36 solved for D). */
+    const double d_yy = EPS_T * (o->tau_wall - 0.5);
     double sum = 0.0, line = 0.0, mx = -INFINITY;
     for (int z = 0; z < n; ++z)
         for (int x = 0; x < n; ++x) {
@@ -608,8 +680,20 @@ void oracle_nusselt(const oracle *o, double *out, double *map)
                 th1 += o->g[i * cells + c1];
             }
             /* Nu = -d theta / dY with Y = y / H, H = n. */
-            double dth = (9.0 * th0 - th1 - 8.0 * o->theta_hot) / 3.0;
-            double nu_loc = -dth * n;
+            double nu_loc;
+            if (stencil == 1) {
+                nu_loc = -2.0 * (th0 - o->theta_hot) * n;
+            } else if (stencil == 2) {
+                /* g_+y at the wall node entered from the wall in the last
+                 * streaming: g_in = -g*_out + 2 w_T theta_h, so the net flux
+                 * into the fluid is g_in - g*_out = 2 (g_in - w_T theta_h). */
+                const double g_in = o->g[3 * cells + c0];
+                const double q = 2.0 * (g_in - W7[3] * o->theta_hot);
+                nu_loc = n * q / d_yy;
+            } else {
+                double dth = (9.0 * th0 - th1 - 8.0 * o->theta_hot) / 3.0;
+                nu_loc = -dth * n;
+            }
             if (map) map[(size_t)x + (size_t)n * z] = nu_loc;
             sum += nu_loc;
             if (nu_loc > mx) mx = nu_loc;

@@ -49,13 +49,13 @@ def lib() -> ctypes.CDLL:
         L.oracle_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
-                                    _dp, _dp, _dp]
+                                    _dp, _dp, _dp, ctypes.c_int, _dp]
         L.oracle_destroy.argtypes = [ctypes.c_void_p]
         L.oracle_step.argtypes = [ctypes.c_void_p, ctypes.c_long]
         L.oracle_time.restype = ctypes.c_long
         L.oracle_time.argtypes = [ctypes.c_void_p]
         L.oracle_macro.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp, _dp]
-        L.oracle_nusselt.argtypes = [ctypes.c_void_p, _dp, _dp]
+        L.oracle_nusselt.argtypes = [ctypes.c_void_p, ctypes.c_int, _dp, _dp]
         L.oracle_get_state.argtypes = [ctypes.c_void_p, _dp, _dp]
         L.oracle_set_state.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_long]
         L.oracle_derive.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double,
@@ -66,6 +66,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_meq.argtypes = [ctypes.c_double] * 4 + [_dp]
         L.oracle_feq.argtypes = [ctypes.c_double, _dp, _dp]
         L.oracle_force.argtypes = [ctypes.c_double, _dp, ctypes.c_double, _dp]
+        L.oracle_guo_force.argtypes = [ctypes.c_double, _dp, ctypes.c_double, _dp]
         L.oracle_collide_node.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
         L.oracle_threads.restype = ctypes.c_int
         _lib = L
@@ -123,6 +124,14 @@ def force(rho, v, gz):
     return out
 
 
+def guo_force(rho, v, gz):
+    """Guo's forcing term Fbar_i (force model 2) for G = (0, 0, gz)."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(19)
+    lib().oracle_guo_force(rho, _ptr(v), gz, _ptr(out))
+    return out
+
+
 def threads() -> int:
     return int(lib().oracle_threads())
 
@@ -134,23 +143,28 @@ class Oracle:
     (oracle-only, used to measure transport coefficients).
     s19: optional diagonal of S (Eq. 23) replacing Eq. (26).
     tau7: optional diagonal of Q^-1 (Eq. 35) replacing the paper's choice.
+    aniso: optional (A_xx, A_yy, A_zz, A_xy, A_xz, A_yz): diffusion tensor
+    D = alpha A in the tau-bar block of Eq. (35) via Eq. (36).
+    force_model: 0 (Eq. 15, reading R3), 1 (Eq. 15 divided by rho), 2 (Guo).
     theta0: initial temperature field (n^3, x fastest); the initial state is
     f_i = w_i, g_i = w_T,i * theta0.
     """
 
     def __init__(self, n, wall_type=1, ra=1e3, pr=0.71, ma=0.1, theta_hot=0.5,
                  theta_cold=-0.5, theta_ref=0.0, buoyancy_scale=1.0, s19=None,
-                 tau7=None, theta0=None):
+                 tau7=None, aniso=None, force_model=0, theta0=None):
         self.n = int(n)
         self.cells = self.n ** 3
         s19 = None if s19 is None else np.ascontiguousarray(s19, dtype=np.float64)
         tau7 = None if tau7 is None else np.ascontiguousarray(tau7, dtype=np.float64)
+        aniso = None if aniso is None else np.ascontiguousarray(aniso, dtype=np.float64)
         if theta0 is not None:
             theta0 = np.ascontiguousarray(theta0, dtype=np.float64).reshape(-1)
             assert theta0.size == self.cells
-        self._keep = (s19, tau7, theta0)
+        self._keep = (s19, tau7, aniso, theta0)
         h = lib().oracle_create(self.n, int(wall_type), ra, pr, ma, theta_hot, theta_cold,
-                                theta_ref, buoyancy_scale, _ptr(s19), _ptr(tau7), _ptr(theta0))
+                                theta_ref, buoyancy_scale, _ptr(s19), _ptr(tau7), _ptr(aniso),
+                                int(force_model), _ptr(theta0))
         if not h:
             raise ValueError("oracle_create rejected the parameters")
         self._h = ctypes.c_void_p(h)
@@ -182,10 +196,12 @@ class Oracle:
         sh = (self.n,) * 3
         return tuple(a.reshape(sh) for a in arrs)
 
-    def nusselt(self, with_map=False):
+    def nusselt(self, with_map=False, stencil=0):
+        """Hot-wall Nu family; stencil 0 (second order), 1 (first order),
+        2 (energy flux of the wall links)."""
         out = np.zeros(3)
         mp = np.zeros(self.n * self.n) if with_map else None
-        lib().oracle_nusselt(self._h, _ptr(out), _ptr(mp))
+        lib().oracle_nusselt(self._h, int(stencil), _ptr(out), _ptr(mp))
         d = {"nu3d": out[0], "nu2d": out[1], "numax": out[2]}
         if with_map:
             d["map"] = mp.reshape(self.n, self.n)  # [z, x]
