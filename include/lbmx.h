@@ -77,7 +77,34 @@ typedef struct {
     int32_t custom_rates;   /* 0: rates of Eq. (26) and Sec. 3.2; 1: use s, tau   */
     double s[19];           /* diagonal of S (Eq. 23) when custom_rates = 1       */
     double tau[7];          /* diagonal of Q^-1 (Eq. 35) when custom_rates = 1    */
+    int32_t force_model;    /* buoyancy term, LBMX_FORCE_* (0 = Eq. 15)           */
+    int32_t nu_stencil;     /* hot-wall gradient for Nu, LBMX_NU_* (0 = default)  */
+    double aniso[6];        /* A_xx, A_yy, A_zz, A_xy, A_xz, A_yz: diffusion      */
+                            /* tensor D = alpha A of Eq. (27), entering Q^-1 by   */
+                            /* Eq. (36); all zero = isotropic D = alpha I         */
 } lbmx_params;
+
+/* Force models: how the buoyancy G = g beta (theta - theta_ref) e_z of
+ * Eq. (16) enters the flow lattice.
+ *   LBMX_FORCE_EQ15: Eq. (15) with the density carried by f^eq of Eq. (17),
+ *     F_i = 3 G.(e_i - V) f^eq_i, added after the collision (Eq. 14); the
+ *     momentum gain per step is rho G.
+ *   LBMX_FORCE_EQ15_RHO: the other reading of Eq. (15), divided by rho
+ *     (momentum gain G).
+ *   LBMX_FORCE_GUO: Guo's forcing in moment space: V = (j + rho G / 2) / rho
+ *     in the flow and energy equilibria and in lbmx_read_macro, and
+ *     M^-1 (I - S/2) M Fbar added, Fbar_i = w_i rho [3 (e_i - V) + 9 (e_i.V) e_i].G. */
+enum { LBMX_FORCE_EQ15 = 0, LBMX_FORCE_EQ15_RHO = 1, LBMX_FORCE_GUO = 2 };
+
+/* Nu stencils for the temperature gradient at the hot wall (Eq. 39); all
+ * assume theta_hot - theta_cold = 1 as in Eq. (38).
+ *   LBMX_NU_SECOND_ORDER: (9 theta_0 - theta_1 - 8 theta_hot)/3, exact for
+ *     quadratic profiles (wall value and the first two nodes);
+ *   LBMX_NU_FIRST_ORDER: 2 (theta_0 - theta_hot);
+ *   LBMX_NU_WALL_FLUX: the energy crossing the hot wall's D3Q7 links in the
+ *     last streaming, q = g_in - g*_out = 2 (g_+y - theta_hot / 8) at the
+ *     wall node, as a gradient q / D_yy. */
+enum { LBMX_NU_SECOND_ORDER = 0, LBMX_NU_FIRST_ORDER = 1, LBMX_NU_WALL_FLUX = 2 };
 
 typedef struct {
     double nu3d;            /* Eq. (40): mean local Nu over the hot wall        */
@@ -90,13 +117,16 @@ typedef struct {
 typedef struct lbmx_cavity lbmx_cavity;
 
 /* Fill *p with the defaults: n = 16, Type 1, Ra = 1e3, Pr = 0.71, Ma = 0.1,
- * theta_hot = 0.5, theta_cold = -0.5, theta_ref = 0, buoyancy 1, LBMX_F32. */
+ * theta_hot = 0.5, theta_cold = -0.5, theta_ref = 0, buoyancy 1, LBMX_F32,
+ * force model Eq. (15), second-order Nu stencil, isotropic diffusion. */
 lbmx_status lbmx_params_default(lbmx_params *p);
 
 /* Lattice-unit parameters (Sec. 4, Eq. 38; Eqs. 26, 36):
  * out[6] = {u_c = Ma c_s, g beta (per unit theta), nu, alpha = nu/Pr,
  *           s_nu = 1/(3 nu + 1/2), tau_T = 1/2 + alpha/epsilon (epsilon 1/4)}.
- * EINVAL if the set is invalid (including s_nu outside (0, 2) or tau_T <= 1/2). */
+ * EINVAL if the set is invalid (including s_nu outside (0, 2) or tau_T <= 1/2,
+ * an unknown force model or stencil, an aniso tensor that is not positive
+ * definite, or aniso together with custom_rates). */
 lbmx_status lbmx_derive(const lbmx_params *p, double *out);
 
 /* Device bytes a cavity needs (two lattices plus reduction scratch). */
@@ -137,7 +167,7 @@ lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host)
  * lbmx_load reads such a file into a cavity created with the same parameter
  * set (the custom s, tau arrays are compared only when custom_rates = 1), so
  * that stepping on continues bitwise as the saved cavity would.  The file is
- * a 320-byte header (magic "LBMXCKPT", version 1, sizeof(lbmx_params), the
+ * a 376-byte header (magic "LBMXCKPT", version 1, sizeof(lbmx_params), the
  * parameters, t, lattice bytes, nodes per slab; host byte order) followed by
  * the lattice; it is tied to this library's lattice layout and is not meant
  * to be portable across versions.  Both calls synchronise the stream.

@@ -31,6 +31,7 @@ enum : int32_t { ST_ACTIVE = 0, ST_CONVERGED = 1, ST_MAXSTEPS = 2, ST_UNSTABLE =
 struct lbmx_batch {
     int count = 0;
     int32_t storage = LBMX_F32;
+    int32_t force_model = LBMX_FORCE_EQ15;  // shared by all cavities
     std::vector<lbmx_params> p;
     std::vector<Derived> d;
     std::vector<Layout> L;
@@ -64,8 +65,8 @@ namespace {
 View view_of(lbmx_batch *b, int k)
 {
     const lbmx_params &p = b->p[k];
-    return View{b->ws + b->off[k] + (size_t)b->cur[k] * b->L[k].lattice, p.n, p.wall_type,
-                p.theta_hot, p.theta_cold, true, b->stream};
+    return make_view(b->ws + b->off[k] + (size_t)b->cur[k] * b->L[k].lattice, p, b->d[k], true,
+                     b->stream);
 }
 
 double *scratch_of(lbmx_batch *b, int k) { return reinterpret_cast<double *>(b->ws + b->scr[k]); }
@@ -88,9 +89,7 @@ lbmx_status upload_cavs(lbmx_batch *b)
         BatchCav<T> &c = h[k];
         c.lat[0] = b->ws + b->off[k];
         c.lat[1] = b->ws + b->off[k] + b->L[k].lattice;
-        View v{c.lat[0], b->p[k].n, b->p[k].wall_type, b->p[k].theta_hot, b->p[k].theta_cold,
-               true, b->stream};
-        c.geo = geometry<St>(v);
+        c.geo = geometry<St>(make_view(c.lat[0], b->p[k], b->d[k], true, b->stream));
         c.rates = make_rates<T>(&b->p[k], b->d[k]);
         c.cells = uint32_t(b->p[k].n) * b->p[k].n * b->p[k].n;
         c.inv_n = 1.0f / float(b->p[k].n);
@@ -144,8 +143,19 @@ lbmx_status launch_direct(lbmx_batch *b, int64_t nsteps)
     using T = typename St::T;
     const auto *cavs = reinterpret_cast<const BatchCav<T> *>(b->d_cavs);
     for (int64_t s = 0; s < nsteps; ++s) {
-        hipLaunchKernelGGL(k_step_batch<St>, dim3(grid_blocks(b)), dim3(b->block), 0, b->stream, cavs,
-                           b->d_tiles, b->ntiles, b->parity);
+        switch (b->force_model) {
+        case LBMX_FORCE_EQ15_RHO:
+            hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_EQ15_RHO>), dim3(grid_blocks(b)),
+                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity);
+            break;
+        case LBMX_FORCE_GUO:
+            hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_GUO>), dim3(grid_blocks(b)),
+                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity);
+            break;
+        default:
+            hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_EQ15>), dim3(grid_blocks(b)),
+                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity);
+        }
         b->parity ^= 1;
     }
     HIP_TRY(hipGetLastError());
@@ -326,6 +336,7 @@ lbmx_status lbmx_batch_create(const lbmx_params *p, int32_t count, void *stream,
         return fail(LBMX_ENOMEM, "host allocation failed");
     b->count = count;
     b->storage = p[0].storage;
+    b->force_model = p[0].force_model;
     size_t total = 0;
     for (int k = 0; k < count; ++k) {
         Derived d;
@@ -337,6 +348,10 @@ lbmx_status lbmx_batch_create(const lbmx_params *p, int32_t count, void *stream,
         if (p[k].storage != b->storage) {
             delete b;
             return fail(LBMX_EINVAL, "cavity %d: all cavities of a batch share one storage", k);
+        }
+        if (p[k].force_model != b->force_model) {
+            delete b;
+            return fail(LBMX_EINVAL, "cavity %d: all cavities of a batch share one force model", k);
         }
         if (p[k].n > 255) {
             delete b;

@@ -57,6 +57,8 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct Derived {
     double u_c, gbeta, nu, alpha, s_nu, tau_t;
     double s[19], tau[7];
+    double tbar[6];   // tau-bar block of Q^-1 (Eq. 35): xx, yy, zz, xy, xz, yz
+    double d_yy;      // D_yy = epsilon (tau-bar_yy - 1/2), Eq. (36) solved for D
 };
 
 // Sec. 4, Eq. (38): Ma = u_c / c_s with c_s^2 = 1/3 (Eq. 13), u_c^2 = g beta dT H
@@ -115,6 +117,36 @@ inline lbmx_status derive(const lbmx_params *p, Derived *d)
         for (int k = 0; k < 7; ++k)
             d->tau[k] = tau[k];
     }
+    if (p->force_model < LBMX_FORCE_EQ15 || p->force_model > LBMX_FORCE_GUO)
+        return fail(LBMX_EINVAL, "force_model = %d not a LBMX_FORCE_* value", p->force_model);
+    if (p->nu_stencil < LBMX_NU_SECOND_ORDER || p->nu_stencil > LBMX_NU_WALL_FLUX)
+        return fail(LBMX_EINVAL, "nu_stencil = %d not a LBMX_NU_* value", p->nu_stencil);
+    // tau-bar block: the diagonal tau_1..tau_3, or Eq. (36) with D = alpha A.
+    const double *A = p->aniso;
+    bool aniso = false;
+    for (int k = 0; k < 6; ++k) {
+        if (!std::isfinite(A[k]))
+            return fail(LBMX_EINVAL, "aniso[%d] is not finite", k);
+        aniso = aniso || A[k] != 0.0;
+    }
+    if (aniso) {
+        if (p->custom_rates)
+            return fail(LBMX_EINVAL, "aniso and custom_rates cannot be combined");
+        // positive definite: leading principal minors > 0 (xx, yy, zz, xy, xz, yz)
+        const double m1 = A[0], m2 = A[0] * A[1] - A[3] * A[3];
+        const double m3 = A[0] * (A[1] * A[2] - A[5] * A[5]) - A[3] * (A[3] * A[2] - A[5] * A[4]) +
+                          A[4] * (A[3] * A[5] - A[1] * A[4]);
+        if (!(m1 > 0.0 && m2 > 0.0 && m3 > 0.0))
+            return fail(LBMX_EINVAL, "aniso tensor is not positive definite");
+        for (int k = 0; k < 6; ++k)
+            d->tbar[k] = (k < 3 ? 0.5 : 0.0) + d->alpha * A[k] / 0.25;
+    } else {
+        d->tbar[0] = d->tau[1];
+        d->tbar[1] = d->tau[2];
+        d->tbar[2] = d->tau[3];
+        d->tbar[3] = d->tbar[4] = d->tbar[5] = 0.0;
+    }
+    d->d_yy = 0.25 * (d->tbar[1] - 0.5);
     return LBMX_OK;
 }
 
@@ -138,10 +170,35 @@ Rates<T> make_rates(const lbmx_params *p, const Derived &d)
     r.mx = T(d.s[16] / 8.0);
     r.my = T(d.s[17] / 8.0);
     r.mz = T(d.s[18] / 8.0);
-    // Q = (Q^-1)^-1 for diagonal Q^-1 (Eq. 35), over |N_k|^2 of Eq. (32).
-    r.t1 = T(1.0 / d.tau[1] / 2.0);
-    r.t2 = T(1.0 / d.tau[2] / 2.0);
-    r.t3 = T(1.0 / d.tau[3] / 2.0);
+    // Guo's forcing: (1 - s_k/2) / |M_k|^2, same rows.
+    const int rows[15] = {1, 2, 4, 6, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18};
+    const double norms[15] = {2394, 252, 40, 40, 40, 36, 72, 12, 24, 4, 4, 4, 8, 8, 8};
+    T *h[15] = {&r.he, &r.heps, &r.hqx, &r.hqy, &r.hqz, &r.hpxx, &r.hpixx, &r.hpww,
+                &r.hpiww, &r.hpxy, &r.hpyz, &r.hpxz, &r.hmx, &r.hmy, &r.hmz};
+    for (int k = 0; k < 15; ++k)
+        *h[k] = T((1.0 - 0.5 * d.s[rows[k]]) / norms[k]);
+    // Q = (Q^-1)^-1 (Eq. 35) over |N_k|^2 of Eq. (32) (2 for n_1..n_3).  The
+    // tau-bar block is inverted as a symmetric 3x3 (cofactors); a diagonal
+    // block takes plain reciprocals.
+    const double *b = d.tbar;  // xx, yy, zz, xy, xz, yz
+    if (b[3] == 0.0 && b[4] == 0.0 && b[5] == 0.0) {
+        r.q11 = T(1.0 / b[0] / 2.0);
+        r.q22 = T(1.0 / b[1] / 2.0);
+        r.q33 = T(1.0 / b[2] / 2.0);
+        r.q12 = r.q13 = r.q23 = T(0);
+    } else {
+        const double c11 = b[1] * b[2] - b[5] * b[5], c22 = b[0] * b[2] - b[4] * b[4];
+        const double c33 = b[0] * b[1] - b[3] * b[3];
+        const double c12 = b[4] * b[5] - b[3] * b[2], c13 = b[3] * b[5] - b[4] * b[1];
+        const double c23 = b[3] * b[4] - b[0] * b[5];
+        const double det = b[0] * c11 + b[3] * c12 + b[4] * c13;
+        r.q11 = T(c11 / det / 2.0);
+        r.q22 = T(c22 / det / 2.0);
+        r.q33 = T(c33 / det / 2.0);
+        r.q12 = T(c12 / det / 2.0);
+        r.q13 = T(c13 / det / 2.0);
+        r.q23 = T(c23 / det / 2.0);
+    }
     r.t4 = T(1.0 / d.tau[4] / 42.0);
     r.t5 = T(1.0 / d.tau[5] / 12.0);
     r.t6 = T(1.0 / d.tau[6] / 4.0);
@@ -178,7 +235,29 @@ struct View {
     double theta_hot, theta_cold;
     bool off32;
     hipStream_t stream;
+    double vshift;     // g beta / 2 for Guo's forcing (reported velocity), else 0
+    double theta_ref;
+    int nu_stencil;
+    double d_yy;       // for the wall-flux Nu stencil
 };
+
+inline View make_view(char *lat, const lbmx_params &p, const Derived &d, bool off32,
+                      hipStream_t stream)
+{
+    View v;
+    v.lat = lat;
+    v.n = p.n;
+    v.wall_type = p.wall_type;
+    v.theta_hot = p.theta_hot;
+    v.theta_cold = p.theta_cold;
+    v.off32 = off32;
+    v.stream = stream;
+    v.vshift = p.force_model == LBMX_FORCE_GUO ? 0.5 * d.gbeta * p.buoyancy_scale : 0.0;
+    v.theta_ref = p.theta_ref;
+    v.nu_stencil = p.nu_stencil;
+    v.d_yy = d.d_yy;
+    return v;
+}
 
 template <class St>
 Geometry<typename St::T> geometry(const View &v)
@@ -214,10 +293,10 @@ lbmx_status launch_macro(const View &v, double *r, double *u, double *w3, double
     const unsigned blocks = (unsigned)((cells + 255) / 256);
     if (v.off32)
         hipLaunchKernelGGL((k_macro<St, true>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
-                           geometry<St>(v), r, u, w3, w, th);
+                           geometry<St>(v), v.vshift, v.theta_ref, r, u, w3, w, th);
     else
         hipLaunchKernelGGL((k_macro<St, false>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
-                           geometry<St>(v), r, u, w3, w, th);
+                           geometry<St>(v), v.vshift, v.theta_ref, r, u, w3, w, th);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -247,10 +326,10 @@ lbmx_status launch_nu(const View &v, double *scratch, double *map)
     const int threads = n <= 64 ? 64 : (n <= 128 ? 128 : 256);
     if (v.off32)
         hipLaunchKernelGGL((k_nu_rows<St, true>), dim3(n), dim3(threads), 0, v.stream, v.lat,
-                           geometry<St>(v), v.theta_hot, scratch, map);
+                           geometry<St>(v), v.theta_hot, v.nu_stencil, v.d_yy, scratch, map);
     else
         hipLaunchKernelGGL((k_nu_rows<St, false>), dim3(n), dim3(threads), 0, v.stream, v.lat,
-                           geometry<St>(v), v.theta_hot, scratch, map);
+                           geometry<St>(v), v.theta_hot, v.nu_stencil, v.d_yy, scratch, map);
     hipLaunchKernelGGL(k_nu_final<0>, dim3(1), dim3(256), 0, v.stream, scratch, n, out);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;

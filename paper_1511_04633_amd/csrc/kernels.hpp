@@ -295,8 +295,9 @@ __device__ __forceinline__ void put(char *__restrict__ dst, size_t node,
 }
 
 // -------------------------------------------------------------- step kernel
-// One thread per node; block (bx, by) over (x, y), grid.z = z.
-template <class St, bool kOff32>
+// One thread per node; block (bx, by) over (x, y), grid.z = z.  kForce is
+// the force model (LBMX_FORCE_*).
+template <class St, bool kOff32, int kForce>
 __global__ __launch_bounds__(1024) void k_step(const char *__restrict__ src, char *__restrict__ dst,
                                                Geometry<typename St::T> geo,
                                                Rates<typename St::T> rates)
@@ -309,7 +310,7 @@ __global__ __launch_bounds__(1024) void k_step(const char *__restrict__ src, cha
         return;
     T f[19], g[7];
     pull<St, kOff32>(src, geo, x, y, z, f, g);
-    collide<T>(f, g, rates);
+    collide<T, kForce>(f, g, rates);
     put<St, kOff32>(dst, size_t(x) + size_t(geo.n) * (size_t(y) + size_t(geo.n) * z), f, g);
 }
 
@@ -438,10 +439,13 @@ __global__ __launch_bounds__(256) void k_unstream(char *__restrict__ dst,
 
 // ------------------------------------------------------------ read kernels
 // Macroscopic fields at time t: rho, u = j / rho, theta (double outputs).
+// Guo's forcing reports u_z = j_z / rho + vshift (theta - theta_ref) with
+// vshift = g beta / 2 (the half-force velocity); vshift = 0 otherwise.
 template <class St, bool kOff32>
 __global__ __launch_bounds__(256) void k_macro(const char *__restrict__ src,
-                                               Geometry<typename St::T> geo, double *rho,
-                                               double *ux, double *uy, double *uz, double *theta)
+                                               Geometry<typename St::T> geo, double vshift,
+                                               double theta_ref, double *rho, double *ux,
+                                               double *uy, double *uz, double *theta)
 {
     using T = typename St::T;
     const int n = geo.n;
@@ -465,7 +469,7 @@ __global__ __launch_bounds__(256) void k_macro(const char *__restrict__ src,
     if (rho) rho[c] = r;
     if (ux) ux[c] = j[0] / r;
     if (uy) uy[c] = j[1] / r;
-    if (uz) uz[c] = j[2] / r;
+    if (uz) uz[c] = vshift != 0.0 ? j[2] / r + vshift * (th - theta_ref) : j[2] / r;
     if (theta) theta[c] = th;
 }
 
@@ -543,12 +547,17 @@ __device__ __forceinline__ void block_reduce4(double &sum, double &line, double 
 }
 
 // One block per z row of the hot wall (y = 0).  Local Nu (Eq. 39) from the
-// two wall-adjacent nodes, second order: dtheta/dy = (9 th0 - th1 - 8 th_w)/3.
+// wall-adjacent nodes, by stencil (LBMX_NU_*):
+//   0  second order, dtheta/dy = (9 th0 - th1 - 8 th_w)/3;
+//   1  first order, dtheta/dy = 2 (th0 - th_w);
+//   2  energy crossing the wall links, q = 2 (g_+y - th_w / 8), as -q / D_yy
+//      (g_+y at the wall node is the population that came from the wall).
 // partial[z] = {sum over x, X = 0.5 line contribution, max, non-finite count}.
 template <class St, bool kOff32>
 __global__ __launch_bounds__(256) void k_nu_rows(const char *__restrict__ src,
                                                  Geometry<typename St::T> geo, double theta_hot,
-                                                 double *partial, double *map)
+                                                 int stencil, double d_yy, double *partial,
+                                                 double *map)
 {
     using T = typename St::T;
     const int n = geo.n;
@@ -557,13 +566,20 @@ __global__ __launch_bounds__(256) void k_nu_rows(const char *__restrict__ src,
     for (int x = threadIdx.x; x < n; x += blockDim.x) {
         T f[19], g0[7], g1[7];
         pull<St, kOff32>(src, geo, x, 0, z, f, g0);
-        pull<St, kOff32>(src, geo, x, 1, z, f, g1);
         double th0 = 0.0, th1 = 0.0;
-        for (int i = 0; i < 7; ++i) {
+        for (int i = 0; i < 7; ++i)
             th0 += double(g0[i]);
-            th1 += double(g1[i]);
+        double nu;
+        if (stencil == 1) {
+            nu = -double(n) * 2.0 * (th0 - theta_hot);
+        } else if (stencil == 2) {
+            nu = double(n) * 2.0 * (double(g0[3]) - 0.125 * theta_hot) / d_yy;
+        } else {
+            pull<St, kOff32>(src, geo, x, 1, z, f, g1);
+            for (int i = 0; i < 7; ++i)
+                th1 += double(g1[i]);
+            nu = -double(n) * (9.0 * th0 - th1 - 8.0 * theta_hot) / 3.0;
         }
-        const double nu = -double(n) * (9.0 * th0 - th1 - 8.0 * theta_hot) / 3.0;
         if (map)
             map[x + (size_t)n * z] = nu;
         if (!isfinite(nu)) {

@@ -62,8 +62,7 @@ double *scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L
 
 View view(lbmx_cavity *h)
 {
-    return View{lattice(h, h->cur), h->p.n, h->p.wall_type, h->p.theta_hot, h->p.theta_cold,
-                h->off32, h->stream};
+    return make_view(lattice(h, h->cur), h->p, h->d, h->off32, h->stream);
 }
 
 // One row of up to 256 nodes along x per block row; up to 256 threads per
@@ -78,8 +77,8 @@ void default_launch(int n, int *bx, int *by)
     *by = b;
 }
 
-template <class St>
-lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
+template <class St, int kForce>
+void launch_step_kernels(lbmx_cavity *h, int64_t nsteps)
 {
     using T = typename St::T;
     const Geometry<T> geo = geometry<St>(view(h));
@@ -89,13 +88,23 @@ lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
     dim3 grid((n + h->bx - 1) / h->bx, (n + h->by - 1) / h->by, n);
     for (int64_t s = 0; s < nsteps; ++s) {
         if (h->off32)
-            hipLaunchKernelGGL((k_step<St, true>), grid, block, 0, h->stream, lattice(h, h->cur),
-                               lattice(h, 1 - h->cur), geo, rates);
+            hipLaunchKernelGGL((k_step<St, true, kForce>), grid, block, 0, h->stream,
+                               lattice(h, h->cur), lattice(h, 1 - h->cur), geo, rates);
         else
-            hipLaunchKernelGGL((k_step<St, false>), grid, block, 0, h->stream, lattice(h, h->cur),
-                               lattice(h, 1 - h->cur), geo, rates);
+            hipLaunchKernelGGL((k_step<St, false, kForce>), grid, block, 0, h->stream,
+                               lattice(h, h->cur), lattice(h, 1 - h->cur), geo, rates);
         h->cur = 1 - h->cur;
         h->t += 1;
+    }
+}
+
+template <class St>
+lbmx_status launch_steps(lbmx_cavity *h, int64_t nsteps)
+{
+    switch (h->p.force_model) {
+    case LBMX_FORCE_EQ15_RHO: launch_step_kernels<St, LBMX_FORCE_EQ15_RHO>(h, nsteps); break;
+    case LBMX_FORCE_GUO: launch_step_kernels<St, LBMX_FORCE_GUO>(h, nsteps); break;
+    default: launch_step_kernels<St, LBMX_FORCE_EQ15>(h, nsteps);
     }
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
@@ -108,7 +117,7 @@ lbmx_status check_handle(const lbmx_cavity *h)
     return LBMX_OK;
 }
 
-// Checkpoint file header (no padding: 8 + 4 + 4 + 280 + 3 x 8 bytes).
+// Checkpoint file header (no padding: 8 + 4 + 4 + 336 + 3 x 8 bytes).
 constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'X', 'C', 'K', 'P', 'T'};
 constexpr uint32_t kCkptVersion = 1;
 constexpr size_t kCkptChunk = size_t(64) << 20;  // staging buffer bytes
@@ -121,8 +130,8 @@ struct CkptHeader {
     uint64_t lattice_bytes;
     uint64_t slab_nodes;
 };
-static_assert(sizeof(lbmx_params) == 280, "lbmx_params is expected to have no padding");
-static_assert(sizeof(CkptHeader) == 320, "checkpoint header layout");
+static_assert(sizeof(lbmx_params) == 336, "lbmx_params is expected to have no padding");
+static_assert(sizeof(CkptHeader) == 376, "checkpoint header layout");
 
 // The parameter set as it matters to the state: custom rates only if used.
 lbmx_params canonical(const lbmx_params &p)

@@ -48,7 +48,14 @@ class lbmx_params(ctypes.Structure):
         ("theta_ref", ctypes.c_double), ("buoyancy_scale", ctypes.c_double),
         ("storage", ctypes.c_int32), ("custom_rates", ctypes.c_int32),
         ("s", ctypes.c_double * 19), ("tau", ctypes.c_double * 7),
+        ("force_model", ctypes.c_int32), ("nu_stencil", ctypes.c_int32),
+        ("aniso", ctypes.c_double * 6),
     ]
+
+
+# lbmx.h force models and Nu stencils, by name
+FORCE_MODELS = {"eq15": 0, "eq15_rho": 1, "guo": 2}
+NU_STENCILS = {"second_order": 0, "first_order": 1, "wall_flux": 2}
 
 
 class lbmx_nu(ctypes.Structure):
@@ -144,13 +151,20 @@ def _dptr(a: Optional[np.ndarray]):
 
 
 def make_params(n=16, wall_type=1, ra=1e3, pr=0.71, ma=0.1, theta_hot=0.5, theta_cold=-0.5,
-                theta_ref=0.0, buoyancy_scale=1.0, storage="f32", s=None, tau=None) -> lbmx_params:
+                theta_ref=0.0, buoyancy_scale=1.0, storage="f32", s=None, tau=None,
+                force_model=0, nu_stencil=0, aniso=None) -> lbmx_params:
+    """force_model / nu_stencil: an int or a name of FORCE_MODELS / NU_STENCILS;
+    aniso: (A_xx, A_yy, A_zz, A_xy, A_xz, A_yz) with D = alpha A, None = isotropic."""
     p = lbmx_params()
     _check(load().lbmx_params_default(ctypes.byref(p)))
     p.n, p.wall_type, p.ra, p.pr, p.ma = int(n), int(wall_type), ra, pr, ma
     p.theta_hot, p.theta_cold, p.theta_ref = theta_hot, theta_cold, theta_ref
     p.buoyancy_scale = buoyancy_scale
     p.storage = STORAGE[storage] if isinstance(storage, str) else int(storage)
+    p.force_model = FORCE_MODELS[force_model] if isinstance(force_model, str) else int(force_model)
+    p.nu_stencil = NU_STENCILS[nu_stencil] if isinstance(nu_stencil, str) else int(nu_stencil)
+    if aniso is not None:
+        p.aniso[:] = [float(v) for v in aniso]
     if s is not None or tau is not None:
         if s is None or tau is None:
             raise ValueError("custom rates need both s (19) and tau (7)")

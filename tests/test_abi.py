@@ -37,8 +37,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_struct_layout_matches_header():
-    """The ctypes mirror has the C struct's size: 4+4 + 7*8 + 4+4 + 19*8 + 7*8."""
-    assert ctypes.sizeof(L.lbmx_params) == 8 + 56 + 8 + 152 + 56
+    """The ctypes mirror has the C struct's size: 4+4 + 7*8 + 4+4 + 19*8 + 7*8
+    + 4+4 + 6*8 (no padding anywhere)."""
+    assert ctypes.sizeof(L.lbmx_params) == 8 + 56 + 8 + 152 + 56 + 8 + 48
     assert ctypes.sizeof(L.lbmx_nu) == 40
 
 
@@ -107,3 +108,28 @@ def test_batch_create_rejects_sizes_before_any_device_call():
     for storage in ("f64", "f32", "f16_f32"):
         ws = L.workspace_bytes(L.make_params(n=255, storage=storage))
         assert ws // 2 < 2 ** 32, storage
+
+
+def test_variant_parameters_validated():
+    """Force model, Nu stencil and the anisotropy tensor are checked on the
+    host: unknown values, a tensor that is not positive definite and aniso
+    together with custom rates are EINVAL; valid sets derive."""
+    L.derive(L.make_params(force_model="guo", nu_stencil="wall_flux",
+                           aniso=[1.0, 0.6, 0.8, 0.3, 0.2, -0.25]))
+    for kw in (dict(force_model=3), dict(force_model=-1), dict(nu_stencil=3),
+               dict(aniso=[1, 1, 1, 1.5, 0, 0]), dict(aniso=[-1, 1, 1, 0, 0, 0]),
+               dict(aniso=[1, 1, 0, 0, 0, 0]), dict(aniso=[1, 1, 1, 0, 0, float("nan")]),
+               dict(aniso=[1, 1, 1, 0, 0, 0], s=[1.0] * 19, tau=[1.0] * 7)):
+        with pytest.raises(L.LbmxError) as e:
+            L.derive(L.make_params(**kw))
+        assert e.value.status == 1, kw
+
+
+def test_batch_rejects_mixed_force_models():
+    lib = L.load()
+    arr = (L.lbmx_params * 2)()
+    arr[0] = L.make_params(n=16, force_model=0)
+    arr[1] = L.make_params(n=16, force_model=2)
+    h = ctypes.c_void_p()
+    assert lib.lbmx_batch_create(arr, 2, None, ctypes.byref(h)) == 1
+    assert b"force model" in lib.lbmx_last_error()
