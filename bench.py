@@ -118,6 +118,10 @@ def main():
                     help="skip timing a plain device copy of the same bytes")
     ap.add_argument("--steady-types", default="1",
                     help="wall types timed to steady at 128^3 Ra 1e5 (comma list; '' = skip)")
+    ap.add_argument("--force-model", type=int, default=0, choices=[0, 1, 2],
+                    help="0 Eq. 15 (default), 1 Eq. 15 / rho, 2 Guo's forcing")
+    ap.add_argument("--aniso", default="",
+                    help="A_xx,A_yy,A_zz,A_xy,A_xz,A_yz: anisotropic diffusion D = alpha A")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -132,8 +136,11 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     n = args.n
+    aniso = [float(v) for v in args.aniso.split(",")] if args.aniso else None
+    variant = args.force_model != 0 or aniso is not None
     cav = lbmx.Cavity(n=n, wall_type=args.wall_type, ra=args.ra, storage=args.storage,
-                      theta0=inputs.theta_noise(n, 20151115))
+                      theta0=inputs.theta_noise(n, 20151115), force_model=args.force_model,
+                      aniso=aniso)
     if args.launch:
         bx, by = (int(v) for v in args.launch.split(","))
         cav.set_launch(bx, by)
@@ -155,7 +162,7 @@ def main():
     bpc = lbmx.bytes_per_cell(args.storage)
     kernel_s = ev_ms / 1e3 / args.steps
     achieved = cells * bpc / kernel_s / 1e9
-    tr = counter_traffic(args.storage, n)
+    tr = None if variant else counter_traffic(args.storage, n)
     dtype = {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32",
              "f16_f32": "f16-flow+f32-energy-storage/f32",
              "bf16_f32": "bf16-flow+f32-energy-storage/f32"}
@@ -185,6 +192,9 @@ def main():
                      "copy_achieved": None if copy_gbs is None else round(copy_gbs, 1)},
         "nu3d_after": nu["nu3d"],
     }
+    if variant:
+        line["config"]["force_model"] = args.force_model
+        line["config"]["aniso"] = aniso
     del cav
     torch.cuda.empty_cache()
     steady = []
