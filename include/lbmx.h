@@ -165,7 +165,8 @@ lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host)
  * parameter set, its time t and its current lattice (the post-collision
  * populations of t - 1, in the storage format, bit for bit) to `path`;
  * lbmx_load reads such a file into a cavity created with the same parameter
- * set (the custom s, tau arrays are compared only when custom_rates = 1), so
+ * set (the custom s, tau arrays are compared only when custom_rates = 1, the
+ * Nu stencil not at all: it only reads the state), so
  * that stepping on continues bitwise as the saved cavity would.  The file is
  * a 376-byte header (magic "LBMXCKPT", version 1, sizeof(lbmx_params), the
  * parameters, t, lattice bytes, nodes per slab; host byte order) followed by

@@ -133,10 +133,12 @@ struct CkptHeader {
 static_assert(sizeof(lbmx_params) == 336, "lbmx_params is expected to have no padding");
 static_assert(sizeof(CkptHeader) == 376, "checkpoint header layout");
 
-// The parameter set as it matters to the state: custom rates only if used.
+// The parameter set as it matters to the state: custom rates only if used;
+// the Nu stencil only reads the state.
 lbmx_params canonical(const lbmx_params &p)
 {
     lbmx_params q = p;
+    q.nu_stencil = 0;
     if (!q.custom_rates) {
         std::memset(q.s, 0, sizeof q.s);
         std::memset(q.tau, 0, sizeof q.tau);

@@ -73,6 +73,13 @@ def test_rejects_mismatch_and_damage(tmp_path):
         assert c.t == 3
         c.close()
 
+    # the Nu stencil only reads the state: a checkpoint loads under another one
+    c = L.Cavity(n=16, wall_type=1, ra=1e4, storage="f32", nu_stencil=2)
+    c.load(path)
+    fc, gc = c.get_populations()
+    assert np.array_equal(f0, fc) and np.array_equal(g0, gc) and c.t == 20
+    c.close()
+
     raw = open(path, "rb").read()
     bad = os.path.join(tmp_path, "bad.ckpt")
     open(bad, "wb").write(b"NOTACKPT" + raw[8:])
