@@ -449,10 +449,12 @@ static int thermal_wall(const oracle *o, int axis, int side, int y, double *thet
     return 0; /* Type 3, z walls: Eq. (10), adiabatic */
 }
 
-oracle *oracle_create(int n, int wall_type, double ra, double pr, double ma,
-                      double theta_hot, double theta_cold, double theta_ref,
-                      double buoyancy_scale, const double *s19, const double *tau7,
-                      const double *aniso6, int force_model, const double *theta0)
+/* The parameter part of an oracle, without state arrays: enough for the
+ * single-node step and the Nusselt numbers of a state held elsewhere. */
+oracle *oracle_create_params(int n, int wall_type, double ra, double pr, double ma,
+                             double theta_hot, double theta_cold, double theta_ref,
+                             double buoyancy_scale, const double *s19, const double *tau7,
+                             const double *aniso6, int force_model)
 {
     if (n < 2 || wall_type < 0 || wall_type > 3 || ra <= 0 || pr <= 0 || ma <= 0 ||
         force_model < 0 || force_model > 2)
@@ -510,7 +512,19 @@ oracle *oracle_create(int n, int wall_type, double ra, double pr, double ma,
         return NULL;
     }
     memcpy(o->qmat, qm, sizeof(qm));
+    o->t = 0;
+    return o;
+}
 
+oracle *oracle_create(int n, int wall_type, double ra, double pr, double ma,
+                      double theta_hot, double theta_cold, double theta_ref,
+                      double buoyancy_scale, const double *s19, const double *tau7,
+                      const double *aniso6, int force_model, const double *theta0)
+{
+    oracle *o = oracle_create_params(n, wall_type, ra, pr, ma, theta_hot, theta_cold, theta_ref,
+                                     buoyancy_scale, s19, tau7, aniso6, force_model);
+    if (!o)
+        return NULL;
     size_t cells = (size_t)n * n * n;
     o->f = (double *)malloc(sizeof(double) * Q19 * cells);
     o->fp = (double *)malloc(sizeof(double) * Q19 * cells);
@@ -663,7 +677,20 @@ void oracle_macro(const oracle *o, double *rho, double *ux, double *uy, double *
 /* Hot-wall Nusselt numbers, Eqs. (39)-(41) with readings R17, R18 and the
  * stencil choice of the header (theta_h - theta_c = 1, as in Eq. 38).
  * out = {Nu_3D, Nu_2D, Nu_max}; map (n*n, x fastest then z) may be NULL. */
+static void nusselt_of(const oracle *o, const double *gs, int stencil, double *out, double *map);
+
 void oracle_nusselt(const oracle *o, int stencil, double *out, double *map)
+{
+    nusselt_of(o, o->g, stencil, out, map);
+}
+
+/* The same for a state g held by the caller (n^3 per population, [i][cell]). */
+void oracle_nusselt_state(const oracle *o, const double *g, int stencil, double *out, double *map)
+{
+    nusselt_of(o, g, stencil, out, map);
+}
+
+static void nusselt_of(const oracle *o, const double *gs, int stencil, double *out, double *map)
 {
     const int n = o->n;
     const size_t cells = (size_t)n * n * n;
@@ -676,8 +703,8 @@ void oracle_nusselt(const oracle *o, int stencil, double *out, double *map)
             size_t c0 = (size_t)x + (size_t)n * (0 + (size_t)n * z);
             size_t c1 = (size_t)x + (size_t)n * (1 + (size_t)n * z);
             for (int i = 0; i < Q7; ++i) {
-                th0 += o->g[i * cells + c0];
-                th1 += o->g[i * cells + c1];
+                th0 += gs[i * cells + c0];
+                th1 += gs[i * cells + c1];
             }
             /* Nu = -d theta / dY with Y = y / H, H = n. */
             double nu_loc;
@@ -687,7 +714,7 @@ void oracle_nusselt(const oracle *o, int stencil, double *out, double *map)
                 /* g_+y at the wall node entered from the wall in the last
                  * streaming: g_in = -g*_out + 2 w_T theta_h, so the net flux
                  * into the fluid is g_in - g*_out = 2 (g_in - w_T theta_h). */
-                const double g_in = o->g[3 * cells + c0];
+                const double g_in = gs[3 * cells + c0];
                 const double q = 2.0 * (g_in - W7[3] * o->theta_hot);
                 nu_loc = n * q / d_yy;
             } else {
@@ -722,4 +749,70 @@ void oracle_set_state(oracle *o, const double *f, const double *g, long t)
     if (f) memcpy(o->f, f, sizeof(double) * Q19 * cells);
     if (g) memcpy(o->g, g, sizeof(double) * Q7 * cells);
     o->t = t;
+}
+
+/* One time step at the single node (x, y, z), for a state S_t held by the
+ * caller (f: 19 n^3, g: 7 n^3, [i][cell]): the streaming of oracle_step read
+ * from the destination's side.  Population i arrives from x - e_i after that
+ * node's collision; where x - e_i lies outside, it is node x's own
+ * post-collision population of the opposite direction reflected at the wall
+ * (Eq. 8, R12; for g the rule of the wall crossed, R10).  fo, go: S_{t+1}. */
+void oracle_step_node(const oracle *o, const double *f, const double *g, int x, int y, int z,
+                      double *fo, double *go)
+{
+    const int n = o->n;
+    const size_t cells = (size_t)n * n * n;
+    double fi[Q19], gi[Q7], fp[Q19], gp[Q7], own_f[Q19], own_g[Q7];
+    const int pos[3] = {x, y, z};
+    size_t c = (size_t)x + (size_t)n * (y + (size_t)n * z);
+    for (int i = 0; i < Q19; ++i) fi[i] = f[i * cells + c];
+    for (int i = 0; i < Q7; ++i) gi[i] = g[i * cells + c];
+    collide_node(o, fi, gi, own_f, own_g);
+
+    for (int i = 0; i < Q19; ++i) {
+        int sp[3], inside = 1;
+        for (int d = 0; d < 3; ++d) {
+            sp[d] = pos[d] - E19[i][d];
+            if (o->wall_type == 0)
+                sp[d] = (sp[d] + n) % n;
+            else if (sp[d] < 0 || sp[d] >= n)
+                inside = 0;
+        }
+        if (!inside) {
+            fo[i] = own_f[opposite19(i)];  /* half-way bounce-back */
+            continue;
+        }
+        size_t sc = (size_t)sp[0] + (size_t)n * (sp[1] + (size_t)n * sp[2]);
+        for (int k = 0; k < Q19; ++k) fi[k] = f[k * cells + sc];
+        for (int k = 0; k < Q7; ++k) gi[k] = g[k * cells + sc];
+        collide_node(o, fi, gi, fp, gp);
+        fo[i] = fp[i];
+    }
+    for (int i = 0; i < Q7; ++i) {
+        int sp[3], inside = 1, axis = -1, side = 0;
+        for (int d = 0; d < 3; ++d) {
+            sp[d] = pos[d] - E7[i][d];
+            if (o->wall_type == 0)
+                sp[d] = (sp[d] + n) % n;
+            else if (sp[d] < 0 || sp[d] >= n) {
+                inside = 0;
+                axis = d;
+                side = -E7[i][d];  /* the opposite direction leaves through this side */
+            }
+        }
+        if (!inside) {
+            const int ib = opposite7(i);
+            double tw;
+            if (thermal_wall(o, axis, side, y, &tw))
+                go[i] = -own_g[ib] + 2.0 * W7[i] * tw; /* R10 */
+            else
+                go[i] = own_g[ib];                     /* R10 */
+            continue;
+        }
+        size_t sc = (size_t)sp[0] + (size_t)n * (sp[1] + (size_t)n * sp[2]);
+        for (int k = 0; k < Q19; ++k) fi[k] = f[k * cells + sc];
+        for (int k = 0; k < Q7; ++k) gi[k] = g[k * cells + sc];
+        collide_node(o, fi, gi, fp, gp);
+        go[i] = gp[i];
+    }
 }

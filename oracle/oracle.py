@@ -45,6 +45,14 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         build(force=False)
         L = ctypes.CDLL(_LIB)
+        L.oracle_create_params.restype = ctypes.c_void_p
+        L.oracle_create_params.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                           _dp, _dp, _dp, ctypes.c_int]
+        L.oracle_step_node.argtypes = [ctypes.c_void_p, _dp, _dp, ctypes.c_int, ctypes.c_int,
+                                       ctypes.c_int, _dp, _dp]
+        L.oracle_nusselt_state.argtypes = [ctypes.c_void_p, _dp, ctypes.c_int, _dp, _dp]
         L.oracle_create.restype = ctypes.c_void_p
         L.oracle_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -148,11 +156,13 @@ class Oracle:
     force_model: 0 (Eq. 15, reading R3), 1 (Eq. 15 divided by rho), 2 (Guo).
     theta0: initial temperature field (n^3, x fastest); the initial state is
     f_i = w_i, g_i = w_T,i * theta0.
+    state: False builds the parameters only (no n^3 arrays): such an oracle
+    serves step_node() and nusselt_of() on a state held by the caller.
     """
 
     def __init__(self, n, wall_type=1, ra=1e3, pr=0.71, ma=0.1, theta_hot=0.5,
                  theta_cold=-0.5, theta_ref=0.0, buoyancy_scale=1.0, s19=None,
-                 tau7=None, aniso=None, force_model=0, theta0=None):
+                 tau7=None, aniso=None, force_model=0, theta0=None, state=True):
         self.n = int(n)
         self.cells = self.n ** 3
         s19 = None if s19 is None else np.ascontiguousarray(s19, dtype=np.float64)
@@ -162,9 +172,15 @@ class Oracle:
             theta0 = np.ascontiguousarray(theta0, dtype=np.float64).reshape(-1)
             assert theta0.size == self.cells
         self._keep = (s19, tau7, aniso, theta0)
-        h = lib().oracle_create(self.n, int(wall_type), ra, pr, ma, theta_hot, theta_cold,
-                                theta_ref, buoyancy_scale, _ptr(s19), _ptr(tau7), _ptr(aniso),
-                                int(force_model), _ptr(theta0))
+        if state:
+            h = lib().oracle_create(self.n, int(wall_type), ra, pr, ma, theta_hot, theta_cold,
+                                    theta_ref, buoyancy_scale, _ptr(s19), _ptr(tau7), _ptr(aniso),
+                                    int(force_model), _ptr(theta0))
+        else:
+            h = lib().oracle_create_params(self.n, int(wall_type), ra, pr, ma, theta_hot,
+                                           theta_cold, theta_ref, buoyancy_scale, _ptr(s19),
+                                           _ptr(tau7), _ptr(aniso), int(force_model))
+        self.has_state = bool(state)
         if not h:
             raise ValueError("oracle_create rejected the parameters")
         self._h = ctypes.c_void_p(h)
@@ -185,12 +201,40 @@ class Oracle:
         lib().oracle_derived_of(self._h, _ptr(out))
         return dict(zip(["u_c", "gbeta", "nu", "alpha", "s_nu", "tau_t"], out.tolist()))
 
+    def _need_state(self):
+        if not self.has_state:
+            raise RuntimeError("this oracle holds parameters only (state=False)")
+
     def step(self, nsteps: int = 1):
+        self._need_state()
         lib().oracle_step(self._h, int(nsteps))
         return self
 
+    def step_node(self, f, g, x, y, z):
+        """S_{t+1} at node (x, y, z) from a caller's state S_t (f: 19 x n^3,
+        g: 7 x n^3 float64, population-major); returns (f19, g7)."""
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        assert f.size == 19 * self.cells and g.size == 7 * self.cells
+        fo, go = np.zeros(19), np.zeros(7)
+        lib().oracle_step_node(self._h, _ptr(f), _ptr(g), int(x), int(y), int(z), _ptr(fo), _ptr(go))
+        return fo, go
+
+    def nusselt_of(self, g, stencil=0, with_map=False):
+        """nusselt() of a caller's state g (7 x n^3 float64)."""
+        g = np.ascontiguousarray(g, dtype=np.float64)
+        assert g.size == 7 * self.cells
+        out = np.zeros(3)
+        mp = np.zeros(self.n * self.n) if with_map else None
+        lib().oracle_nusselt_state(self._h, _ptr(g), int(stencil), _ptr(out), _ptr(mp))
+        d = {"nu3d": out[0], "nu2d": out[1], "numax": out[2]}
+        if with_map:
+            d["map"] = mp.reshape(self.n, self.n)
+        return d
+
     def macro(self):
         """(rho, ux, uy, uz, theta), each shaped (n, n, n) indexed [z, y, x]."""
+        self._need_state()
         arrs = [np.zeros(self.cells) for _ in range(5)]
         lib().oracle_macro(self._h, *[_ptr(a) for a in arrs])
         sh = (self.n,) * 3
@@ -199,6 +243,7 @@ class Oracle:
     def nusselt(self, with_map=False, stencil=0):
         """Hot-wall Nu family; stencil 0 (second order), 1 (first order),
         2 (energy flux of the wall links)."""
+        self._need_state()
         out = np.zeros(3)
         mp = np.zeros(self.n * self.n) if with_map else None
         lib().oracle_nusselt(self._h, int(stencil), _ptr(out), _ptr(mp))
@@ -208,12 +253,14 @@ class Oracle:
         return d
 
     def get_state(self):
+        self._need_state()
         f = np.zeros(19 * self.cells)
         g = np.zeros(7 * self.cells)
         lib().oracle_get_state(self._h, _ptr(f), _ptr(g))
         return f.reshape(19, self.cells), g.reshape(7, self.cells)
 
     def set_state(self, f, g, t=0):
+        self._need_state()
         f = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
         g = np.ascontiguousarray(g, dtype=np.float64).reshape(-1)
         assert f.size == 19 * self.cells and g.size == 7 * self.cells

@@ -216,3 +216,34 @@ def test_anisotropic_mode_decay(kvec):
     r1, r2 = _aniso_decay_ratio(16, kvec), _aniso_decay_ratio(32, kvec)
     assert abs(r2 - 1) < 1e-2, (kvec, r1, r2)
     assert abs((4 * r2 - r1) / 3 - 1) < 2.5e-3, (kvec, r1, r2)
+
+
+# ---------------------------------------------------- single-node evaluation
+
+@pytest.mark.parametrize("wall_type,force_model", [(0, 0), (1, 0), (2, 2), (3, 1)])
+def test_step_node_is_oracle_step(wall_type, force_model):
+    """The single-node step (streaming read from the destination) reproduces
+    the whole-lattice step bit for bit at every node of a developed state, for
+    periodic and walled boxes; the Nu of an external state equals nusselt()."""
+    n = 7
+    th0 = np.random.default_rng(15).uniform(-0.2, 0.2, n ** 3)
+    o = O.Oracle(n, wall_type, ra=1e5, theta0=th0, force_model=force_model,
+                 aniso=[1.0, 0.6, 0.8, 0.3, 0.2, -0.25])
+    o.step(40)
+    f0, g0 = o.get_state()
+    o.step(1)
+    f1, g1 = o.get_state()
+    p = O.Oracle(n, wall_type, ra=1e5, force_model=force_model,
+                 aniso=[1.0, 0.6, 0.8, 0.3, 0.2, -0.25], state=False)
+    for z in range(n):
+        for y in range(n):
+            for x in range(n):
+                c = x + n * (y + n * z)
+                fo, go = p.step_node(f0, g0, x, y, z)
+                assert np.array_equal(fo, f1[:, c]) and np.array_equal(go, g1[:, c]), (x, y, z)
+    if wall_type:
+        for st in (0, 1, 2):
+            a, b = o.nusselt(with_map=True, stencil=st), p.nusselt_of(g1, stencil=st, with_map=True)
+            assert np.array_equal(a["map"], b["map"]) and a["nu3d"] == b["nu3d"]
+    with pytest.raises(RuntimeError):
+        p.step(1)
