@@ -19,10 +19,11 @@
 //
 // Backward: the data gradient is the same convolution of the output gradient
 // with the flipped, transposed weights (W'[ci][26-tap][co] = W[co][tap][ci]);
-// the weight gradient is a GEMM over voxels (K = voxels), staged through LDS
-// transposed to [channel][voxel] so that every MFMA operand is one 8-byte
-// LDS read, accumulated in FP32 and added to the global gradient atomically
-// (the bias gradient rides along in the centre-tap blocks).
+// the weight gradient is a GEMM over voxels (K = voxels) for all 27 taps of a
+// brick of voxels at once, staged through LDS transposed to [channel][voxel]
+// so that every MFMA operand is one 8-byte LDS read, accumulated in FP32 and
+// added to the global gradient atomically (the bias gradient is one more
+// MFMA against ones).
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
@@ -53,64 +54,111 @@ __device__ __forceinline__ long long nvox_of(const Dims &d)
 }
 
 // ------------------------------------------------------------- convolution
-// One wavefront: 16 consecutive voxels (flat index), all COT*16 output
-// channels.  Block = 4 wavefronts.
-template <int COT>
+// out[p][co] = bias[co] + sum_{tap, ci} W[co][tap][ci] in[p + off(tap)][ci].
+//
+// A block owns a brick of 16 x 4 x 4 voxels (blockIdx.x) and NCO output
+// channel tiles of 16 (blockIdx.y selects the group).  The brick's input
+// plus a one-voxel halo (18 x 6 x 6 voxels) is staged channel-last in LDS,
+// FC_CC input channels per round, so the MFMA operand "4 consecutive input
+// channels of the voxel at this tap" is one aligned 8-byte LDS read for any
+// tap; the voxel stride is padded to 36 channels (18 words), which puts the
+// 16 voxels read by one quarter-wavefront on distinct LDS banks.  Wave w
+// computes the brick's rows 4w .. 4w+3 (16 voxels each): every weight
+// operand, read from global memory (cache-resident), serves 4 rows, and
+// every input operand serves the NCO channel tiles.  Each lane ends with 4
+// consecutive output channels of one voxel and stores them together.
+constexpr int FC_X = 16, FC_Y = 4, FC_Z = 4;        // brick
+constexpr int FC_HX = FC_X + 2, FC_HY = FC_Y + 2, FC_HZ = FC_Z + 2;
+constexpr int FC_HVOX = FC_HX * FC_HY * FC_HZ;      // 648 halo voxels
+constexpr int FC_CC = 32;                           // input channels per staging round
+constexpr int FC_VSTRIDE = FC_CC + 4;               // LDS elements per halo voxel
+
+template <int NCO>
 __global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, const bf *__restrict__ w,
                                                   const float *__restrict__ bias, void *__restrict__ out,
-                                                  int out_f32, Dims d)
+                                                  int out_f32, Dims d, int nbx, int nby, int nbz)
 {
-    const int lane = threadIdx.x & 63;
-    const long long nv = nvox_of(d);
-    const long long v0 = ((long long)blockIdx.x * 4 + (threadIdx.x >> 6)) * 16;
-    if (v0 >= nv)
-        return;
+    __shared__ __attribute__((aligned(16))) bf xs[FC_HVOX * FC_VSTRIDE];
+    const int Ci = d.Ci, Co = d.Co;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const long long p = v0 + col;
-    const bool pv = p < nv;
-    int x = 0, y = 0, z = 0, b = 0;
-    if (pv) {
-        long long r = p;
-        x = int(r % d.W); r /= d.W;
-        y = int(r % d.H); r /= d.H;
-        z = int(r % d.D);
-        b = int(r / d.D);
-    }
-    f4 acc[COT];
+    int r = blockIdx.x;
+    const int bx = r % nbx; r /= nbx;
+    const int by = r % nby; r /= nby;
+    const int bz = r % nbz;
+    const int b = r / nbz;
+    const int x0 = bx * FC_X, y0 = by * FC_Y, z0 = bz * FC_Z;
+    const int co0 = blockIdx.y * NCO * 16;
+    const size_t wrow = size_t(27) * Ci;  // weights per output channel
+
+    f4 acc[4][NCO];
 #pragma unroll
-    for (int j = 0; j < COT; ++j)
-        acc[j] = f4{0.f, 0.f, 0.f, 0.f};
-    const size_t wrow = size_t(27) * d.Ci;  // weights per output channel
-    for (int tap = 0; tap < 27; ++tap) {
-        const int xs = x + tap % 3 - 1, ys = y + (tap / 3) % 3 - 1, zs = z + tap / 9 - 1;
-        const bool inb = pv && xs >= 0 && xs < d.W && ys >= 0 && ys < d.H && zs >= 0 && zs < d.D;
-        const long long q = (((long long)b * d.D + zs) * d.H + ys) * d.W + xs;
-        const bf *src = in + (inb ? q : 0) * d.Ci + kq * 4;
-        const bf *wt = w + size_t(col) * wrow + size_t(tap) * d.Ci + kq * 4;
-        for (int c0 = 0; c0 < d.Ci; c0 += 16) {
-            s4 bv = s4{0, 0, 0, 0};
-            if (inb)
-                bv = *reinterpret_cast<const s4 *>(src + c0);
+    for (int rr = 0; rr < 4; ++rr)
 #pragma unroll
-            for (int j = 0; j < COT; ++j) {
-                const s4 av = *reinterpret_cast<const s4 *>(wt + size_t(j) * 16 * wrow + c0);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
+        for (int j = 0; j < NCO; ++j)
+            acc[rr][j] = f4{0.f, 0.f, 0.f, 0.f};
+
+    for (int c0 = 0; c0 < Ci; c0 += FC_CC) {
+        const int cc = Ci - c0 < FC_CC ? Ci - c0 : FC_CC;  // 16 or 32
+        const int parts = cc / 4;                          // 8-byte pieces per voxel
+        __syncthreads();
+        for (int i = threadIdx.x; i < FC_HVOX * parts; i += blockDim.x) {
+            const int hv = i / parts, part = i - hv * parts;
+            const int hx = hv % FC_HX, hrow = hv / FC_HX;
+            const int hy = hrow % FC_HY, hz = hrow / FC_HY;
+            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+            uint2 v = make_uint2(0, 0);
+            if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
+                const int q = ((b * d.D + z) * d.H + y) * d.W + x;
+                v = *reinterpret_cast<const uint2 *>(in + size_t(q) * Ci + c0 + part * 4);
+            }
+            *reinterpret_cast<uint2 *>(xs + hv * FC_VSTRIDE + part * 4) = v;
+        }
+        __syncthreads();
+        for (int tap = 0; tap < 27; ++tap) {
+            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+            for (int k16 = 0; k16 < cc; k16 += 16) {
+                s4 a[NCO];
+#pragma unroll
+                for (int j = 0; j < NCO; ++j)
+                    a[j] = *reinterpret_cast<const s4 *>(w + size_t(co0 + j * 16 + col) * wrow +
+                                                         size_t(tap) * Ci + c0 + k16 + kq * 4);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int g = wv * 4 + rr, gy = g % FC_Y, gz = g / FC_Y;
+                    const int hv = ((gz + 1 + dz) * FC_HY + (gy + 1 + dy)) * FC_HX + (col + 1 + dx);
+                    const s4 bv = *reinterpret_cast<const s4 *>(xs + hv * FC_VSTRIDE + k16 + kq * 4);
+#pragma unroll
+                    for (int j = 0; j < NCO; ++j)
+                        acc[rr][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[j], bv, acc[rr][j], 0, 0, 0);
+                }
             }
         }
     }
-    if (!pv)
-        return;
-    const int Co = COT * 16;
 #pragma unroll
-    for (int j = 0; j < COT; ++j) {
+    for (int rr = 0; rr < 4; ++rr) {
+        const int g = wv * 4 + rr;
+        const int x = x0 + col, y = y0 + g % FC_Y, z = z0 + g / FC_Y;
+        if (x >= d.W || y >= d.H || z >= d.D)
+            continue;
+        const size_t p = size_t(((b * d.D + z) * d.H + y) * d.W + x);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = j * 16 + kq * 4 + r;
-            const float v = acc[j][r] + (bias ? bias[co] : 0.f);
-            if (out_f32)
-                reinterpret_cast<float *>(out)[p * Co + co] = v;
-            else
-                reinterpret_cast<bf *>(out)[p * Co + co] = f2bf(v);
+        for (int j = 0; j < NCO; ++j) {
+            const int cb = co0 + j * 16 + kq * 4;  // 4 consecutive output channels
+            f4 v = acc[rr][j];
+            if (bias) {
+                v[0] += bias[cb];
+                v[1] += bias[cb + 1];
+                v[2] += bias[cb + 2];
+                v[3] += bias[cb + 3];
+            }
+            if (out_f32) {
+                *reinterpret_cast<f4 *>(reinterpret_cast<float *>(out) + p * Co + cb) = v;
+            } else {
+                const uint2 pk = make_uint2(uint32_t(f2bf(v[0])) | (uint32_t(f2bf(v[1])) << 16),
+                                            uint32_t(f2bf(v[2])) | (uint32_t(f2bf(v[3])) << 16));
+                *reinterpret_cast<uint2 *>(reinterpret_cast<bf *>(out) + p * Co + cb) = pk;
+            }
         }
     }
 }
@@ -128,112 +176,130 @@ __global__ __launch_bounds__(256) void k_conv_flip(const bf *__restrict__ w, bf 
     wt[((long long)ci * 27 + (26 - tap)) * Co + co] = w[i];
 }
 
-// gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci].  grid.y = tap;
-// block x covers the voxel range [bx*per, (bx+1)*per) in sub-chunks of 64.
-// Per sub-chunk the 64 voxels' neighbours at this tap are decoded once into
-// LDS, then gout and the shifted input are staged transposed ([channel][voxel])
-// with 8-byte loads; each wavefront then runs its (co tile, ci tile) MFMAs.
-// The centre-tap blocks also accumulate the bias gradient sum_p gout[p][co].
-// Voxel and element indices are 32-bit (the host checks B D H W C < 2^31).
-constexpr int WG_VOX = 64;
-constexpr int WG_SLOTS = 16;  // (co tile, ci tile) pairs per wavefront
+// gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci], gb[co] += sum_p gout[p][co].
+//
+// A block owns one (co tile, ci tile) pair (blockIdx.y) and walks bricks of
+// 16 x 4 x 4 voxels (blockIdx.x, blockIdx.x + gridDim.x, ...), all 27 taps
+// per brick, so each operand is read from global memory once per brick
+// instead of once per tap.  Per brick it stages in LDS, transposed to
+// [channel][voxel] so that every MFMA operand is one aligned 8-byte read:
+//   gT: the brick's gout tile, 16 channels x 256 voxels;
+//   iT: the input tile on the brick plus a one-voxel halo in y and z, in
+//       three copies shifted by dx = -1, 0, +1 along x (copy dx holds
+//       in[x + dx] at x), so a tap's 4 consecutive voxels never straddle an
+//       8-byte boundary.
+// Channel planes are padded by 4 elements (8 bytes), which puts the 16
+// channels read by one quarter-wavefront on distinct LDS banks.
+// Wave w runs the taps w, w + 4, ... (7 or 6) over the brick's 16 rows of 16
+// voxels, reusing the gout operand across its taps; wave 3's free slot
+// accumulates the bias gradient as an MFMA against ones.  Partial sums stay
+// in registers across the block's bricks and are added to gw / gb
+// atomically at the end.  Voxel and element indices are 32-bit (the host
+// checks B D H W C < 2^31).
+constexpr int WB_X = 16, WB_Y = 4, WB_Z = 4, WB_V = WB_X * WB_Y * WB_Z;
+constexpr int WB_HROWS = (WB_Y + 2) * (WB_Z + 2);   // halo rows of 16 voxels
+constexpr int WB_PLANE = WB_HROWS * WB_X + 4;       // one channel of one shifted copy
+constexpr int WB_GROW = WB_V + 4;                   // one channel of the gout tile
+constexpr int WB_SLOTS = 7;                         // taps per wave (27 = 7 + 7 + 7 + 6)
+constexpr long long WG_TARGET_BLOCKS = 512;         // blocks per launch, all channel pairs
 
 __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, const bf *__restrict__ gout,
                                                     float *__restrict__ gw, float *__restrict__ gb, Dims d,
-                                                    int per)
+                                                    int nbx, int nby, int nbz)
 {
-    extern __shared__ bf lds[];
-    const int tap = blockIdx.y;
+    __shared__ __attribute__((aligned(16))) bf gT[16 * WB_GROW];
+    __shared__ __attribute__((aligned(16))) bf iT[3 * 16 * WB_PLANE];
     const int Ci = d.Ci, Co = d.Co;
-    bf *gT = lds;                                   // [Co][64]
-    bf *iT = lds + Co * WG_VOX;                     // [Ci][64]
-    int *nb = reinterpret_cast<int *>(lds + (Ci + Co) * WG_VOX);  // [64] neighbour voxel or -1
-    int *pv = nb + WG_VOX;                                         // [64] voxel or -1
+    const int CIT = Ci / 16;
+    const int ct = blockIdx.y / CIT, it = blockIdx.y % CIT;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const int COT = Co / 16, CIT = Ci / 16, npair = COT * CIT;
-    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-    const int nv = d.B * d.D * d.H * d.W;
-    const int vb = blockIdx.x * per;
-    const int ve = min(vb + per, nv);
-    const bool do_bias = gb != nullptr && tap == 13;
-    const int cq_o = Co / 4, cq_i = Ci / 4;        // 4-channel groups
-    float bsum = 0.f;
-    f4 acc[WG_SLOTS];
+    const bool do_bias = gb != nullptr && it == 0;
+    const int nbricks = d.B * nbx * nby * nbz;
+    const s4 ones = s4{0x3f80, 0x3f80, 0x3f80, 0x3f80};  // BF16 1.0
+    f4 acc[WB_SLOTS];
 #pragma unroll
-    for (int s = 0; s < WG_SLOTS; ++s)
+    for (int s = 0; s < WB_SLOTS; ++s)
         acc[s] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int v0 = vb; v0 < ve; v0 += WG_VOX) {
-        __syncthreads();
-        if (threadIdx.x < WG_VOX) {
-            const int p = v0 + threadIdx.x;
-            int q = -1;
-            if (p < ve) {
-                int r = p;
-                const int x = r % d.W; r /= d.W;
-                const int y = r % d.H; r /= d.H;
-                const int z = r % d.D;
-                const int b = r / d.D;
-                const int xs = x + dx, ys = y + dy, zs = z + dz;
-                if (xs >= 0 && xs < d.W && ys >= 0 && ys < d.H && zs >= 0 && zs < d.D)
-                    q = ((b * d.D + zs) * d.H + ys) * d.W + xs;
+
+    for (int br = blockIdx.x; br < nbricks; br += gridDim.x) {
+        int r = br;
+        const int bx = r % nbx; r /= nbx;
+        const int by = r % nby; r /= nby;
+        const int bz = r % nbz;
+        const int b = r / nbz;
+        const int x0 = bx * WB_X, y0 = by * WB_Y, z0 = bz * WB_Z;
+        __syncthreads();  // the previous brick's reads are done
+        {   // gout tile: thread = voxel
+            const int v = threadIdx.x;
+            const int x = x0 + (v & 15), y = y0 + ((v >> 4) & 3), z = z0 + (v >> 6);
+            uint4 lo = make_uint4(0, 0, 0, 0), hi = lo;
+            if (x < d.W && y < d.H && z < d.D) {
+                const int p = ((b * d.D + z) * d.H + y) * d.W + x;
+                const uint4 *src = reinterpret_cast<const uint4 *>(gout + p * Co + ct * 16);
+                lo = src[0];
+                hi = src[1];
             }
-            nb[threadIdx.x] = q;
-            pv[threadIdx.x] = p < ve ? p : -1;
+            const uint32_t w8[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                gT[c * WB_GROW + v] = bf((w8[c >> 1] >> (16 * (c & 1))) & 0xffff);
+        }
+        // input tile with halo: 18 x positions (x0-1 .. x0+16) per halo row
+        for (int i = threadIdx.x; i < 18 * WB_HROWS; i += blockDim.x) {
+            const int hx = i % 18 - 1, row = i / 18;
+            const int hy = row % (WB_Y + 2), hz = row / (WB_Y + 2);
+            const int x = x0 + hx, y = y0 + hy - 1, z = z0 + hz - 1;
+            uint4 lo = make_uint4(0, 0, 0, 0), hi = lo;
+            if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
+                const int q = ((b * d.D + z) * d.H + y) * d.W + x;
+                const uint4 *src = reinterpret_cast<const uint4 *>(in + q * Ci + it * 16);
+                lo = src[0];
+                hi = src[1];
+            }
+            const uint32_t w8[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {  // copy k holds in[x + (k - 1)] at x
+                const int xs = hx - (k - 1);
+                if (xs >= 0 && xs < WB_X) {
+#pragma unroll
+                    for (int c = 0; c < 16; ++c)
+                        iT[(k * 16 + c) * WB_PLANE + row * WB_X + xs] =
+                            bf((w8[c >> 1] >> (16 * (c & 1))) & 0xffff);
+                }
+            }
         }
         __syncthreads();
-        for (int i = threadIdx.x; i < WG_VOX * cq_o; i += blockDim.x) {
-            const int vo = i / cq_o, c = (i - vo * cq_o) * 4;
-            const int p = pv[vo];
-            s4 v = s4{0, 0, 0, 0};
-            if (p >= 0)
-                v = *reinterpret_cast<const s4 *>(gout + p * Co + c);
+        for (int g = 0; g < WB_Y * WB_Z; ++g) {  // brick row (gy, gz) of 16 voxels
+            const int gy = g % WB_Y, gz = g / WB_Y;
+            const s4 av = *reinterpret_cast<const s4 *>(gT + col * WB_GROW + g * 16 + kq * 4);
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-                gT[(c + k) * WG_VOX + vo] = bf(v[k]);
-        }
-        for (int i = threadIdx.x; i < WG_VOX * cq_i; i += blockDim.x) {
-            const int vo = i / cq_i, c = (i - vo * cq_i) * 4;
-            const int q = nb[vo];
-            s4 v = s4{0, 0, 0, 0};
-            if (q >= 0)
-                v = *reinterpret_cast<const s4 *>(in + q * Ci + c);
-#pragma unroll
-            for (int k = 0; k < 4; ++k)
-                iT[(c + k) * WG_VOX + vo] = bf(v[k]);
-        }
-        __syncthreads();
-        if (do_bias && threadIdx.x < Co)
-            for (int vo = 0; vo < WG_VOX; ++vo)
-                bsum += bf2f(gT[threadIdx.x * WG_VOX + vo]);
-#pragma unroll
-        for (int s = 0; s < WG_SLOTS; ++s) {
-            const int pr = wv + 4 * s;
-            if (pr < npair) {
-                const int ct = pr / CIT, it = pr % CIT;
-#pragma unroll
-                for (int kk = 0; kk < WG_VOX / 16; ++kk) {
-                    const s4 av = *reinterpret_cast<const s4 *>(gT + (ct * 16 + col) * WG_VOX + kk * 16 + kq * 4);
-                    const s4 bv = *reinterpret_cast<const s4 *>(iT + (it * 16 + col) * WG_VOX + kk * 16 + kq * 4);
+            for (int s = 0; s < WB_SLOTS; ++s) {
+                const int tap = wv + 4 * s;
+                if (tap < 27) {
+                    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+                    const int row = (gz + 1 + dz) * (WB_Y + 2) + (gy + 1 + dy);
+                    const s4 bv = *reinterpret_cast<const s4 *>(
+                        iT + ((dx + 1) * 16 + col) * WB_PLANE + row * WB_X + kq * 4);
                     acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[s], 0, 0, 0);
+                } else if (do_bias) {  // wave 3, slot 6: D[co][*] = sum_k gout[k][co]
+                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, ones, acc[s], 0, 0, 0);
                 }
             }
         }
     }
 #pragma unroll
-    for (int s = 0; s < WG_SLOTS; ++s) {
-        const int pr = wv + 4 * s;
-        if (pr < npair) {
-            const int ct = pr / CIT, it = pr % CIT;
+    for (int s = 0; s < WB_SLOTS; ++s) {
+        const int tap = wv + 4 * s;
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int co = ct * 16 + kq * 4 + r, ci = it * 16 + col;
+        for (int r = 0; r < 4; ++r) {
+            const int co = ct * 16 + kq * 4 + r, ci = it * 16 + col;
+            if (tap < 27)
                 atomicAdd(&gw[(co * 27 + tap) * Ci + ci], acc[s][r]);
-            }
+            else if (do_bias && col == 0)
+                atomicAdd(&gb[co], acc[s][r]);
         }
     }
-    if (do_bias && threadIdx.x < Co)
-        atomicAdd(&gb[threadIdx.x], bsum);
 }
 
 // ------------------------------------------------------------ elementwise
@@ -509,12 +575,14 @@ lbmx_status check_dims(int B, int D, int H, int W)
     return LBMX_OK;
 }
 
-template <int COT>
+template <int NCO>
 void launch_fwd(const bf *in, const bf *w, const float *bias, void *out, int out_f32, Dims d, hipStream_t s)
 {
-    const long long nv = (long long)d.B * d.D * d.H * d.W;
-    const unsigned blocks = unsigned((nv + 63) / 64);
-    hipLaunchKernelGGL(k_conv_fwd<COT>, dim3(blocks), dim3(256), 0, s, in, w, bias, out, out_f32, d);
+    const int nbx = (d.W + FC_X - 1) / FC_X, nby = (d.H + FC_Y - 1) / FC_Y, nbz = (d.D + FC_Z - 1) / FC_Z;
+    const unsigned bricks = unsigned(d.B * nbx * nby * nbz);
+    const unsigned groups = unsigned(d.Co / 16 / NCO);
+    hipLaunchKernelGGL(k_conv_fwd<NCO>, dim3(bricks, groups), dim3(256), 0, s, in, w, bias, out, out_f32, d,
+                       nbx, nby, nbz);
 }
 
 }  // namespace
@@ -536,17 +604,14 @@ lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias,
     const bf *i = reinterpret_cast<const bf *>(in);
     const bf *wb = reinterpret_cast<const bf *>(w);
     hipStream_t s = S(stream);
-    switch (Co / 16) {
-    case 1: launch_fwd<1>(i, wb, bias, out, out_f32, d, s); break;
-    case 2: launch_fwd<2>(i, wb, bias, out, out_f32, d, s); break;
-    case 3: launch_fwd<3>(i, wb, bias, out, out_f32, d, s); break;
-    case 4: launch_fwd<4>(i, wb, bias, out, out_f32, d, s); break;
+    // output channel tiles per block: the largest divisor of Co/16 up to 5
+    switch ((Co / 16) % 5 == 0 ? 5 : (Co / 16) % 4 == 0 ? 4 : (Co / 16) % 3 == 0 ? 3
+                                                                : (Co / 16) % 2 == 0 ? 2 : 1) {
     case 5: launch_fwd<5>(i, wb, bias, out, out_f32, d, s); break;
-    case 6: launch_fwd<6>(i, wb, bias, out, out_f32, d, s); break;
-    case 7: launch_fwd<7>(i, wb, bias, out, out_f32, d, s); break;
-    case 8: launch_fwd<8>(i, wb, bias, out, out_f32, d, s); break;
-    case 9: launch_fwd<9>(i, wb, bias, out, out_f32, d, s); break;
-    case 10: launch_fwd<10>(i, wb, bias, out, out_f32, d, s); break;
+    case 4: launch_fwd<4>(i, wb, bias, out, out_f32, d, s); break;
+    case 3: launch_fwd<3>(i, wb, bias, out, out_f32, d, s); break;
+    case 2: launch_fwd<2>(i, wb, bias, out, out_f32, d, s); break;
+    default: launch_fwd<1>(i, wb, bias, out, out_f32, d, s); break;
     }
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
@@ -571,22 +636,23 @@ lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, fl
         return st;
     if (!in || !gout || !gw)
         return fail(LBMX_EINVAL, "conv3d_wgrad: NULL tensor");
-    if (Ci < 16 || Ci % 16 || Co < 16 || Co % 16 || (Co / 16) * (Ci / 16) > 4 * WG_SLOTS ||
-        Co > 256)
-        return fail(LBMX_EINVAL, "conv3d_wgrad: need Ci, Co multiples of 16 with (Co/16)(Ci/16) <= %d",
-                    4 * WG_SLOTS);
+    if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 1024)
+        return fail(LBMX_EINVAL, "conv3d_wgrad: need Ci, Co multiples of 16 in [16, 1024]");
     const Dims d{B, D, H, W, Ci, Co};
     const long long nv = (long long)B * D * H * W;
     if (nv * (Ci > Co ? Ci : Co) >= (1LL << 31))
         return fail(LBMX_EINVAL, "conv3d_wgrad: tensor of %lld voxels too large", nv);
-    const long long chunks = (nv + WG_VOX - 1) / WG_VOX;
-    long long gx = chunks < 96 ? chunks : 96;
-    const long long per = ((chunks + gx - 1) / gx) * WG_VOX;
-    gx = (nv + per - 1) / per;
-    const size_t lds = size_t(Ci + Co) * WG_VOX * sizeof(bf) + 2 * WG_VOX * sizeof(int);
-    hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned(gx), 27), dim3(256), lds, S(stream),
+    const int nbx = (W + WB_X - 1) / WB_X, nby = (H + WB_Y - 1) / WB_Y, nbz = (D + WB_Z - 1) / WB_Z;
+    const long long nbricks = (long long)B * nbx * nby * nbz;
+    const int pairs = (Co / 16) * (Ci / 16);
+    // about two blocks per CU in total; each block sums several bricks in
+    // registers before its atomic adds
+    long long gx = (WG_TARGET_BLOCKS + pairs - 1) / pairs;
+    if (gx > nbricks) gx = nbricks;
+    if (gx < 1) gx = 1;
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned(gx), unsigned(pairs)), dim3(256), 0, S(stream),
                        reinterpret_cast<const bf *>(in), reinterpret_cast<const bf *>(gout), gw, gb, d,
-                       int(per));
+                       nbx, nby, nbz);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }

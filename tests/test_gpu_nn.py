@@ -63,7 +63,7 @@ def P(t):
     return unet.P(t)
 
 
-SHAPES = [(2, 6, 6, 6), (1, 5, 4, 7)]
+SHAPES = [(2, 6, 6, 6), (1, 5, 4, 7), (1, 9, 10, 35)]  # the last: 3 ragged bricks per axis
 CHANNELS = [(16, 16), (48, 16), (16, 32), (32, 96), (160, 64), (16, 160)]
 
 
@@ -107,6 +107,9 @@ def test_conv_data_gradient(shape, ci, co):
 @pytest.mark.parametrize("shape", SHAPES + [(2, 16, 16, 16)])
 @pytest.mark.parametrize("ci,co", [(16, 16), (48, 16), (32, 96), (160, 64), (96, 96)])
 def test_conv_weight_gradient(shape, ci, co):
+    """Against the oracle, shapes with partial 16 x 4 x 4 bricks in every
+    direction (1 x 9 x 10 x 35: three bricks along each axis, the last ones
+    ragged) and one brick smaller than a brick (1 x 5 x 4 x 7)."""
     import torch
     print(f"case: conv wgrad {shape} {ci}->{co}", flush=True)
     B, D, H, W = shape
