@@ -57,28 +57,29 @@ __device__ __forceinline__ long long nvox_of(const Dims &d)
 // out[p][co] = bias[co] + sum_{tap, ci} W[co][tap][ci] in[p + off(tap)][ci].
 //
 // A block owns a brick of 16 x 4 x 4 voxels (blockIdx.x) and NCO output
-// channel tiles of 16 (blockIdx.y selects the group).  The brick's input
-// plus a one-voxel halo (18 x 6 x 6 voxels) is staged channel-last in LDS,
-// FC_CC input channels per round, so the MFMA operand "4 consecutive input
-// channels of the voxel at this tap" is one aligned 8-byte LDS read for any
-// tap; the voxel stride is padded to 36 channels (18 words), which puts the
-// 16 voxels read by one quarter-wavefront on distinct LDS banks.  Wave w
-// computes the brick's rows 4w .. 4w+3 (16 voxels each): every weight
-// operand, read from global memory (cache-resident), serves 4 rows, and
-// every input operand serves the NCO channel tiles.  Each lane ends with 4
+// channel tiles of 16 (blockIdx.y selects the group).  Per round of 16 input
+// channels it stages in LDS, channel-last:
+//   xs: the brick's input plus a one-voxel halo (18 x 6 x 6 voxels), so the
+//       MFMA operand "4 consecutive input channels of the voxel at this tap"
+//       is one aligned 8-byte read for any tap;
+//   ws: the weights of the block's output channels for all 27 taps.
+// Both are padded to 20 elements (10 words) per row, which puts the 16 rows
+// read by one quarter-wavefront on distinct LDS banks.  Wave w computes the
+// brick's rows 4w .. 4w+3 (16 voxels each): every weight operand serves 4
+// rows and every input operand the NCO channel tiles.  Each lane ends with 4
 // consecutive output channels of one voxel and stores them together.
 constexpr int FC_X = 16, FC_Y = 4, FC_Z = 4;        // brick
 constexpr int FC_HX = FC_X + 2, FC_HY = FC_Y + 2, FC_HZ = FC_Z + 2;
 constexpr int FC_HVOX = FC_HX * FC_HY * FC_HZ;      // 648 halo voxels
-constexpr int FC_CC = 32;                           // input channels per staging round
-constexpr int FC_VSTRIDE = FC_CC + 4;               // LDS elements per halo voxel
+constexpr int FC_ROW = 20;                          // LDS elements per 16-channel row
 
 template <int NCO>
 __global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, const bf *__restrict__ w,
                                                   const float *__restrict__ bias, void *__restrict__ out,
                                                   int out_f32, Dims d, int nbx, int nby, int nbz)
 {
-    __shared__ __attribute__((aligned(16))) bf xs[FC_HVOX * FC_VSTRIDE];
+    __shared__ __attribute__((aligned(16))) bf xs[FC_HVOX * FC_ROW];
+    __shared__ __attribute__((aligned(16))) bf ws[27 * NCO * 16 * FC_ROW];
     const int Ci = d.Ci, Co = d.Co;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
@@ -89,7 +90,6 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, con
     const int b = r / nbz;
     const int x0 = bx * FC_X, y0 = by * FC_Y, z0 = bz * FC_Z;
     const int co0 = blockIdx.y * NCO * 16;
-    const size_t wrow = size_t(27) * Ci;  // weights per output channel
 
     f4 acc[4][NCO];
 #pragma unroll
@@ -98,40 +98,47 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, con
         for (int j = 0; j < NCO; ++j)
             acc[rr][j] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int c0 = 0; c0 < Ci; c0 += FC_CC) {
-        const int cc = Ci - c0 < FC_CC ? Ci - c0 : FC_CC;  // 16 or 32
-        const int parts = cc / 4;                          // 8-byte pieces per voxel
+    for (int c0 = 0; c0 < Ci; c0 += 16) {
         __syncthreads();
-        for (int i = threadIdx.x; i < FC_HVOX * parts; i += blockDim.x) {
-            const int hv = i / parts, part = i - hv * parts;
+        for (int i = threadIdx.x; i < FC_HVOX * 2; i += blockDim.x) {  // 2 x 8 bytes per voxel
+            const int hv = i >> 1, part = i & 1;
             const int hx = hv % FC_HX, hrow = hv / FC_HX;
             const int hy = hrow % FC_HY, hz = hrow / FC_HY;
             const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-            uint2 v = make_uint2(0, 0);
+            uint4 v = make_uint4(0, 0, 0, 0);
             if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
                 const int q = ((b * d.D + z) * d.H + y) * d.W + x;
-                v = *reinterpret_cast<const uint2 *>(in + size_t(q) * Ci + c0 + part * 4);
+                v = *reinterpret_cast<const uint4 *>(in + size_t(q) * Ci + c0 + part * 8);
             }
-            *reinterpret_cast<uint2 *>(xs + hv * FC_VSTRIDE + part * 4) = v;
+            uint2 *dst = reinterpret_cast<uint2 *>(xs + hv * FC_ROW + part * 8);
+            dst[0] = make_uint2(v.x, v.y);
+            dst[1] = make_uint2(v.z, v.w);
+        }
+        for (int i = threadIdx.x; i < 27 * NCO * 16 * 2; i += blockDim.x) {  // [tap][co][2 x 8 ch]
+            const int row = i >> 1, part = i & 1;
+            const int tap = row / (NCO * 16), co = row % (NCO * 16);
+            const uint4 v = *reinterpret_cast<const uint4 *>(
+                w + (size_t(co0 + co) * 27 + tap) * Ci + c0 + part * 8);
+            uint2 *dst = reinterpret_cast<uint2 *>(ws + row * FC_ROW + part * 8);
+            dst[0] = make_uint2(v.x, v.y);
+            dst[1] = make_uint2(v.z, v.w);
         }
         __syncthreads();
+#pragma unroll 3
         for (int tap = 0; tap < 27; ++tap) {
             const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-            for (int k16 = 0; k16 < cc; k16 += 16) {
-                s4 a[NCO];
+            s4 a[NCO];
+#pragma unroll
+            for (int j = 0; j < NCO; ++j)
+                a[j] = *reinterpret_cast<const s4 *>(ws + ((tap * NCO + j) * 16 + col) * FC_ROW + kq * 4);
+#pragma unroll
+            for (int rr = 0; rr < 4; ++rr) {
+                const int g = wv * 4 + rr, gy = g % FC_Y, gz = g / FC_Y;
+                const int hv = ((gz + 1 + dz) * FC_HY + (gy + 1 + dy)) * FC_HX + (col + 1 + dx);
+                const s4 bv = *reinterpret_cast<const s4 *>(xs + hv * FC_ROW + kq * 4);
 #pragma unroll
                 for (int j = 0; j < NCO; ++j)
-                    a[j] = *reinterpret_cast<const s4 *>(w + size_t(co0 + j * 16 + col) * wrow +
-                                                         size_t(tap) * Ci + c0 + k16 + kq * 4);
-#pragma unroll
-                for (int rr = 0; rr < 4; ++rr) {
-                    const int g = wv * 4 + rr, gy = g % FC_Y, gz = g / FC_Y;
-                    const int hv = ((gz + 1 + dz) * FC_HY + (gy + 1 + dy)) * FC_HX + (col + 1 + dx);
-                    const s4 bv = *reinterpret_cast<const s4 *>(xs + hv * FC_VSTRIDE + k16 + kq * 4);
-#pragma unroll
-                    for (int j = 0; j < NCO; ++j)
-                        acc[rr][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[j], bv, acc[rr][j], 0, 0, 0);
-                }
+                    acc[rr][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[j], bv, acc[rr][j], 0, 0, 0);
             }
         }
     }
@@ -192,7 +199,8 @@ __global__ __launch_bounds__(256) void k_conv_flip(const bf *__restrict__ w, bf 
 // channels read by one quarter-wavefront on distinct LDS banks.
 // Wave w runs the taps w, w + 4, ... (7 or 6) over the brick's 16 rows of 16
 // voxels, reusing the gout operand across its taps; wave 3's free slot
-// accumulates the bias gradient as an MFMA against ones.  Partial sums stay
+// accumulates the bias gradient as an MFMA against ones (every wave issues 7
+// MFMAs per row with no branch).  Partial sums stay
 // in registers across the block's bricks and are added to gw / gb
 // atomically at the end.  Voxel and element indices are 32-bit (the host
 // checks B D H W C < 2^31).
@@ -217,74 +225,106 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
     const bool do_bias = gb != nullptr && it == 0;
     const int nbricks = d.B * nbx * nby * nbz;
     const s4 ones = s4{0x3f80, 0x3f80, 0x3f80, 0x3f80};  // BF16 1.0
+    // LDS offset of each slot's input operand at brick row 0; slot s runs tap
+    // wv + 4 s, except wave 3's last slot, which runs the bias (operand ones;
+    // its offset is any valid one and the value is not used).
+    int boff[WB_SLOTS];
+#pragma unroll
+    for (int s = 0; s < WB_SLOTS; ++s) {
+        const int tap = min(wv + 4 * s, 26);
+        const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+        boff[s] = ((dx + 1) * 16 + col) * WB_PLANE + ((1 + dz) * (WB_Y + 2) + (1 + dy)) * WB_X + kq * 4;
+    }
     f4 acc[WB_SLOTS];
 #pragma unroll
     for (int s = 0; s < WB_SLOTS; ++s)
         acc[s] = f4{0.f, 0.f, 0.f, 0.f};
 
-    for (int br = blockIdx.x; br < nbricks; br += gridDim.x) {
+    // Software pipeline: the global loads of brick br + gridDim.x are issued
+    // into registers before brick br's MFMAs and stored to LDS afterwards.
+    // Thread t holds the gout row of voxel t and halo voxels t, t + 256,
+    // t + 512 (of 18 x 36 = 648).
+    constexpr int NH = (18 * WB_HROWS + 255) / 256;
+    uint4 g_lo, g_hi, h_lo[NH], h_hi[NH];
+    auto load_brick = [&](int br) {
         int r = br;
         const int bx = r % nbx; r /= nbx;
         const int by = r % nby; r /= nby;
         const int bz = r % nbz;
         const int b = r / nbz;
         const int x0 = bx * WB_X, y0 = by * WB_Y, z0 = bz * WB_Z;
-        __syncthreads();  // the previous brick's reads are done
-        {   // gout tile: thread = voxel
+        {
             const int v = threadIdx.x;
             const int x = x0 + (v & 15), y = y0 + ((v >> 4) & 3), z = z0 + (v >> 6);
-            uint4 lo = make_uint4(0, 0, 0, 0), hi = lo;
+            g_lo = g_hi = make_uint4(0, 0, 0, 0);
             if (x < d.W && y < d.H && z < d.D) {
                 const int p = ((b * d.D + z) * d.H + y) * d.W + x;
                 const uint4 *src = reinterpret_cast<const uint4 *>(gout + p * Co + ct * 16);
-                lo = src[0];
-                hi = src[1];
+                g_lo = src[0];
+                g_hi = src[1];
             }
-            const uint32_t w8[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+        }
+#pragma unroll
+        for (int k = 0; k < NH; ++k) {
+            const int i = threadIdx.x + 256 * k;
+            h_lo[k] = h_hi[k] = make_uint4(0, 0, 0, 0);
+            if (i < 18 * WB_HROWS) {
+                const int hx = i % 18 - 1, row = i / 18;
+                const int hy = row % (WB_Y + 2), hz = row / (WB_Y + 2);
+                const int x = x0 + hx, y = y0 + hy - 1, z = z0 + hz - 1;
+                if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
+                    const int q = ((b * d.D + z) * d.H + y) * d.W + x;
+                    const uint4 *src = reinterpret_cast<const uint4 *>(in + q * Ci + it * 16);
+                    h_lo[k] = src[0];
+                    h_hi[k] = src[1];
+                }
+            }
+        }
+    };
+    if (blockIdx.x < nbricks)
+        load_brick(blockIdx.x);
+
+    for (int br = blockIdx.x; br < nbricks; br += gridDim.x) {
+        __syncthreads();  // the previous brick's reads are done
+        {   // gout tile: thread = voxel
+            const int v = threadIdx.x;
+            const uint32_t w8[8] = {g_lo.x, g_lo.y, g_lo.z, g_lo.w, g_hi.x, g_hi.y, g_hi.z, g_hi.w};
 #pragma unroll
             for (int c = 0; c < 16; ++c)
                 gT[c * WB_GROW + v] = bf((w8[c >> 1] >> (16 * (c & 1))) & 0xffff);
         }
-        // input tile with halo: 18 x positions (x0-1 .. x0+16) per halo row
-        for (int i = threadIdx.x; i < 18 * WB_HROWS; i += blockDim.x) {
-            const int hx = i % 18 - 1, row = i / 18;
-            const int hy = row % (WB_Y + 2), hz = row / (WB_Y + 2);
-            const int x = x0 + hx, y = y0 + hy - 1, z = z0 + hz - 1;
-            uint4 lo = make_uint4(0, 0, 0, 0), hi = lo;
-            if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
-                const int q = ((b * d.D + z) * d.H + y) * d.W + x;
-                const uint4 *src = reinterpret_cast<const uint4 *>(in + q * Ci + it * 16);
-                lo = src[0];
-                hi = src[1];
-            }
-            const uint32_t w8[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-            for (int k = 0; k < 3; ++k) {  // copy k holds in[x + (k - 1)] at x
-                const int xs = hx - (k - 1);
+        for (int k = 0; k < NH; ++k) {  // input tile with halo, three x-shifted copies
+            const int i = threadIdx.x + 256 * k;
+            if (i >= 18 * WB_HROWS)
+                continue;
+            const int hx = i % 18 - 1, row = i / 18;
+            const uint32_t w8[8] = {h_lo[k].x, h_lo[k].y, h_lo[k].z, h_lo[k].w,
+                                    h_hi[k].x, h_hi[k].y, h_hi[k].z, h_hi[k].w};
+#pragma unroll
+            for (int c3 = 0; c3 < 3; ++c3) {  // copy c3 holds in[x + (c3 - 1)] at x
+                const int xs = hx - (c3 - 1);
                 if (xs >= 0 && xs < WB_X) {
 #pragma unroll
                     for (int c = 0; c < 16; ++c)
-                        iT[(k * 16 + c) * WB_PLANE + row * WB_X + xs] =
+                        iT[(c3 * 16 + c) * WB_PLANE + row * WB_X + xs] =
                             bf((w8[c >> 1] >> (16 * (c & 1))) & 0xffff);
                 }
             }
         }
         __syncthreads();
+        if (br + int(gridDim.x) < nbricks)
+            load_brick(br + gridDim.x);
+#pragma unroll 4
         for (int g = 0; g < WB_Y * WB_Z; ++g) {  // brick row (gy, gz) of 16 voxels
-            const int gy = g % WB_Y, gz = g / WB_Y;
+            const int rowoff = ((g / WB_Y) * (WB_Y + 2) + g % WB_Y) * WB_X;
             const s4 av = *reinterpret_cast<const s4 *>(gT + col * WB_GROW + g * 16 + kq * 4);
 #pragma unroll
             for (int s = 0; s < WB_SLOTS; ++s) {
-                const int tap = wv + 4 * s;
-                if (tap < 27) {
-                    const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-                    const int row = (gz + 1 + dz) * (WB_Y + 2) + (gy + 1 + dy);
-                    const s4 bv = *reinterpret_cast<const s4 *>(
-                        iT + ((dx + 1) * 16 + col) * WB_PLANE + row * WB_X + kq * 4);
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[s], 0, 0, 0);
-                } else if (do_bias) {  // wave 3, slot 6: D[co][*] = sum_k gout[k][co]
-                    acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, ones, acc[s], 0, 0, 0);
-                }
+                s4 bv = *reinterpret_cast<const s4 *>(iT + boff[s] + rowoff);
+                if (s == WB_SLOTS - 1)
+                    bv = wv == 3 ? ones : bv;
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[s], 0, 0, 0);
             }
         }
     }
@@ -296,7 +336,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
             const int co = ct * 16 + kq * 4 + r, ci = it * 16 + col;
             if (tap < 27)
                 atomicAdd(&gw[(co * 27 + tap) * Ci + ci], acc[s][r]);
-            else if (do_bias && col == 0)
+            else if (do_bias && col == 0)  // wave 3, last slot: D[co][*] = sum_k gout[k][co]
                 atomicAdd(&gb[co], acc[s][r]);
         }
     }
@@ -604,15 +644,12 @@ lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias,
     const bf *i = reinterpret_cast<const bf *>(in);
     const bf *wb = reinterpret_cast<const bf *>(w);
     hipStream_t s = S(stream);
-    // output channel tiles per block: the largest divisor of Co/16 up to 5
-    switch ((Co / 16) % 5 == 0 ? 5 : (Co / 16) % 4 == 0 ? 4 : (Co / 16) % 3 == 0 ? 3
-                                                                : (Co / 16) % 2 == 0 ? 2 : 1) {
-    case 5: launch_fwd<5>(i, wb, bias, out, out_f32, d, s); break;
-    case 4: launch_fwd<4>(i, wb, bias, out, out_f32, d, s); break;
-    case 3: launch_fwd<3>(i, wb, bias, out, out_f32, d, s); break;
-    case 2: launch_fwd<2>(i, wb, bias, out, out_f32, d, s); break;
-    default: launch_fwd<1>(i, wb, bias, out, out_f32, d, s); break;
-    }
+    // two output channel tiles per block when Co/16 is even (weights of both
+    // for all taps fit in LDS beside the input tile at two blocks per CU)
+    if ((Co / 16) % 2 == 0)
+        launch_fwd<2>(i, wb, bias, out, out_f32, d, s);
+    else
+        launch_fwd<1>(i, wb, bias, out, out_f32, d, s);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
