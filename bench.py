@@ -110,7 +110,7 @@ def main():
     ap.add_argument("--ra", type=float, default=1e6)
     ap.add_argument("--wall-type", type=int, default=1)
     ap.add_argument("--storage", default="f32",
-                    choices=["f64", "f32", "f16", "bf16", "f16_f32", "bf16_f32"])
+                    choices=["f64", "f32", "f16", "bf16", "f16_f32", "bf16_f32", "f16_i16"])
     ap.add_argument("--launch", default="", help="bx,by override of the step kernel block")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -165,7 +165,8 @@ def main():
     tr = None if variant else counter_traffic(args.storage, n)
     dtype = {"f64": "f64", "f32": "f32", "f16": "f16-storage/f32", "bf16": "bf16-storage/f32",
              "f16_f32": "f16-flow+f32-energy-storage/f32",
-             "bf16_f32": "bf16-flow+f32-energy-storage/f32"}
+             "bf16_f32": "bf16-flow+f32-energy-storage/f32",
+             "f16_i16": "f16-flow+i16-fixed-energy-storage/f32"}
     line = {
         "metric": "double-MRT MLUPS + % HBM roofline at 256^3; wall time to steady Nu",
         "value": round(mlups, 1),

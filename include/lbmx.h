@@ -53,14 +53,20 @@ typedef enum {
  * from the lattice weights (Eq. 18), D3Q7 (energy) populations as g_i; in a
  * 16-bit format a population is stored divided by its weight (1/w_i, 1/w_T,i).
  * The mixed formats keep the flow lattice in 16 bits and the energy lattice
- * in FP32.  Bytes moved per node update: 416, 208, 104, 104, 132, 132. */
+ * in FP32, or (LBMX_F16_I16) the energy populations as g_i / w_T,i in signed
+ * 16-bit fixed point with 14 fraction bits (range +-2, saturating; the code
+ * -32768 stands for NaN), rounded stochastically by the step (a
+ * deterministic counter-based stream of node and step), so that increments
+ * below one spacing are kept on average.  Bytes moved per node update: 416,
+ * 208, 104, 104, 132, 132, 104. */
 typedef enum {
     LBMX_F64 = 0,       /* flow FP64, energy FP64                      */
     LBMX_F32 = 1,       /* flow FP32, energy FP32                      */
     LBMX_F16 = 2,       /* flow FP16, energy FP16                      */
     LBMX_BF16 = 3,      /* flow BF16, energy BF16                      */
     LBMX_F16_F32 = 4,   /* flow FP16, energy FP32                      */
-    LBMX_BF16_F32 = 5   /* flow BF16, energy FP32                      */
+    LBMX_BF16_F32 = 5,  /* flow BF16, energy FP32                      */
+    LBMX_F16_I16 = 6    /* flow FP16, energy 16-bit fixed point        */
 } lbmx_storage;
 
 typedef struct {

@@ -50,6 +50,7 @@ struct lbmx_batch {
     size_t tiles_cap = 0;
     uint32_t ntiles = 0;
     int parity = 0;                // lattice index of every active cavity
+    uint64_t launches = 0;         // step launches so far (stochastic-rounding stream)
     int block = 256;               // threads per block = nodes per tile
     int grid = 0;                  // blocks; 0 = one per tile
     int graph_steps = 64;          // steps per captured graph; 0 = direct launches
@@ -146,18 +147,22 @@ lbmx_status launch_direct(lbmx_batch *b, int64_t nsteps)
         switch (b->force_model) {
         case LBMX_FORCE_EQ15_RHO:
             hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_EQ15_RHO>), dim3(grid_blocks(b)),
-                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity);
+                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity,
+                               uint32_t(b->launches + s));
             break;
         case LBMX_FORCE_GUO:
             hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_GUO>), dim3(grid_blocks(b)),
-                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity);
+                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity,
+                               uint32_t(b->launches + s));
             break;
         default:
             hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_EQ15>), dim3(grid_blocks(b)),
-                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity);
+                               dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity,
+                               uint32_t(b->launches + s));
         }
         b->parity ^= 1;
     }
+    b->launches += uint64_t(nsteps);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }

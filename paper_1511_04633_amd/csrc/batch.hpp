@@ -47,7 +47,7 @@ __device__ __forceinline__ uint32_t div_small(uint32_t c, uint32_t n, float inv_
 template <class St, int kForce>
 __global__ __launch_bounds__(1024) void k_step_batch(const BatchCav<typename St::T> *__restrict__ cavs,
                                                      const Tile *__restrict__ tiles, uint32_t ntiles,
-                                                     int parity)
+                                                     int parity, uint32_t step)
 {
     using T = typename St::T;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
@@ -64,7 +64,7 @@ __global__ __launch_bounds__(1024) void k_step_batch(const BatchCav<typename St:
         T f[19], g[7];
         pull<St, true>(cv->lat[parity], geo, x, y, int(z), f, g);
         collide<T, kForce>(f, g, cv->rates);
-        put<St, true>(cv->lat[parity ^ 1], c, f, g);
+        put<St, true>(cv->lat[parity ^ 1], c, step, f, g);
     }
 }
 

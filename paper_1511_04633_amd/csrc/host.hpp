@@ -35,7 +35,8 @@ inline size_t flow_size(int32_t s)
     case LBMX_F16:
     case LBMX_BF16:
     case LBMX_F16_F32:
-    case LBMX_BF16_F32: return 2;
+    case LBMX_BF16_F32:
+    case LBMX_F16_I16: return 2;
     default: return 0;
     }
 }
@@ -47,7 +48,8 @@ inline size_t energy_size(int32_t s)
     case LBMX_F16_F32:
     case LBMX_BF16_F32: return 4;
     case LBMX_F16:
-    case LBMX_BF16: return 2;
+    case LBMX_BF16:
+    case LBMX_F16_I16: return 2;
     default: return 0;
     }
 }
@@ -268,6 +270,7 @@ Geometry<typename St::T> geometry(const View &v)
     g.wall_type = v.wall_type;
     g.theta_hot = T(v.theta_hot);
     g.theta_cold = T(v.theta_cold);
+    g.step = 0;
     return g;
 }
 
@@ -378,6 +381,7 @@ struct DevBuf {
         case LBMX_BF16: return fn<Store<__hip_bfloat16, __hip_bfloat16>>(__VA_ARGS__);         \
         case LBMX_F16_F32: return fn<Store<__half, float>>(__VA_ARGS__);                       \
         case LBMX_BF16_F32: return fn<Store<__hip_bfloat16, float>>(__VA_ARGS__);              \
+        case LBMX_F16_I16: return fn<Store<__half, Fix16>>(__VA_ARGS__);                       \
         default: return ::lbmx::host::fail(LBMX_EINVAL, "bad storage %d", int(storage));       \
         }                                                                                      \
     }())

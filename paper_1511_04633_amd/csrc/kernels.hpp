@@ -95,6 +95,80 @@ __host__ __device__ constexpr int slab_shift_for(size_t flow_bytes)
     return flow_bytes >= 8 ? 10 : (flow_bytes == 4 ? 11 : 12);
 }
 
+// Fixed-point energy storage: g_i / w_T,i as a signed 16-bit integer in
+// units of 2^-14 (range +-2, uniform spacing 6.1e-5; FP16 spacing is 1.2e-4
+// to 2.4e-4 over the |g/w_T| = 0.25 .. 1 where the temperature signal lives).
+// The step kernels round stochastically (enc_r): up with probability equal to
+// the fraction below, so that a change smaller than one spacing per step is
+// kept on average instead of being rounded away every step (the slow thermal
+// drift would otherwise stall: with rounding to nearest this format's Nu
+// error at 64^3, Ra 1e6 was 4.3e-3, with stochastic rounding 1.5e-5).
+// Initialisation rounds to nearest (enc).
+// Finite values saturate at +-32767; -32768 encodes NaN, so that a diverging
+// run still reports non-finite values.
+struct Fix16 {
+    short bits;
+};
+
+template <>
+struct Codec<Fix16> {
+    using Raw = unsigned short;
+    template <typename T> static __device__ __forceinline__ T dec(Raw v, T w)
+    {
+        const short q = short(v);
+        return q == -32768 ? T(NAN) : T(q) * (w * T(1.0 / 16384.0));
+    }
+    static __device__ __forceinline__ Raw pack(float q)
+    {
+        return Raw(short(fminf(fmaxf(q, -32767.0f), 32767.0f)));
+    }
+    template <typename T> static __device__ __forceinline__ Raw enc(T v, T inv_w)
+    {
+        const float x = float(v * inv_w) * 16384.0f;
+        return x == x ? pack(rintf(x)) : Raw(0x8000);
+    }
+    // u16: 16 uniformly random bits, u = u16 / 2^16 in [0, 1)
+    template <typename T> static __device__ __forceinline__ Raw enc_r(T v, T inv_w, uint32_t u16)
+    {
+        const float x = float(v * inv_w) * 16384.0f;
+        if (!(x == x))
+            return Raw(0x8000);
+        const float fl = floorf(x);
+        const float u = float(u16) * (1.0f / 65536.0f);
+        return pack(u < x - fl ? fl + 1.0f : fl);
+    }
+};
+
+// Random bits for the stochastic rounding of node c's energy populations at
+// step t: the MurmurHash3 finaliser (multiply-xorshift) of a combination of
+// the two counters gives the first 32-bit word, xorshift32 (Marsaglia) the
+// next three; each word serves two populations, 16 bits each.
+// Deterministic: a run repeats exactly.
+struct RoundBits {
+    uint32_t w[4];
+    __device__ __forceinline__ RoundBits(uint32_t c, uint32_t t)
+    {
+        uint32_t h = c * 0x9E3779B1u + t * 0xC2B2AE3Du;
+        h ^= h >> 16;
+        h *= 0x85EBCA6Bu;
+        h ^= h >> 13;
+        h *= 0xC2B2AE35u;
+        h ^= h >> 16;
+        h |= 1u;  // xorshift needs a nonzero state
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            w[k] = h;
+            h ^= h << 13;
+            h ^= h >> 17;
+            h ^= h << 5;
+        }
+    }
+    __device__ __forceinline__ uint32_t u16(int i) const
+    {
+        return (i & 1) ? (w[i >> 1] >> 16) : (w[i >> 1] & 0xffffu);
+    }
+};
+
 // Element types of the flow (SF) and energy (SG) segments; T is the
 // arithmetic type of the collision (FP64 only when both are FP64).
 template <typename SF, typename SG>
@@ -144,6 +218,7 @@ struct Geometry {
     int n;
     int wall_type;     // 1, 2, 3
     T theta_hot, theta_cold;
+    uint32_t step;     // time step being written (stochastic-rounding stream)
 };
 
 // theta on a linear wall (Eqs. 9-10) at node height y: the crossing point of
@@ -274,9 +349,9 @@ __device__ __forceinline__ void pull(const char *__restrict__ src,
     }
 }
 
-// Write node c's 26 populations.
+// Write node c's 26 populations (post-collision values of step `step`).
 template <class St, bool kOff32>
-__device__ __forceinline__ void put(char *__restrict__ dst, size_t node,
+__device__ __forceinline__ void put(char *__restrict__ dst, size_t node, uint32_t step,
                                     const typename St::T f[19], const typename St::T g[7])
 {
     using T = typename St::T;
@@ -289,9 +364,16 @@ __device__ __forceinline__ void put(char *__restrict__ dst, size_t node,
 #pragma unroll
     for (int i = 0; i < 19; ++i)
         A::template st<SF>(dst, Lt::f(c, i), Codec<SF>::enc(f[i], T(inv_w19(i))));
+    if constexpr (std::is_same<SG, Fix16>::value) {
+        const RoundBits rb(uint32_t(node), step);
 #pragma unroll
-    for (int i = 0; i < 7; ++i)
-        A::template st<SG>(dst, Lt::g(c, i), Codec<SG>::enc(g[i], T(inv_w7(i))));
+        for (int i = 0; i < 7; ++i)
+            A::template st<SG>(dst, Lt::g(c, i), Codec<SG>::enc_r(g[i], T(inv_w7(i)), rb.u16(i)));
+    } else {
+#pragma unroll
+        for (int i = 0; i < 7; ++i)
+            A::template st<SG>(dst, Lt::g(c, i), Codec<SG>::enc(g[i], T(inv_w7(i))));
+    }
 }
 
 // -------------------------------------------------------------- step kernel
@@ -311,7 +393,7 @@ __global__ __launch_bounds__(1024) void k_step(const char *__restrict__ src, cha
     T f[19], g[7];
     pull<St, kOff32>(src, geo, x, y, z, f, g);
     collide<T, kForce>(f, g, rates);
-    put<St, kOff32>(dst, size_t(x) + size_t(geo.n) * (size_t(y) + size_t(geo.n) * z), f, g);
+    put<St, kOff32>(dst, size_t(x) + size_t(geo.n) * (size_t(y) + size_t(geo.n) * z), geo.step, f, g);
 }
 
 // --------------------------------------------------------- state sources

@@ -86,13 +86,15 @@ void launch_step_kernels(lbmx_cavity *h, int64_t nsteps)
     const int n = h->p.n;
     dim3 block(h->bx, h->by, 1);
     dim3 grid((n + h->bx - 1) / h->bx, (n + h->by - 1) / h->by, n);
+    Geometry<T> g = geo;
     for (int64_t s = 0; s < nsteps; ++s) {
+        g.step = uint32_t(h->t);
         if (h->off32)
             hipLaunchKernelGGL((k_step<St, true, kForce>), grid, block, 0, h->stream,
-                               lattice(h, h->cur), lattice(h, 1 - h->cur), geo, rates);
+                               lattice(h, h->cur), lattice(h, 1 - h->cur), g, rates);
         else
             hipLaunchKernelGGL((k_step<St, false, kForce>), grid, block, 0, h->stream,
-                               lattice(h, h->cur), lattice(h, 1 - h->cur), geo, rates);
+                               lattice(h, h->cur), lattice(h, 1 - h->cur), g, rates);
         h->cur = 1 - h->cur;
         h->t += 1;
     }

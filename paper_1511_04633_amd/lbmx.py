@@ -16,9 +16,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liblbmx.so")
 
-F64, F32, F16, BF16, F16_F32, BF16_F32 = 0, 1, 2, 3, 4, 5
+F64, F32, F16, BF16, F16_F32, BF16_F32, F16_I16 = 0, 1, 2, 3, 4, 5, 6
 STORAGE = {"f64": F64, "f32": F32, "f16": F16, "bf16": BF16, "f16_f32": F16_F32,
-           "bf16_f32": BF16_F32}
+           "bf16_f32": BF16_F32, "f16_i16": F16_I16}
 STATUS = {0: "LBMX_OK", 1: "LBMX_EINVAL", 2: "LBMX_ENOMEM", 3: "LBMX_EDEVICE",
           4: "LBMX_EUNSTABLE", 5: "LBMX_ENOTCONVERGED", 6: "LBMX_ESTATE", 7: "LBMX_EIO"}
 

@@ -54,7 +54,7 @@ def test_derived_parameters_match_the_oracle():
 
 def test_invalid_parameters_rejected_on_host():
     bad = [dict(n=3), dict(n=2048), dict(wall_type=0), dict(wall_type=4), dict(ra=0.0),
-           dict(ra=-1.0), dict(pr=0.0), dict(ma=0.0), dict(ma=0.9), dict(storage=7),
+           dict(ra=-1.0), dict(pr=0.0), dict(ma=0.0), dict(ma=0.9), dict(storage=7), dict(storage=-1),
            dict(ra=float("inf")), dict(theta_hot=float("nan"))]
     for kw in bad:
         p = L.make_params(**kw)
@@ -72,6 +72,7 @@ def test_sizes():
     assert L.bytes_per_cell("f32") == 208.0
     assert L.bytes_per_cell("f16") == 104.0 and L.bytes_per_cell("bf16") == 104.0
     assert L.bytes_per_cell("f16_f32") == 132.0 and L.bytes_per_cell("bf16_f32") == 132.0
+    assert L.bytes_per_cell("f16_i16") == 104.0
     p = L.make_params(n=256, ra=1e6, storage="f32")
     ws = L.workspace_bytes(p)
     assert ws >= 2 * 26 * 256 ** 3 * 4

@@ -9,6 +9,9 @@ Bounds per format (measured, see the table in the design notes):
   f16_f32    fields 5e-3 u_c, Nu 1e-3      (16-bit flow, FP32 energy)
   f16        fields 3e-2 u_c, Nu 5e-3      (misses the 1e-3 Nu target)
   bf16_f32   fields 5e-2 u_c, Nu 3e-2      (misses the 1e-3 Nu target)
+  f16_i16    fields 5e-3 u_c, Nu 1e-3      (16-bit flow, 16-bit fixed-point energy
+                                           with stochastic rounding: measured
+                                           1.0e-3 u_c, Nu 4e-5)
   bf16       stays finite only             (8-bit significands: far off)
 """
 import numpy as np
@@ -28,6 +31,7 @@ BOUNDS = {  # storage: (field bound in u_c units / abs theta, Nu relative bound)
     "f16_f32": (5e-3, 1e-3),
     "f16": (3e-2, 5e-3),
     "bf16_f32": (5e-2, 3e-2),
+    "f16_i16": (5e-3, 1e-3),
 }
 
 
