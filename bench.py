@@ -12,6 +12,9 @@ roofline: algorithmic bytes per launch (26 populations read + written per
 node, 208 B at FP32) over the average kernel time from HIP events recorded
 on the stream the kernels run on, against the 8 TB/s HBM peak.
 cpu_baseline: the FP64 CPU oracle timed on a bounded sample (64^3, same case).
+time_to_steady: 128^3, Ra 1e5, FP32, wall types 1-3, wall time to |dNu_3D| <
+1e-6 per 1000 steps from rest and from the shipped U-Net's predicted fields
+(warm start; inference and initialisation included).
 """
 from __future__ import annotations
 
@@ -43,22 +46,24 @@ def cpu_baseline(seconds: float, n: int = 64, ra: float = 1e6, wall_type: int = 
             "sample": f"FP64 oracle, {n}^3 Type {wall_type} Ra {ra:g}, {steps} steps in {dt:.1f} s"}
 
 
-def time_to_steady(wall_type: int, n: int = 128, ra: float = 1e5, storage: str = "f32"):
-    """Wall time from rest to |dNu_3D| < 1e-6 per 1000 steps (host clock, all
-    synchronisations included) for the 128^3, Ra 1e5 cavity."""
-    import torch
+def time_to_steady(wall_type: int, net=None, n: int = 128, ra: float = 1e5):
+    """Wall time to |dNu_3D| < 1e-6 per 1000 steps (host clock, all
+    synchronisations included) for the 128^3, Ra 1e5, FP32 cavity, from rest
+    and, when the network is given, from its predicted fields (inference and
+    initialisation inside the timed region)."""
+    from paper_1511_04633_amd import warmstart
 
-    from paper_1511_04633_amd import inputs, lbmx
-
-    cav = lbmx.Cavity(n=n, wall_type=wall_type, ra=ra, storage=storage,
-                      theta0=inputs.theta_noise(n, 20151115))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    r = cav.run_to_steady(tol=1e-6, every=1000, max_steps=2_000_000)
-    dt = time.perf_counter() - t0
-    return {"workload": f"{n}^3 Type {wall_type} Ra {ra:g} {storage}", "seconds": round(dt, 3),
-            "steps": r["step"], "converged": r["converged"], "nu3d": r["nu3d"],
-            "nu2d": r["nu2d"], "numax": r["numax"]}
+    rest = warmstart.solve(n, ra, wall_type, None, max_steps=2_000_000)
+    out = {"workload": f"{n}^3 Type {wall_type} Ra {ra:g} f32", "seconds": rest["seconds"],
+           "steps": rest["steps"], "converged": rest["converged"], "nu3d": rest["nu3d"],
+           "nu2d": rest["nu2d"], "numax": rest["numax"]}
+    if net is not None:
+        warm = warmstart.solve(n, ra, wall_type, net, max_steps=2_000_000)
+        out["warm_start"] = {"seconds": warm["seconds"], "steps": warm["steps"],
+                             "init_s": warm["init_s"], "converged": warm["converged"],
+                             "nu3d": warm["nu3d"],
+                             "nu_rel_diff": abs(warm["nu3d"] - rest["nu3d"]) / rest["nu3d"]}
+    return out
 
 
 def counter_traffic(storage: str, n: int):
@@ -116,8 +121,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-copy-probe", action="store_true",
                     help="skip timing a plain device copy of the same bytes")
-    ap.add_argument("--steady-types", default="1",
+    ap.add_argument("--steady-types", default="1,2,3",
                     help="wall types timed to steady at 128^3 Ra 1e5 (comma list; '' = skip)")
+    ap.add_argument("--no-warm-start", action="store_true",
+                    help="time the steady runs from rest only (no U-Net warm start)")
     ap.add_argument("--force-model", type=int, default=0, choices=[0, 1, 2],
                     help="0 Eq. 15 (default), 1 Eq. 15 / rho, 2 Guo's forcing")
     ap.add_argument("--aniso", default="",
@@ -199,8 +206,13 @@ def main():
     del cav
     torch.cuda.empty_cache()
     steady = []
-    for wt in [int(v) for v in args.steady_types.split(",") if v.strip()]:
-        steady.append(time_to_steady(wt))
+    types = [int(v) for v in args.steady_types.split(",") if v.strip()]
+    net = None
+    if types and not args.no_warm_start:
+        from paper_1511_04633_amd import warmstart
+        net = warmstart.load_net(os.path.join(ROOT, "paper_1511_04633_amd", "weights", "unet64.npz"))
+    for wt in types:
+        steady.append(time_to_steady(wt, net))
     if steady:
         line["time_to_steady"] = steady
     if not args.no_cpu_baseline:
