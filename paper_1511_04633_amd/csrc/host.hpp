@@ -26,7 +26,7 @@ lbmx_status fail(lbmx_status s, const char *fmt, ...) __attribute__((format(prin
             return fail(LBMX_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
 
-// Element bytes of the flow (D3Q19) and energy (D3Q7) planes.
+// Element bytes of the flow (D3Q19) and energy (D3Q7) populations.
 inline size_t flow_size(int32_t s)
 {
     switch (s) {

@@ -21,7 +21,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 KERNEL_SOURCES = ["csrc/collide.hpp", "csrc/kernels.hpp", "csrc/lbmx.hip"]
-# element bytes of the (flow, energy) planes per storage format
+# element bytes of the (flow, energy) populations per storage format
 BYTES = {"f64": (8, 8), "f32": (4, 4), "f16": (2, 2), "bf16": (2, 2), "f16_f32": (2, 4),
          "bf16_f32": (2, 4), "f16_i16": (2, 2)}
 
