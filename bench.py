@@ -15,6 +15,7 @@ cpu_baseline: the FP64 CPU oracle timed on a bounded sample (64^3, same case).
 time_to_steady: 128^3, Ra 1e5, FP32, wall types 1-3, wall time to |dNu_3D| <
 1e-6 per 1000 steps from rest and from the shipped U-Net's predicted fields
 (warm start; inference and initialisation included).
+storage_sweep: every storage format at the same size and case (500 steps each).
 """
 from __future__ import annotations
 
@@ -63,6 +64,35 @@ def time_to_steady(wall_type: int, net=None, n: int = 128, ra: float = 1e5):
                              "init_s": warm["init_s"], "converged": warm["converged"],
                              "nu3d": warm["nu3d"],
                              "nu_rel_diff": abs(warm["nu3d"] - rest["nu3d"]) / rest["nu3d"]}
+    return out
+
+
+def storage_sweep(n: int, wall_type: int, ra: float, steps: int = 500, warmup: int = 100):
+    """Every storage format at the benchmark size: MLUPS (host clock) and the
+    step kernel's HBM roofline fraction (HIP events), same case and start."""
+    import torch
+
+    from paper_1511_04633_amd import inputs, lbmx
+
+    out = []
+    for st in ("f64", "f32", "f16", "bf16", "f16_f32", "bf16_f32", "f16_i16"):
+        cav = lbmx.Cavity(n=n, wall_type=wall_type, ra=ra, storage=st,
+                          theta0=inputs.theta_noise(n, 20151115))
+        cav.step(warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ev_ms = cav.step_timed(steps)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        bpc = lbmx.bytes_per_cell(st)
+        kernel_s = ev_ms / 1e3 / steps
+        out.append({"storage": st, "bytes_per_cell": bpc,
+                    "mlups": round(n ** 3 * steps / wall / 1e6, 1),
+                    "kernel_us": round(kernel_s * 1e6, 2),
+                    "frac": round(n ** 3 * bpc / kernel_s / 1e9 / HBM_PEAK_GBS, 4)})
+        cav.close()
+        del cav
+        torch.cuda.empty_cache()
     return out
 
 
@@ -125,6 +155,8 @@ def main():
                     help="wall types timed to steady at 128^3 Ra 1e5 (comma list; '' = skip)")
     ap.add_argument("--no-warm-start", action="store_true",
                     help="time the steady runs from rest only (no U-Net warm start)")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the storage-format sweep at the benchmark size")
     ap.add_argument("--force-model", type=int, default=0, choices=[0, 1, 2],
                     help="0 Eq. 15 (default), 1 Eq. 15 / rho, 2 Guo's forcing")
     ap.add_argument("--aniso", default="",
@@ -215,6 +247,8 @@ def main():
         steady.append(time_to_steady(wt, net))
     if steady:
         line["time_to_steady"] = steady
+    if not args.no_sweep and not variant:
+        line["storage_sweep"] = storage_sweep(n, args.wall_type, args.ra)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wall_type=args.wall_type, ra=args.ra)
     print(json.dumps(line), flush=True)
