@@ -313,7 +313,7 @@ lbmx_status lbmx_batch_autotune(lbmx_batch *b, const char *cache_path, double *u
 
 /* out[p][co] = bias[co] + sum_{tap,ci} w[co][tap][ci] in[p + off(tap)][ci];
  * out is BF16 (out_f32 = 0) or FP32 [B][D][H][W][Co].  bias may be NULL.
- * 16 <= Ci <= 1024, 16 <= Co <= 160, multiples of 16. */
+ * 16 <= Ci, Co <= 1024, multiples of 16; B D H W < 2^31.  EINVAL otherwise. */
 lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias, void *out,
                                int32_t out_f32, int32_t B, int32_t D, int32_t H, int32_t W,
                                int32_t Ci, int32_t Co, void *stream);
@@ -324,7 +324,8 @@ lbmx_status lbmx_nn_conv3d_flip(const void *w, void *wt, int32_t Ci, int32_t Co,
 
 /* gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci] and, if gb is
  * not NULL, gb[co] += sum_p gout[p][co] (FP32, accumulated atomically, so
- * the summation order varies between runs).  (Co/16)(Ci/16) <= 64. */
+ * the summation order varies between runs).  16 <= Ci, Co <= 1024,
+ * multiples of 16; B D H W max(Ci, Co) < 2^31.  EINVAL otherwise. */
 lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, float *gb, int32_t B,
                                  int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
                                  void *stream);

@@ -638,8 +638,11 @@ lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias,
         return st;
     if (!in || !w || !out)
         return fail(LBMX_EINVAL, "conv3d: NULL tensor");
-    if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 160)
-        return fail(LBMX_EINVAL, "conv3d: need Ci, Co multiples of 16, Ci <= 1024, Co <= 160");
+    if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 1024)
+        return fail(LBMX_EINVAL, "conv3d: need Ci, Co multiples of 16 in [16, 1024]");
+    if ((long long)B * D * H * W >= (1LL << 31))
+        return fail(LBMX_EINVAL, "conv3d: %lld voxels exceed 32-bit voxel indices",
+                    (long long)B * D * H * W);
     const Dims d{B, D, H, W, Ci, Co};
     const bf *i = reinterpret_cast<const bf *>(in);
     const bf *wb = reinterpret_cast<const bf *>(w);

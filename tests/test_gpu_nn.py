@@ -64,7 +64,7 @@ def P(t):
 
 
 SHAPES = [(2, 6, 6, 6), (1, 5, 4, 7), (1, 9, 10, 35)]  # the last: 3 ragged bricks per axis
-CHANNELS = [(16, 16), (48, 16), (16, 32), (32, 96), (160, 64), (16, 160)]
+CHANNELS = [(16, 16), (48, 16), (16, 32), (32, 96), (160, 64), (16, 160), (16, 256)]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
