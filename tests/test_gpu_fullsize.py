@@ -49,7 +49,7 @@ def sample_nodes(n, seed=7):
     return sorted(pts)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16"])
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16_i16"])
 def test_sampled_step_at_256cube(storage):
     print(f"case: full size 256^3 T1 Ra1e6 {storage}, sampled one-step parity", flush=True)
     cav = L.Cavity(n=N, wall_type=1, ra=1e6, storage=storage,
@@ -82,6 +82,10 @@ def test_sampled_step_at_256cube(storage):
             vf, vg = np.abs(fo / W19 - 1), np.abs(go / W7)
             tol_f = W19 * (2.0 ** -10 * vf + 2.0 ** -24) + 1e-8
             tol_g = W7 * (2.0 ** -10 * vg + 2.0 ** -24) + 1e-8
+            if storage == "f16_i16":
+                # stochastic rounding to the fixed-point grid: within one
+                # spacing 2^-14 of g/w_T
+                tol_g = W7 * 2.0 ** -14 + 1e-8
         assert np.all(df <= tol_f), ((x, y, z), df.max())
         assert np.all(dg <= tol_g), ((x, y, z), dg.max())
         worst_f, worst_g = max(worst_f, df.max()), max(worst_g, dg.max())
