@@ -13,8 +13,9 @@ node, 208 B at FP32) over the average kernel time from HIP events recorded
 on the stream the kernels run on, against the 8 TB/s HBM peak.
 cpu_baseline: the FP64 CPU oracle timed on a bounded sample (64^3, same case).
 time_to_steady: 128^3, Ra 1e5, FP32, wall types 1-3, wall time to |dNu_3D| <
-1e-6 per 1000 steps from rest and from the shipped U-Net's predicted fields
-(warm start; inference and initialisation included).
+1e-6 per 1000 steps from rest, from the shipped U-Net's predicted fields
+(warm start; inference and initialisation included), and by grid sequencing
+(the prediction run to steady on 64^3 first, that solve included).
 storage_sweep: every storage format at the same size and case (500 steps each).
 """
 from __future__ import annotations
@@ -47,11 +48,14 @@ def cpu_baseline(seconds: float, n: int = 64, ra: float = 1e6, wall_type: int = 
             "sample": f"FP64 oracle, {n}^3 Type {wall_type} Ra {ra:g}, {steps} steps in {dt:.1f} s"}
 
 
-def time_to_steady(wall_type: int, net=None, n: int = 128, ra: float = 1e5):
+def time_to_steady(wall_type: int, net=None, coarse: int = 64, n: int = 128, ra: float = 1e5):
     """Wall time to |dNu_3D| < 1e-6 per 1000 steps (host clock, all
-    synchronisations included) for the 128^3, Ra 1e5, FP32 cavity, from rest
-    and, when the network is given, from its predicted fields (inference and
-    initialisation inside the timed region)."""
+    synchronisations included) for the 128^3, Ra 1e5, FP32 cavity, from rest;
+    when the network is given, from its predicted fields (inference and
+    initialisation inside the timed region); with coarse = m > 0, by grid
+    sequencing: the m^3 cavity run to steady by the same criterion (from the
+    network's fields, or from rest without a network) starts the 128^3 one
+    (coarse solve inside the timed region)."""
     from paper_1511_04633_amd import warmstart
 
     rest = warmstart.solve(n, ra, wall_type, None, max_steps=2_000_000)
@@ -64,6 +68,13 @@ def time_to_steady(wall_type: int, net=None, n: int = 128, ra: float = 1e5):
                              "init_s": warm["init_s"], "converged": warm["converged"],
                              "nu3d": warm["nu3d"],
                              "nu_rel_diff": abs(warm["nu3d"] - rest["nu3d"]) / rest["nu3d"]}
+    if coarse:
+        ml = warmstart.solve(n, ra, wall_type, net, coarse=coarse, max_steps=2_000_000)
+        out["multilevel"] = {"seconds": ml["seconds"], "steps": ml["steps"],
+                             "start": "network" if net is not None else "rest",
+                             "coarse": ml["coarse"], "init_s": ml["init_s"],
+                             "converged": ml["converged"], "nu3d": ml["nu3d"],
+                             "nu_rel_diff": abs(ml["nu3d"] - rest["nu3d"]) / rest["nu3d"]}
     return out
 
 
@@ -155,6 +166,8 @@ def main():
                     help="wall types timed to steady at 128^3 Ra 1e5 (comma list; '' = skip)")
     ap.add_argument("--no-warm-start", action="store_true",
                     help="time the steady runs from rest only (no U-Net warm start)")
+    ap.add_argument("--coarse", type=int, default=64,
+                    help="grid-sequenced steady runs from a coarse^3 steady cavity (0 = skip)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the storage-format sweep at the benchmark size")
     ap.add_argument("--force-model", type=int, default=0, choices=[0, 1, 2],
@@ -244,7 +257,7 @@ def main():
         from paper_1511_04633_amd import warmstart
         net = warmstart.load_net(os.path.join(ROOT, "paper_1511_04633_amd", "weights", "unet64.npz"))
     for wt in types:
-        steady.append(time_to_steady(wt, net))
+        steady.append(time_to_steady(wt, net, coarse=args.coarse))
     if steady:
         line["time_to_steady"] = steady
     if not args.no_sweep and not variant:

@@ -192,6 +192,20 @@ lbmx_status lbmx_load(lbmx_cavity *h, const char *path);
 lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *dev_v,
                              const float *dev_w, const float *dev_theta, int32_t src_n);
 
+/* Set dst's state at t = 0 from the current state of another cavity src of
+ * any size, storage or parameter set (grid sequencing: a coarse cavity's
+ * steady state as the start of a finer one; the paper fixes no initial
+ * state).  src's fields rho, u = j / rho, theta (Eqs. 20, 25, 30; the
+ * half-force velocity under Guo's forcing) are formed on the device in
+ * FP64, sampled trilinearly onto dst's nodes as in lbmx_init_fields, the
+ * velocities multiplied by u_c(dst) / u_c(src) (Eq. 38: equal unless Ma
+ * differs), and dst takes f = f^eq(1, u), g = g^eq(theta, u).  src is only
+ * read.  Both cavities must live on the current device.  Allocates and
+ * frees a 32 src_n^3-byte device buffer; synchronises both streams.
+ * Errors: EINVAL for a NULL, failed or identical handle or another device,
+ * EDEVICE for a HIP failure. */
+lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src);
+
 /* Advance nsteps >= 0 time steps (fused streaming + double-MRT collision,
  * Eqs. 14 and 29, wall conditions of Eqs. 6-10).  Asynchronous. */
 lbmx_status lbmx_step(lbmx_cavity *h, int64_t nsteps);

@@ -302,6 +302,31 @@ void oracle_feq(double rho, const double *v, double *feq)
     }
 }
 
+/* Eq. (33): equilibrium moments of the energy populations. */
+static void thermal_neq(double theta, const double *v, double *neq)
+{
+    neq[0] = theta;
+    neq[1] = v[0] * theta;
+    neq[2] = v[1] * theta;
+    neq[3] = v[2] * theta;
+    neq[4] = A_THERMAL * theta;
+    neq[5] = 0.0;
+    neq[6] = 0.0;
+}
+
+/* The energy populations whose moments are n^eq of Eq. (33): N^-1 n^eq. */
+void oracle_geq(double theta, const double *v, double *geq)
+{
+    double ninv[Q7 * Q7], neq[Q7];
+    oracle_matrices(NULL, NULL, NULL, ninv);
+    thermal_neq(theta, v, neq);
+    for (int i = 0; i < Q7; ++i) {
+        geq[i] = 0.0;
+        for (int k = 0; k < Q7; ++k)
+            geq[i] += ninv[i * Q7 + k] * neq[k];
+    }
+}
+
 /* Eq. (15) under reading R3, with G = (0, 0, gz) (Eq. 16, reading R7), dt = 1. */
 void oracle_force(double rho, const double *v, double gz, double *force)
 {
@@ -400,13 +425,7 @@ static void collide_node(const oracle *o, const double *f, const double *g,
         for (int i = 0; i < Q7; ++i)
             n[k] += N7[k][i] * g[i];
     }
-    neq[0] = theta;
-    neq[1] = v[0] * theta;
-    neq[2] = v[1] * theta;
-    neq[3] = v[2] * theta;
-    neq[4] = A_THERMAL * theta;
-    neq[5] = 0.0;
-    neq[6] = 0.0;
+    thermal_neq(theta, v, neq);
     for (int k = 0; k < Q7; ++k) {
         dn[k] = 0.0;
         for (int l = 0; l < Q7; ++l)

@@ -73,6 +73,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_velocities.argtypes = [_ip, _dp, _ip, _dp]
         L.oracle_meq.argtypes = [ctypes.c_double] * 4 + [_dp]
         L.oracle_feq.argtypes = [ctypes.c_double, _dp, _dp]
+        L.oracle_geq.argtypes = [ctypes.c_double, _dp, _dp]
         L.oracle_force.argtypes = [ctypes.c_double, _dp, ctypes.c_double, _dp]
         L.oracle_guo_force.argtypes = [ctypes.c_double, _dp, ctypes.c_double, _dp]
         L.oracle_collide_node.argtypes = [ctypes.c_void_p, _dp, _dp, _dp, _dp]
@@ -123,6 +124,47 @@ def feq(rho, v):
     out = np.zeros(19)
     lib().oracle_feq(rho, _ptr(v), _ptr(out))
     return out
+
+
+def geq(theta, v):
+    """Energy populations whose moments are n^eq of Eq. (33): N^-1 n^eq."""
+    v = np.ascontiguousarray(v, dtype=np.float64)
+    out = np.zeros(7)
+    lib().oracle_geq(theta, _ptr(v), _ptr(out))
+    return out
+
+
+def equilibrium_state(ux, uy, uz, theta):
+    """Pre-collision state with f = f^eq(rho = 1, u) (Eq. 17) and
+    g = N^-1 n^eq(theta, u) (Eq. 33) at every node: the state a warm start
+    builds from velocity and temperature fields (the paper fixes no initial
+    state).  Fields of n^3 values, x fastest; returns (f 19 x n^3, g 7 x n^3)."""
+    fs = [np.asarray(a, dtype=np.float64).reshape(-1) for a in (ux, uy, uz, theta)]
+    cells = fs[0].size
+    f, g = np.zeros((19, cells)), np.zeros((7, cells))
+    for c in range(cells):
+        v = np.array([fs[0][c], fs[1][c], fs[2][c]])
+        f[:, c] = feq(1.0, v)
+        g[:, c] = geq(fs[3][c], v)
+    return f, g
+
+
+def resample(a, m):
+    """Trilinear resampling of a node-centred field of the unit cube (n^3,
+    indexed [z, y, x]) onto its m^3 node centres.  Output node i sits at
+    p = (i + 1/2) n / m - 1/2 in input node units, clamped to [0, n - 1]
+    (outside the outermost node centres the field is taken constant); the
+    weights are linear in each axis, applied along x, then y, then z.  Used
+    to move fields between grids for warm starts; not part of the paper."""
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[0]
+    p = np.clip((np.arange(m) + 0.5) * n / m - 0.5, 0.0, n - 1.0)
+    k0 = np.minimum(np.floor(p).astype(np.int64), max(n - 2, 0))
+    k1 = np.minimum(k0 + 1, n - 1)
+    fr = p - k0
+    out = a[:, :, k0] * (1 - fr) + a[:, :, k1] * fr
+    out = out[:, k0, :] * (1 - fr)[None, :, None] + out[:, k1, :] * fr[None, :, None]
+    return out[k0] * (1 - fr)[:, None, None] + out[k1] * fr[:, None, None]
 
 
 def force(rho, v, gz):

@@ -350,11 +350,11 @@ lbmx_status unstream_pops(const View &v, const double *f, const double *g)
     return launch_unstream<St>(v, SourcePops{f, g, (size_t)v.n * v.n * v.n});
 }
 
-template <class St>
-lbmx_status unstream_fields(const View &v, const float *u, const float *w2, const float *w,
-                            const float *th, int src_n)
+template <class St, class E>
+lbmx_status unstream_fields(const View &v, const E *u, const E *w2, const E *w, const E *th,
+                            int src_n, double vscale)
 {
-    return launch_unstream<St>(v, SourceFields{u, w2, w, th, src_n, v.n});
+    return launch_unstream<St>(v, SourceFields<E>{u, w2, w, th, src_n, v.n, E(vscale)});
 }
 
 // Device buffer released at scope exit (after the work using it completed:

@@ -413,42 +413,46 @@ struct SourcePops {            // full population arrays f[19][n^3], g[7][n^3]
 };
 
 // Velocity / temperature fields sampled trilinearly from a node-centred
-// src_n^3 grid: f = f^eq(1, u) (Eq. 17) and g = w_T theta (1 + 4 e.u),
-// whose moments are n^eq of Eq. (33).
+// src_n^3 grid of element type E (FP32 fields from a caller or a network,
+// FP64 fields of another cavity): f = f^eq(1, u) (Eq. 17) and
+// g = w_T theta (1 + 4 e.u), whose moments are n^eq of Eq. (33).  The
+// sampled velocities are multiplied by vscale (1 keeps them bitwise).
+template <class E>
 struct SourceFields {
-    const float *u, *v, *w, *th;
+    const E *u, *v, *w, *th;
     int src_n, n;
-    __device__ float sample(const float *a, int x, int y, int z) const
+    E vscale;
+    __device__ E sample(const E *a, int x, int y, int z) const
     {
-        const float s = float(src_n) / float(n);
-        float p[3] = {(x + 0.5f) * s - 0.5f, (y + 0.5f) * s - 0.5f, (z + 0.5f) * s - 0.5f};
+        const E s = E(src_n) / E(n);
+        E p[3] = {(x + E(0.5)) * s - E(0.5), (y + E(0.5)) * s - E(0.5), (z + E(0.5)) * s - E(0.5)};
         int i0[3];
-        float fr[3];
+        E fr[3];
         for (int d = 0; d < 3; ++d) {
-            float q = fminf(fmaxf(p[d], 0.0f), float(src_n - 1));
-            int k = min(int(floorf(q)), src_n - 2 < 0 ? 0 : src_n - 2);
+            E q = fmin(fmax(p[d], E(0)), E(src_n - 1));
+            int k = min(int(floor(q)), src_n - 2 < 0 ? 0 : src_n - 2);
             i0[d] = k;
-            fr[d] = q - float(k);
+            fr[d] = q - E(k);
         }
         auto at = [&](int dx, int dy, int dz) {
             int xx = min(i0[0] + dx, src_n - 1), yy = min(i0[1] + dy, src_n - 1),
                 zz = min(i0[2] + dz, src_n - 1);
             return a[xx + (size_t)src_n * (yy + (size_t)src_n * zz)];
         };
-        float c00 = at(0, 0, 0) * (1 - fr[0]) + at(1, 0, 0) * fr[0];
-        float c10 = at(0, 1, 0) * (1 - fr[0]) + at(1, 1, 0) * fr[0];
-        float c01 = at(0, 0, 1) * (1 - fr[0]) + at(1, 0, 1) * fr[0];
-        float c11 = at(0, 1, 1) * (1 - fr[0]) + at(1, 1, 1) * fr[0];
-        float c0 = c00 * (1 - fr[1]) + c10 * fr[1];
-        float c1 = c01 * (1 - fr[1]) + c11 * fr[1];
+        E c00 = at(0, 0, 0) * (1 - fr[0]) + at(1, 0, 0) * fr[0];
+        E c10 = at(0, 1, 0) * (1 - fr[0]) + at(1, 1, 0) * fr[0];
+        E c01 = at(0, 0, 1) * (1 - fr[0]) + at(1, 0, 1) * fr[0];
+        E c11 = at(0, 1, 1) * (1 - fr[0]) + at(1, 1, 1) * fr[0];
+        E c0 = c00 * (1 - fr[1]) + c10 * fr[1];
+        E c1 = c01 * (1 - fr[1]) + c11 * fr[1];
         return c0 * (1 - fr[2]) + c1 * fr[2];
     }
     __device__ void node(int c, double *vel, double &theta) const
     {
         int x = c % n, y = (c / n) % n, z = c / (n * n);
-        vel[0] = sample(u, x, y, z);
-        vel[1] = sample(v, x, y, z);
-        vel[2] = sample(w, x, y, z);
+        vel[0] = sample(u, x, y, z) * vscale;
+        vel[1] = sample(v, x, y, z) * vscale;
+        vel[2] = sample(w, x, y, z) * vscale;
         theta = sample(th, x, y, z);
     }
     __device__ double f(int i, int c) const

@@ -480,11 +480,51 @@ lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *de
     if (src_n < 1 || src_n > 4096)
         return fail(LBMX_EINVAL, "src_n = %d outside [1, 4096]", src_n);
     h->cur = 0;
-    s = LBMX_DISPATCH(h->p.storage, unstream_fields, view(h), dev_u, dev_v, dev_w, dev_theta, src_n);
+    s = LBMX_DISPATCH(h->p.storage, unstream_fields, view(h), dev_u, dev_v, dev_w, dev_theta, src_n,
+                      1.0);
     if (s != LBMX_OK)
         return s;
     HIP_TRY(hipStreamSynchronize(h->stream));
     h->t = 0;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src)
+{
+    lbmx_status s = check_handle(dst);
+    if (s != LBMX_OK)
+        return s;
+    s = check_handle(src);
+    if (s != LBMX_OK)
+        return s;
+    if (src == dst)
+        return fail(LBMX_EINVAL, "source and destination are the same cavity");
+    hipPointerAttribute_t as, ad;
+    HIP_TRY(hipPointerGetAttributes(&as, src->ws));
+    HIP_TRY(hipPointerGetAttributes(&ad, dst->ws));
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (as.device != ad.device || ad.device != dev)
+        return fail(LBMX_EINVAL, "cavities on devices %d and %d, current device %d", as.device,
+                    ad.device, dev);
+    const int m = src->p.n;
+    const size_t mc = (size_t)m * m * m;
+    DevBuf buf;
+    HIP_TRY(hipMalloc(&buf.p, 4 * mc * sizeof(double)));
+    double *f4 = reinterpret_cast<double *>(buf.p);
+    s = LBMX_DISPATCH(src->p.storage, launch_macro, view(src), nullptr, f4, f4 + mc, f4 + 2 * mc,
+                      f4 + 3 * mc);
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(src->stream));
+    dst->cur = 0;
+    s = LBMX_DISPATCH(dst->p.storage, unstream_fields, view(dst), (const double *)f4,
+                      (const double *)(f4 + mc), (const double *)(f4 + 2 * mc),
+                      (const double *)(f4 + 3 * mc), m, dst->d.u_c / src->d.u_c);
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(dst->stream));
+    dst->t = 0;
     return LBMX_OK;
 }
 

@@ -36,6 +36,15 @@ def theta_noise(n: int, seed: int, amp: float = 1e-6) -> np.ndarray:
     return amp * (2.0 * uniform01(seed, n ** 3) - 1.0)
 
 
+def random_fields(n: int, seed: int, u_amp: float = 0.03, theta_amp: float = 0.5) -> np.ndarray:
+    """Velocity and temperature fields for initialisation tests: u, v, w
+    uniform in [-u_amp, u_amp) and theta in [-theta_amp, theta_amp) per node,
+    FP32, shaped (4, n, n, n) indexed [field, z, y, x]."""
+    u = 2.0 * uniform01(seed, 4 * n ** 3).reshape(4, n, n, n) - 1.0
+    amp = np.array([u_amp, u_amp, u_amp, theta_amp])[:, None, None, None]
+    return (amp * u).astype(np.float32)
+
+
 def batch_cases(seed: int, count: int, sizes=(32, 48, 64, 80, 96),
                 log10_ra=(3.0, 6.0), wall_types=(1, 2, 3)):
     """A batch of cavities: edge length uniform over `sizes`, Ra log-uniform in

@@ -26,7 +26,8 @@ STATUS = {0: "LBMX_OK", 1: "LBMX_EINVAL", 2: "LBMX_ENOMEM", 3: "LBMX_EDEVICE",
 SYMBOLS = [
     "lbmx_params_default", "lbmx_derive", "lbmx_workspace_bytes", "lbmx_bytes_per_cell",
     "lbmx_create", "lbmx_destroy", "lbmx_init_rest", "lbmx_set_populations",
-    "lbmx_get_populations", "lbmx_save", "lbmx_load", "lbmx_init_fields", "lbmx_step", "lbmx_step_timed", "lbmx_time",
+    "lbmx_get_populations", "lbmx_save", "lbmx_load", "lbmx_init_fields", "lbmx_init_from_cavity",
+    "lbmx_step", "lbmx_step_timed", "lbmx_time",
     "lbmx_read_macro", "lbmx_nusselt", "lbmx_run_to_steady", "lbmx_set_launch",
     "lbmx_get_launch", "lbmx_strerror", "lbmx_last_error",
     "lbmx_batch_create", "lbmx_batch_destroy", "lbmx_batch_init_rest", "lbmx_batch_step",
@@ -99,6 +100,7 @@ def load() -> ctypes.CDLL:
         "lbmx_save": [_vp, ctypes.c_char_p],
         "lbmx_load": [_vp, ctypes.c_char_p],
         "lbmx_init_fields": [_vp, _vp, _vp, _vp, _vp, i32],
+        "lbmx_init_from_cavity": [_vp, _vp],
         "lbmx_step": [_vp, i64],
         "lbmx_step_timed": [_vp, i64, _dp],
         "lbmx_time": [_vp, ctypes.POINTER(i64)],
@@ -243,6 +245,12 @@ class Cavity:
                 raise ValueError("fields must be float32 CUDA tensors of m^3 values")
         self._keep_fields = ts
         _check(load().lbmx_init_fields(self._h, *[_vp(t.data_ptr()) for t in ts], int(m)))
+        return self
+
+    def init_from(self, other: "Cavity"):
+        """State at t = 0 from another cavity's current fields, resampled
+        onto this cavity's nodes on the device (``lbmx_init_from_cavity``)."""
+        _check(load().lbmx_init_from_cavity(self._h, other._h))
         return self
 
     def set_populations(self, f, g, t=0):

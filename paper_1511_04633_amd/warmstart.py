@@ -9,8 +9,9 @@ CLI:
       generates the 64-cavity training set with the batched solver, trains,
       saves the weights and prints the loss history summary;
   python -m paper_1511_04633_amd.warmstart eval --weights weights.npz
-      [--ra 2e4,3e5,8e5] [--types 1,2,3] [--n 192]
-      prints one JSON line per case.
+      [--ra 2e4,3e5,8e5] [--types 1,2,3] [--n 192] [--coarse 64]
+      prints one JSON line per case; with --coarse also the grid-sequenced
+      start (network -> steady coarse^3 cavity -> n^3 cavity).
 """
 from __future__ import annotations
 
@@ -56,24 +57,43 @@ def load_net(path):
     return net
 
 
-def solve(n, ra, wt, net=None, tol=1e-6, every=1000, max_steps=400_000, history=False):
-    """Run one cavity to steady from rest (net None) or from the network's
-    fields.  With history, step in chunks of `every` from Python (same
-    criterion as lbmx_run_to_steady) and also report the first step after
-    which Nu_3D stays within 1e-3 of its final value."""
+def solve(n, ra, wt, net=None, coarse=0, tol=1e-6, every=1000, max_steps=400_000,
+          history=False):
+    """Run one cavity to steady from rest (net None, coarse 0), from the
+    network's fields (net), or by grid sequencing (coarse = m > 0): an m^3
+    cavity of the same case is first run to steady by the same criterion,
+    from the network's fields or from rest, and the n^3 cavity starts from
+    its fields (``Cavity.init_from``).  Wall time covers inference, the
+    coarse solve and every initialisation.  With history, step in chunks of
+    `every` from Python (same criterion as lbmx_run_to_steady) and also
+    report the first step after which Nu_3D stays within 1e-3 of its final
+    value."""
     import torch
+
+    def start_from_net(c):
+        f = unet.predict_fields(net, np.log10(ra), wt, u_c=c.derived()["u_c"])
+        fv = f.view(4, net.m, net.m, net.m)
+        c.init_fields(fv[0], fv[1], fv[2], fv[3])
 
     cav = lbmx.Cavity(n=n, wall_type=wt, ra=ra, storage="f32",
                       theta0=inputs.theta_noise(n, 20151115))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     t_init = 0.0
-    if net is not None:
-        u_c = cav.derived()["u_c"]
-        f = unet.predict_fields(net, np.log10(ra), wt, u_c=u_c)
-        m = net.m
-        fv = f.view(4, m, m, m)
-        cav.init_fields(fv[0], fv[1], fv[2], fv[3])
+    coarse_info = None
+    if coarse:
+        cc = lbmx.Cavity(n=coarse, wall_type=wt, ra=ra, storage="f32",
+                         theta0=inputs.theta_noise(coarse, 20151115))
+        if net is not None:
+            start_from_net(cc)
+        rc = cc.run_to_steady(tol=tol, every=every, max_steps=max_steps)
+        cav.init_from(cc)
+        cc.close()
+        coarse_info = {"n": coarse, "steps": rc["step"], "converged": rc["converged"],
+                       "nu3d": rc["nu3d"]}
+        t_init = time.perf_counter() - t0
+    elif net is not None:
+        start_from_net(cav)
         torch.cuda.synchronize()
         t_init = time.perf_counter() - t0
     hist = None
@@ -95,6 +115,8 @@ def solve(n, ra, wt, net=None, tol=1e-6, every=1000, max_steps=400_000, history=
     dt = time.perf_counter() - t0
     out = {"steps": r["step"], "seconds": round(dt, 3), "init_s": round(t_init, 4),
            "converged": r["converged"], "nu3d": r["nu3d"], "nu2d": r["nu2d"], "numax": r["numax"]}
+    if coarse_info is not None:
+        out["coarse"] = coarse_info
     if hist is not None:
         final = hist[-1][1]
         within = 0
@@ -119,6 +141,12 @@ def eval_main(a):
                     "step_ratio": warm["steps"] / max(rest["steps"], 1),
                     "time_ratio": warm["seconds"] / rest["seconds"],
                     "nu_rel_diff": abs(warm["nu3d"] - rest["nu3d"]) / rest["nu3d"]}
+            if a.coarse:
+                ml = solve(a.n, ra, wt, net, coarse=a.coarse, max_steps=a.max_steps,
+                           history=a.history)
+                line["multilevel"] = ml
+                line["multilevel_time_ratio"] = ml["seconds"] / rest["seconds"]
+                line["multilevel_nu_rel_diff"] = abs(ml["nu3d"] - rest["nu3d"]) / rest["nu3d"]
             print(json.dumps(line), flush=True)
 
 
@@ -141,6 +169,8 @@ def main(argv=None):
     e.add_argument("--types", default="1,2,3")
     e.add_argument("--n", type=int, default=192)
     e.add_argument("--max-steps", type=int, default=400_000)
+    e.add_argument("--coarse", type=int, default=0,
+                   help="also solve by grid sequencing: network -> coarse^3 steady -> n^3")
     e.add_argument("--history", action="store_true",
                    help="log Nu every 1000 steps and report steps to within 1e-3 of the final Nu")
     a = ap.parse_args(argv)

@@ -1,0 +1,138 @@
+"""Initial states built from fields on the GPU against the FP64 oracle.
+
+lbmx_init_fields (fields of a caller or the network, FP32) and
+lbmx_init_from_cavity (the fields of another cavity, FP64 on the device)
+sample trilinearly onto the cavity's nodes and set f = f^eq(1, u) (Eq. 17),
+g = N^-1 n^eq(theta, u) (Eq. 33).  The oracle builds the same state from the
+same seeded inputs (oracle.resample, oracle.equilibrium_state); for
+init_from_cavity it also steps its own copy of the source cavity.  The paper
+fixes no initial state (it is a warm start); what is checked is that the
+state the GPU writes is the one defined above.  Grid sequencing, the use of
+init_from_cavity, is checked for its gain at the end."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1511_04633_amd import inputs
+from paper_1511_04633_amd import lbmx as L
+
+pytestmark = pytest.mark.gpu
+
+SEED = 20151115
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _setup():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    L.load()
+    O.build(force=False)
+
+
+def dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("m,n", [(6, 9), (8, 8), (11, 5)])
+def test_init_fields_is_the_equilibrium_of_the_sampled_fields(storage, m, n):
+    print(f"case: init_fields {m}^3 -> {n}^3 {storage}", flush=True)
+    fld = inputs.random_fields(m, SEED + m)
+    cav = L.Cavity(n=n, wall_type=2, ra=1e3, storage=storage)
+    d = dev(fld)
+    cav.init_fields(d[0], d[1], d[2], d[3])
+    assert cav.t == 0
+    f, g = cav.get_populations()
+    cav.close()
+    fe, ge = O.equilibrium_state(*[O.resample(a.astype(np.float64), n) for a in fld])
+    if storage == "f64" and m == n:
+        tol_f = tol_g = 1e-15  # identical grids: weights 1 and 0, exact samples
+    else:
+        # The GPU samples FP32 fields in FP32: each sample position carries a
+        # few roundings of (x + 1/2) m / n (<= 4 ulp of m per axis) and the
+        # field may jump by 2 amp between neighbouring nodes, so a sample is
+        # within 3 * 4 * 2^-24 m * 2 amp (+ 8 ulp of amp for the lerps); f and
+        # g change by at most 1.2 and 0.3 times that (w_i <= 1/3, |u| < 0.1).
+        eps = 2.0 ** -24
+
+        def sample_bound(amp):
+            return 3 * 4 * eps * max(m, n) * 2 * amp + 8 * eps * amp
+
+        tol_f = 1.2 * sample_bound(0.03) + 2e-9    # + FP32 storage of f - w
+        tol_g = 0.3 * sample_bound(0.5) + 4e-8      # + FP32 storage of g
+    assert np.abs(f - fe).max() <= tol_f, np.abs(f - fe).max()
+    assert np.abs(g - ge).max() <= tol_g, np.abs(g - ge).max()
+    print({"max |df|": np.abs(f - fe).max(), "max |dg|": np.abs(g - ge).max()})
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+@pytest.mark.parametrize("m,n,ma", [(8, 12, 0.1), (10, 7, 0.05)])
+def test_init_from_cavity(storage, m, n, ma):
+    """A developed source cavity (20 steps from random fields, FP64 storage)
+    initialises a cavity of another size, and with another Ma (velocities
+    scaled by u_c(dst) / u_c(src), Eq. 38)."""
+    print(f"case: init_from_cavity {m}^3 -> {n}^3 Ma {ma} {storage}", flush=True)
+    fld = inputs.random_fields(m, SEED + 7 * m)
+    src = L.Cavity(n=m, wall_type=2, ra=1e3, storage="f64")
+    d = dev(fld)
+    src.init_fields(d[0], d[1], d[2], d[3])
+    src.step(20)
+    before = src.get_populations()
+    dst = L.Cavity(n=n, wall_type=2, ra=1e3, ma=ma, storage=storage)
+    dst.step(3)
+    dst.init_from(src)
+    assert dst.t == 0
+    f, g = dst.get_populations()
+    after = src.get_populations()
+    assert all(np.array_equal(a, b) for a, b in zip(before, after))  # src only read
+    with pytest.raises(L.LbmxError):
+        src.init_from(src)
+    src.close()
+    dst.close()
+
+    ora = O.Oracle(m, 2, ra=1e3)
+    ora.set_state(*O.equilibrium_state(*fld.astype(np.float64)))
+    ora.step(20)
+    rho, ux, uy, uz, th = ora.macro()
+    scale = O.derive(n, 1e3, ma=ma)["u_c"] / O.derive(m, 1e3)["u_c"]
+    r = [O.resample(a, n) for a in (ux, uy, uz, th)]
+    fe, ge = O.equilibrium_state(r[0] * scale, r[1] * scale, r[2] * scale, r[3])
+    # FP64: 20 steps of GPU-vs-oracle rounding; FP32: storage rounding
+    tol = 1e-12 if storage == "f64" else 1e-8
+    assert np.abs(f - fe).max() <= tol, np.abs(f - fe).max()
+    assert np.abs(g - ge).max() <= tol, np.abs(g - ge).max()
+
+
+def test_init_from_cavity_across_storage_formats():
+    """A 16-bit source feeds an FP32 cavity: the FP32 cavity's fields are
+    the source's fields (same grid) within the 16-bit format's resolution."""
+    print("case: init_from_cavity f16_i16 -> f32 same grid", flush=True)
+    n = 12
+    src = L.Cavity(n=n, wall_type=1, ra=1e5, storage="f16_i16", theta0=inputs.theta_noise(n, SEED))
+    src.step(300)
+    dst = L.Cavity(n=n, wall_type=1, ra=1e5, storage="f32")
+    dst.init_from(src)
+    a, b = src.read_macro(), dst.read_macro()
+    assert np.abs(b[0] - 1).max() < 1e-6                          # rho = 1
+    for k in (1, 2, 3, 4):                                          # u, v, w, theta
+        assert np.abs(a[k] - b[k]).max() <= 1e-6 * max(1.0, np.abs(a[k]).max()), k
+    src.close()
+    dst.close()
+
+
+@pytest.mark.parametrize("wall_type", [1, 3])
+def test_grid_sequencing_reaches_the_same_steady_state_sooner(wall_type):
+    """A 48^3 cavity run to steady, resampled onto 96^3, reaches the 96^3
+    rest start's steady Nu (same criterion, |dNu| < 1e-6 per 1000 steps) in
+    fewer fine steps and less wall time, coarse solve included.  (Below
+    ~64^3 a step costs about one kernel launch, 4-12 us, whatever the size,
+    so the coarse level saves steps but not time there.)"""
+    from paper_1511_04633_amd import warmstart
+    print(f"case: grid sequencing 48^3 -> 96^3 Ra 1e5 type {wall_type}", flush=True)
+    rest = warmstart.solve(96, 1e5, wall_type, None)
+    seq = warmstart.solve(96, 1e5, wall_type, None, coarse=48)
+    print(rest, seq)
+    assert rest["converged"] and seq["converged"] and seq["coarse"]["converged"]
+    assert abs(seq["nu3d"] - rest["nu3d"]) <= 1e-3 * rest["nu3d"]
+    assert seq["steps"] < 0.7 * rest["steps"] and seq["seconds"] < rest["seconds"]

@@ -170,6 +170,50 @@ def test_thermal_equilibrium_moments():
         assert np.abs(n @ geq - want).max() < 1e-15
 
 
+def test_oracle_thermal_equilibrium_closed_form():
+    """The oracle's N^-1 n^eq (Eq. 33, inverse by elimination) is the
+    velocity-space form w_T,i theta (1 + 4 e_i . V), and the warm-start state
+    built from fields carries exactly the fields' rho = 1, u and theta."""
+    e19, _, e7, w7 = O.velocities()
+    rng = np.random.default_rng(6)
+    for _ in range(20):
+        th = rng.standard_normal()
+        v = 0.05 * rng.standard_normal(3)
+        assert np.abs(O.geq(th, v) - w7 * th * (1 + 4 * (e7 @ v))).max() < 1e-16
+    ux, uy, uz = (0.03 * rng.standard_normal(27) for _ in range(3))
+    th = rng.standard_normal(27)
+    f, g = O.equilibrium_state(ux, uy, uz, th)
+    assert np.abs(f.sum(0) - 1).max() < 1e-15
+    assert np.abs(e19.T @ f - np.stack([ux, uy, uz])).max() < 1e-16
+    assert np.abs(g.sum(0) - th).max() < 1e-15
+
+
+def test_resample_is_trilinear_interpolation():
+    """oracle.resample against scipy's order-1 spline interpolation
+    (map_coordinates) at the clamped node-centre positions; identity on the
+    same grid; linear fields reproduced wherever no clamping occurs."""
+    from scipy.ndimage import map_coordinates
+    rng = np.random.default_rng(7)
+    for n, m in [(5, 9), (8, 12), (9, 4), (6, 6), (2, 5)]:
+        a = rng.standard_normal((n, n, n))
+        p = np.clip((np.arange(m) + 0.5) * n / m - 0.5, 0, n - 1)
+        zz, yy, xx = np.meshgrid(p, p, p, indexing="ij")
+        want = map_coordinates(a, [zz, yy, xx], order=1, mode="nearest")
+        assert np.abs(O.resample(a, m) - want).max() < 1e-13, (n, m)
+    a = rng.standard_normal((7, 7, 7))
+    assert np.array_equal(O.resample(a, 7), a)
+    n, m = 6, 15
+    z, y, x = np.meshgrid(*(np.arange(n),) * 3, indexing="ij")
+    lin = 0.3 + 0.1 * x - 0.2 * y + 0.05 * z
+    p = (np.arange(m) + 0.5) * n / m - 0.5
+    inside = (p >= 0) & (p <= n - 1)
+    Z, Y, X = np.meshgrid(p, p, p, indexing="ij")
+    want = 0.3 + 0.1 * X - 0.2 * Y + 0.05 * Z
+    got = O.resample(lin, m)
+    sel = np.ix_(inside, inside, inside)
+    assert np.abs(got[sel] - want[sel]).max() < 1e-14
+
+
 def test_force_moments():
     """Eq. (15) (reading R3): the force adds no mass and exactly rho G of momentum."""
     e, _, _, _ = O.velocities()
