@@ -197,11 +197,12 @@ lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *de
  * steady state as the start of a finer one; the paper fixes no initial
  * state).  src's fields rho, u = j / rho, theta (Eqs. 20, 25, 30; the
  * half-force velocity under Guo's forcing) are formed on the device in
- * FP64, sampled trilinearly onto dst's nodes as in lbmx_init_fields, the
- * velocities multiplied by u_c(dst) / u_c(src) (Eq. 38: equal unless Ma
- * differs), and dst takes f = f^eq(1, u), g = g^eq(theta, u).  src is only
- * read.  Both cavities must live on the current device.  Allocates and
- * frees a 32 src_n^3-byte device buffer; synchronises both streams.
+ * FP64 and sampled trilinearly onto dst's nodes as in lbmx_init_fields;
+ * with s = u_c(dst) / u_c(src) (Eq. 38: 1 unless Ma differs) dst takes
+ * f = f^eq(rho', s u) of Eq. (17), rho' = 1 + s^2 (rho - 1) (the density
+ * variations are pressure, of order u_c^2), and g = g^eq(theta, s u).  src
+ * is only read.  Both cavities must live on the current device.  Allocates
+ * and frees a 40 src_n^3-byte device buffer; synchronises both streams.
  * Errors: EINVAL for a NULL, failed or identical handle or another device,
  * EDEVICE for a HIP failure. */
 lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src);

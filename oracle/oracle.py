@@ -134,17 +134,18 @@ def geq(theta, v):
     return out
 
 
-def equilibrium_state(ux, uy, uz, theta):
-    """Pre-collision state with f = f^eq(rho = 1, u) (Eq. 17) and
-    g = N^-1 n^eq(theta, u) (Eq. 33) at every node: the state a warm start
-    builds from velocity and temperature fields (the paper fixes no initial
-    state).  Fields of n^3 values, x fastest; returns (f 19 x n^3, g 7 x n^3)."""
+def equilibrium_state(ux, uy, uz, theta, rho=None):
+    """Pre-collision state with f = f^eq(rho, u) (Eq. 17; rho = 1 when not
+    given) and g = N^-1 n^eq(theta, u) (Eq. 33) at every node: the state a
+    warm start builds from fields (the paper fixes no initial state).
+    Fields of n^3 values, x fastest; returns (f 19 x n^3, g 7 x n^3)."""
     fs = [np.asarray(a, dtype=np.float64).reshape(-1) for a in (ux, uy, uz, theta)]
     cells = fs[0].size
+    r = np.ones(cells) if rho is None else np.asarray(rho, dtype=np.float64).reshape(-1)
     f, g = np.zeros((19, cells)), np.zeros((7, cells))
     for c in range(cells):
         v = np.array([fs[0][c], fs[1][c], fs[2][c]])
-        f[:, c] = feq(1.0, v)
+        f[:, c] = feq(r[c], v)
         g[:, c] = geq(fs[3][c], v)
     return f, g
 

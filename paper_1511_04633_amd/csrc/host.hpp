@@ -352,9 +352,9 @@ lbmx_status unstream_pops(const View &v, const double *f, const double *g)
 
 template <class St, class E>
 lbmx_status unstream_fields(const View &v, const E *u, const E *w2, const E *w, const E *th,
-                            int src_n, double vscale)
+                            int src_n, double vscale, const E *rho)
 {
-    return launch_unstream<St>(v, SourceFields<E>{u, w2, w, th, src_n, v.n, E(vscale)});
+    return launch_unstream<St>(v, SourceFields<E>{u, w2, w, th, src_n, v.n, E(vscale), rho});
 }
 
 // Device buffer released at scope exit (after the work using it completed:

@@ -412,9 +412,11 @@ struct SourcePops {            // full population arrays f[19][n^3], g[7][n^3]
     __device__ double g(int i, int c) const { return ga[(size_t)i * cells + c]; }
 };
 
-// Velocity / temperature fields sampled trilinearly from a node-centred
-// src_n^3 grid of element type E (FP32 fields from a caller or a network,
-// FP64 fields of another cavity): f = f^eq(1, u) (Eq. 17) and
+// Velocity / temperature (and optionally density) fields sampled
+// trilinearly from a node-centred src_n^3 grid of element type E (FP32
+// fields from a caller or a network, FP64 fields of another cavity):
+// f = f^eq(rho, u) (Eq. 17; rho = 1 without a density field, otherwise
+// 1 + (rho_src - 1) vscale^2) and
 // g = w_T theta (1 + 4 e.u), whose moments are n^eq of Eq. (33).  The
 // sampled velocities are multiplied by vscale (1 keeps them bitwise).
 template <class E>
@@ -422,6 +424,7 @@ struct SourceFields {
     const E *u, *v, *w, *th;
     int src_n, n;
     E vscale;
+    const E *rho;  // density field, or null for rho = 1
     __device__ E sample(const E *a, int x, int y, int z) const
     {
         const E s = E(src_n) / E(n);
@@ -462,7 +465,12 @@ struct SourceFields {
         const int e[3] = {ex19(i), ey19(i), ez19(i)};
         double eu = e[0] * vel[0] + e[1] * vel[1] + e[2] * vel[2];
         double uu = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
-        return w19(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        if (!rho)
+            return w19(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        // rho - 1 scales with u_c^2 (hydrostatic and dynamic pressure), as u with u_c
+        const int x = c % n, y = (c / n) % n, z = c / (n * n);
+        const double dr = (double(sample(rho, x, y, z)) - 1.0) * double(vscale) * double(vscale);
+        return w19(i) * (dr + (1.0 + dr) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
     }
     __device__ double g(int i, int c) const
     {

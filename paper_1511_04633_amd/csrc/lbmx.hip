@@ -481,7 +481,7 @@ lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *de
         return fail(LBMX_EINVAL, "src_n = %d outside [1, 4096]", src_n);
     h->cur = 0;
     s = LBMX_DISPATCH(h->p.storage, unstream_fields, view(h), dev_u, dev_v, dev_w, dev_theta, src_n,
-                      1.0);
+                      1.0, (const float *)nullptr);
     if (s != LBMX_OK)
         return s;
     HIP_TRY(hipStreamSynchronize(h->stream));
@@ -510,17 +510,18 @@ lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src)
     const int m = src->p.n;
     const size_t mc = (size_t)m * m * m;
     DevBuf buf;
-    HIP_TRY(hipMalloc(&buf.p, 4 * mc * sizeof(double)));
-    double *f4 = reinterpret_cast<double *>(buf.p);
-    s = LBMX_DISPATCH(src->p.storage, launch_macro, view(src), nullptr, f4, f4 + mc, f4 + 2 * mc,
-                      f4 + 3 * mc);
+    HIP_TRY(hipMalloc(&buf.p, 5 * mc * sizeof(double)));
+    double *f5 = reinterpret_cast<double *>(buf.p);
+    s = LBMX_DISPATCH(src->p.storage, launch_macro, view(src), f5 + 4 * mc, f5, f5 + mc,
+                      f5 + 2 * mc, f5 + 3 * mc);
     if (s != LBMX_OK)
         return s;
     HIP_TRY(hipStreamSynchronize(src->stream));
     dst->cur = 0;
-    s = LBMX_DISPATCH(dst->p.storage, unstream_fields, view(dst), (const double *)f4,
-                      (const double *)(f4 + mc), (const double *)(f4 + 2 * mc),
-                      (const double *)(f4 + 3 * mc), m, dst->d.u_c / src->d.u_c);
+    s = LBMX_DISPATCH(dst->p.storage, unstream_fields, view(dst), (const double *)f5,
+                      (const double *)(f5 + mc), (const double *)(f5 + 2 * mc),
+                      (const double *)(f5 + 3 * mc), m, dst->d.u_c / src->d.u_c,
+                      (const double *)(f5 + 4 * mc));
     if (s != LBMX_OK)
         return s;
     HIP_TRY(hipStreamSynchronize(dst->stream));

@@ -49,7 +49,29 @@ def sample_nodes(n, seed=7):
     return sorted(pts)
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16", "f16_i16"])
+# Stored mantissa bits of the flow and energy populations per storage format
+# (None: FP32 / FP64 storage; "fix": 16-bit fixed point in units of 2^-14).
+FLOW_BITS = {"f64": None, "f32": None, "f16": 10, "bf16": 7, "f16_f32": 10, "bf16_f32": 7,
+             "f16_i16": 10}
+ENERGY_BITS = {"f64": None, "f32": None, "f16": 10, "bf16": 7, "f16_f32": None,
+               "bf16_f32": None, "f16_i16": "fix"}
+
+
+def tolerance(bits, w, ref, fp_tol):
+    """Bound on |GPU - oracle| for one population after one step from the
+    same state.  FP32 / FP64 storage: fp_tol (a few ulps of arithmetic and
+    storage rounding).  16-bit floating point: one ulp of the stored value
+    ref / w - 1 (or ref / w), since the FP32 result may sit on the other side
+    of a rounding boundary from the FP64 one, plus FP32 arithmetic.  Fixed
+    point with stochastic rounding: one spacing 2^-14 of g / w_T."""
+    if bits is None:
+        return fp_tol
+    if bits == "fix":
+        return w * 2.0 ** -14 + 1e-8
+    return w * (2.0 ** -bits * np.abs(ref) + 2.0 ** -24) + 1e-8
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16", "f16_i16", "bf16", "f16_f32", "bf16_f32", "f64"])
 def test_sampled_step_at_256cube(storage):
     print(f"case: full size 256^3 T1 Ra1e6 {storage}, sampled one-step parity", flush=True)
     cav = L.Cavity(n=N, wall_type=1, ra=1e6, storage=storage,
@@ -63,6 +85,10 @@ def test_sampled_step_at_256cube(storage):
     cav.close()
     assert np.abs(f1 - W19[:, None]).max() > 1e-4  # the flow has developed
 
+    # FP32: offsets f - w (|f - w| < 1e-2: ulp < 1e-9) and g (up to
+    # w_T theta_h = 1/16: ulp 7.5e-9), a few ulps (observed 5e-11 and 1.0e-8);
+    # FP64: a few ulps of values below 1
+    fp_f, fp_g = (1e-14, 1e-14) if storage == "f64" else (2e-8, 4e-8)
     ora = O.Oracle(N, 1, ra=1e6, state=False)
     worst_f = worst_g = 0.0
     for (x, y, z) in sample_nodes(N):
@@ -70,22 +96,8 @@ def test_sampled_step_at_256cube(storage):
         fo, go = ora.step_node(f0, g0, x, y, z)
         df = np.abs(f1[:, c] - fo)
         dg = np.abs(g1[:, c] - go)
-        if storage == "f32":
-            # FP32 offsets f - w (|f - w| < 1e-2: ulp < 1e-9) and g (up to
-            # w_T theta_h = 1/16: ulp 7.5e-9): a few ulps of arithmetic and
-            # storage rounding (observed 5e-11 and 1.0e-8)
-            tol_f, tol_g = 2e-8, 4e-8
-        else:
-            # one FP16 ulp of the stored (f - w)/w and g/w_T: the FP32 result
-            # may sit on the other side of a rounding boundary from the FP64
-            # one (observed: half an ulp of g)
-            vf, vg = np.abs(fo / W19 - 1), np.abs(go / W7)
-            tol_f = W19 * (2.0 ** -10 * vf + 2.0 ** -24) + 1e-8
-            tol_g = W7 * (2.0 ** -10 * vg + 2.0 ** -24) + 1e-8
-            if storage == "f16_i16":
-                # stochastic rounding to the fixed-point grid: within one
-                # spacing 2^-14 of g/w_T
-                tol_g = W7 * 2.0 ** -14 + 1e-8
+        tol_f = tolerance(FLOW_BITS[storage], W19, fo / W19 - 1, fp_f)
+        tol_g = tolerance(ENERGY_BITS[storage], W7, go / W7, fp_g)
         assert np.all(df <= tol_f), ((x, y, z), df.max())
         assert np.all(dg <= tol_g), ((x, y, z), dg.max())
         worst_f, worst_g = max(worst_f, df.max()), max(worst_g, dg.max())

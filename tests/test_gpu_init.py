@@ -71,7 +71,7 @@ def test_init_fields_is_the_equilibrium_of_the_sampled_fields(storage, m, n):
 def test_init_from_cavity(storage, m, n, ma):
     """A developed source cavity (20 steps from random fields, FP64 storage)
     initialises a cavity of another size, and with another Ma (velocities
-    scaled by u_c(dst) / u_c(src), Eq. 38)."""
+    scaled by s = u_c(dst) / u_c(src), Eq. 38, density variations by s^2)."""
     print(f"case: init_from_cavity {m}^3 -> {n}^3 Ma {ma} {storage}", flush=True)
     fld = inputs.random_fields(m, SEED + 7 * m)
     src = L.Cavity(n=m, wall_type=2, ra=1e3, storage="f64")
@@ -96,8 +96,9 @@ def test_init_from_cavity(storage, m, n, ma):
     ora.step(20)
     rho, ux, uy, uz, th = ora.macro()
     scale = O.derive(n, 1e3, ma=ma)["u_c"] / O.derive(m, 1e3)["u_c"]
-    r = [O.resample(a, n) for a in (ux, uy, uz, th)]
-    fe, ge = O.equilibrium_state(r[0] * scale, r[1] * scale, r[2] * scale, r[3])
+    r = [O.resample(a, n) for a in (ux, uy, uz, th, rho)]
+    fe, ge = O.equilibrium_state(r[0] * scale, r[1] * scale, r[2] * scale, r[3],
+                                 rho=1 + scale ** 2 * (r[4] - 1))
     # FP64: 20 steps of GPU-vs-oracle rounding; FP32: storage rounding
     tol = 1e-12 if storage == "f64" else 1e-8
     assert np.abs(f - fe).max() <= tol, np.abs(f - fe).max()
@@ -114,8 +115,7 @@ def test_init_from_cavity_across_storage_formats():
     dst = L.Cavity(n=n, wall_type=1, ra=1e5, storage="f32")
     dst.init_from(src)
     a, b = src.read_macro(), dst.read_macro()
-    assert np.abs(b[0] - 1).max() < 1e-6                          # rho = 1
-    for k in (1, 2, 3, 4):                                          # u, v, w, theta
+    for k in (0, 1, 2, 3, 4):                                       # rho, u, v, w, theta
         assert np.abs(a[k] - b[k]).max() <= 1e-6 * max(1.0, np.abs(a[k]).max()), k
     src.close()
     dst.close()

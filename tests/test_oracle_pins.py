@@ -173,7 +173,8 @@ def test_thermal_equilibrium_moments():
 def test_oracle_thermal_equilibrium_closed_form():
     """The oracle's N^-1 n^eq (Eq. 33, inverse by elimination) is the
     velocity-space form w_T,i theta (1 + 4 e_i . V), and the warm-start state
-    built from fields carries exactly the fields' rho = 1, u and theta."""
+    built from fields carries exactly the fields' rho (1 by default), u and
+    theta."""
     e19, _, e7, w7 = O.velocities()
     rng = np.random.default_rng(6)
     for _ in range(20):
@@ -186,6 +187,10 @@ def test_oracle_thermal_equilibrium_closed_form():
     assert np.abs(f.sum(0) - 1).max() < 1e-15
     assert np.abs(e19.T @ f - np.stack([ux, uy, uz])).max() < 1e-16
     assert np.abs(g.sum(0) - th).max() < 1e-15
+    rho = 1 + 0.01 * rng.standard_normal(27)
+    f, _ = O.equilibrium_state(ux, uy, uz, th, rho=rho)
+    assert np.abs(f.sum(0) - rho).max() < 1e-15
+    assert np.abs(e19.T @ f - rho * np.stack([ux, uy, uz])).max() < 1e-16
 
 
 def test_resample_is_trilinear_interpolation():
