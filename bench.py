@@ -167,7 +167,8 @@ def main():
     ap.add_argument("--no-warm-start", action="store_true",
                     help="time the steady runs from rest only (no U-Net warm start)")
     ap.add_argument("--coarse", type=int, default=64,
-                    help="grid-sequenced steady runs from a coarse^3 steady cavity (0 = skip)")
+                    help="grid-sequenced steady runs from a coarse^3 steady cavity (0 = skip; "
+                         "one halving of the 128^3 grid by default)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the storage-format sweep at the benchmark size")
     ap.add_argument("--force-model", type=int, default=0, choices=[0, 1, 2],

@@ -60,26 +60,42 @@ __device__ __forceinline__ long long nvox_of(const Dims &d)
 // channel tiles of 16 (blockIdx.y selects the group).  Per round of 16 input
 // channels it stages in LDS, channel-last:
 //   xs: the brick's input plus a one-voxel halo (18 x 6 x 6 voxels), so the
-//       MFMA operand "4 consecutive input channels of the voxel at this tap"
-//       is one aligned 8-byte read for any tap;
-//   ws: the weights of the block's output channels for all 27 taps.
-// Both are padded to 20 elements (10 words) per row, which puts the 16 rows
-// read by one quarter-wavefront on distinct LDS banks.  Wave w computes the
-// brick's rows 4w .. 4w+3 (16 voxels each): every weight operand serves 4
-// rows and every input operand the NCO channel tiles.  Each lane ends with 4
-// consecutive output channels of one voxel and stores them together.
+//       MFMA operand "8 consecutive input channels of the voxel at this tap"
+//       is one aligned 16-byte read for any tap;
+//   ws: the weights of the block's output channels for all 27 taps, plus a
+//       28th tap of zeros.
+// Rows are padded to 24 elements (48 bytes), which puts the 8 rows read by
+// each 8-lane phase of a 16-byte LDS read on distinct banks.  The products
+// run on v_mfma_f32_16x16x32_bf16 (gfx950; lane layout checked on the
+// device): its K = 32 covers two taps of the round's 16 channels (lanes 0-31
+// tap 2p, lanes 32-63 tap 2p + 1, p < 14; the 28th tap's input operand is
+// zeroed too, so non-finite inputs cannot leak into it).  Wave w computes
+// the brick's rows 4w .. 4w+3 (16 voxels each): every weight operand serves
+// 4 rows and every input operand the NCO channel tiles.  Each lane ends with
+// 4 consecutive output channels of one voxel and stores them together.
+// A round's global loads are all issued before any is written to LDS (a
+// fixed count per thread, held in registers), and the next round's are
+// issued before this round's MFMAs, so their latency overlaps the taps.
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
 constexpr int FC_X = 16, FC_Y = 4, FC_Z = 4;        // brick
 constexpr int FC_HX = FC_X + 2, FC_HY = FC_Y + 2, FC_HZ = FC_Z + 2;
 constexpr int FC_HVOX = FC_HX * FC_HY * FC_HZ;      // 648 halo voxels
-constexpr int FC_ROW = 20;                          // LDS elements per 16-channel row
+constexpr int FC_ROW = 24;                          // LDS elements per 16-channel row
+constexpr int FC_THREADS = 256;                     // block size (the launcher's)
+constexpr int FC_XITEMS = FC_HVOX * 2;              // 16-byte pieces of the input tile
+constexpr int FC_XITERS = (FC_XITEMS + FC_THREADS - 1) / FC_THREADS;
 
 template <int NCO>
-__global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, const bf *__restrict__ w,
-                                                  const float *__restrict__ bias, void *__restrict__ out,
-                                                  int out_f32, Dims d, int nbx, int nby, int nbz)
+__global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ in,
+                                                         const bf *__restrict__ w,
+                                                         const float *__restrict__ bias,
+                                                         void *__restrict__ out, int out_f32, Dims d,
+                                                         int nbx, int nby, int nbz)
 {
+    constexpr int WITEMS = 27 * NCO * 16 * 2;       // 16-byte pieces of the weight tile
+    constexpr int WITERS = (WITEMS + FC_THREADS - 1) / FC_THREADS;
     __shared__ __attribute__((aligned(16))) bf xs[FC_HVOX * FC_ROW];
-    __shared__ __attribute__((aligned(16))) bf ws[27 * NCO * 16 * FC_ROW];
+    __shared__ __attribute__((aligned(16))) bf ws[28 * NCO * 16 * FC_ROW];
     const int Ci = d.Ci, Co = d.Co;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
@@ -91,6 +107,57 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, con
     const int x0 = bx * FC_X, y0 = by * FC_Y, z0 = bz * FC_Z;
     const int co0 = blockIdx.y * NCO * 16;
 
+    uint4 xv[FC_XITERS], wt[WITERS];
+    auto load_round = [&](int c0) {
+#pragma unroll
+        for (int k = 0; k < FC_XITERS; ++k) {
+            const int i = threadIdx.x + k * FC_THREADS;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (i < FC_XITEMS) {
+                const int hv = i >> 1, part = i & 1;
+                const int hx = hv % FC_HX, hrow = hv / FC_HX;
+                const int hy = hrow % FC_HY, hz = hrow / FC_HY;
+                const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+                if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
+                    const int q = ((b * d.D + z) * d.H + y) * d.W + x;
+                    v = *reinterpret_cast<const uint4 *>(in + size_t(q) * Ci + c0 + part * 8);
+                }
+            }
+            xv[k] = v;
+        }
+#pragma unroll
+        for (int k = 0; k < WITERS; ++k) {  // [tap][co][2 x 8 ch]
+            const int i = threadIdx.x + k * FC_THREADS;
+            uint4 v = make_uint4(0, 0, 0, 0);
+            if (i < WITEMS) {
+                const int row = i >> 1, part = i & 1;
+                const int tap = row / (NCO * 16), co = row % (NCO * 16);
+                v = *reinterpret_cast<const uint4 *>(w + (size_t(co0 + co) * 27 + tap) * Ci + c0 + part * 8);
+            }
+            wt[k] = v;
+        }
+    };
+    auto store_round = [&]() {
+#pragma unroll
+        for (int k = 0; k < FC_XITERS; ++k) {
+            const int i = threadIdx.x + k * FC_THREADS;
+            if (i < FC_XITEMS) {
+                uint2 *dst = reinterpret_cast<uint2 *>(xs + (i >> 1) * FC_ROW + (i & 1) * 8);
+                dst[0] = make_uint2(xv[k].x, xv[k].y);
+                dst[1] = make_uint2(xv[k].z, xv[k].w);
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < WITERS; ++k) {
+            const int i = threadIdx.x + k * FC_THREADS;
+            if (i < WITEMS) {
+                uint2 *dst = reinterpret_cast<uint2 *>(ws + (i >> 1) * FC_ROW + (i & 1) * 8);
+                dst[0] = make_uint2(wt[k].x, wt[k].y);
+                dst[1] = make_uint2(wt[k].z, wt[k].w);
+            }
+        }
+    };
+
     f4 acc[4][NCO];
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr)
@@ -98,49 +165,47 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, con
         for (int j = 0; j < NCO; ++j)
             acc[rr][j] = f4{0.f, 0.f, 0.f, 0.f};
 
+    for (int i = threadIdx.x; i < NCO * 16 * FC_ROW / 8; i += FC_THREADS)
+        reinterpret_cast<uint4 *>(ws + 27 * NCO * 16 * FC_ROW)[i] = make_uint4(0, 0, 0, 0);
+    load_round(0);
     for (int c0 = 0; c0 < Ci; c0 += 16) {
+        __syncthreads();  // the previous round's operands are no longer read
+        store_round();
         __syncthreads();
-        for (int i = threadIdx.x; i < FC_HVOX * 2; i += blockDim.x) {  // 2 x 8 bytes per voxel
-            const int hv = i >> 1, part = i & 1;
-            const int hx = hv % FC_HX, hrow = hv / FC_HX;
-            const int hy = hrow % FC_HY, hz = hrow / FC_HY;
-            const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
-                const int q = ((b * d.D + z) * d.H + y) * d.W + x;
-                v = *reinterpret_cast<const uint4 *>(in + size_t(q) * Ci + c0 + part * 8);
-            }
-            uint2 *dst = reinterpret_cast<uint2 *>(xs + hv * FC_ROW + part * 8);
-            dst[0] = make_uint2(v.x, v.y);
-            dst[1] = make_uint2(v.z, v.w);
-        }
-        for (int i = threadIdx.x; i < 27 * NCO * 16 * 2; i += blockDim.x) {  // [tap][co][2 x 8 ch]
-            const int row = i >> 1, part = i & 1;
-            const int tap = row / (NCO * 16), co = row % (NCO * 16);
-            const uint4 v = *reinterpret_cast<const uint4 *>(
-                w + (size_t(co0 + co) * 27 + tap) * Ci + c0 + part * 8);
-            uint2 *dst = reinterpret_cast<uint2 *>(ws + row * FC_ROW + part * 8);
-            dst[0] = make_uint2(v.x, v.y);
-            dst[1] = make_uint2(v.z, v.w);
-        }
-        __syncthreads();
-#pragma unroll 3
-        for (int tap = 0; tap < 27; ++tap) {
-            const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-            s4 a[NCO];
+        if (c0 + 16 < Ci)
+            load_round(c0 + 16);
+#pragma unroll 2
+        for (int pr = 0; pr < 14; ++pr) {
+            // K = 32: lanes kq = 0, 1 carry tap 2 pr, lanes 2, 3 tap 2 pr + 1
+            // (tap 27 has zero weights and a zero input operand)
+            const int t = 2 * pr + (kq >> 1);
+            const int tt = t < 27 ? t : 26;
+            const int dx = tt % 3 - 1, dy = (tt / 3) % 3 - 1, dz = tt / 9 - 1;
+            const int ch = 8 * (kq & 1);
+            bf8v a[NCO];
 #pragma unroll
             for (int j = 0; j < NCO; ++j)
-                a[j] = *reinterpret_cast<const s4 *>(ws + ((tap * NCO + j) * 16 + col) * FC_ROW + kq * 4);
+                a[j] = *reinterpret_cast<const bf8v *>(ws + ((t * NCO + j) * 16 + col) * FC_ROW + ch);
 #pragma unroll
             for (int rr = 0; rr < 4; ++rr) {
                 const int g = wv * 4 + rr, gy = g % FC_Y, gz = g / FC_Y;
                 const int hv = ((gz + 1 + dz) * FC_HY + (gy + 1 + dy)) * FC_HX + (col + 1 + dx);
-                const s4 bv = *reinterpret_cast<const s4 *>(xs + hv * FC_ROW + kq * 4);
+                bf8v bv = *reinterpret_cast<const bf8v *>(xs + hv * FC_ROW + ch);
+                if (t == 27)
+                    bv = bf8v{};
 #pragma unroll
                 for (int j = 0; j < NCO; ++j)
-                    acc[rr][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[j], bv, acc[rr][j], 0, 0, 0);
+                    acc[rr][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[j], bv, acc[rr][j], 0, 0, 0);
             }
         }
+    }
+    f4 bj[NCO];
+#pragma unroll
+    for (int j = 0; j < NCO; ++j) {
+        const int cb = co0 + j * 16 + kq * 4;
+        bj[j] = f4{0.f, 0.f, 0.f, 0.f};
+        if (bias)
+            bj[j] = f4{bias[cb], bias[cb + 1], bias[cb + 2], bias[cb + 3]};
     }
 #pragma unroll
     for (int rr = 0; rr < 4; ++rr) {
@@ -153,12 +218,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const bf *__restrict__ in, con
         for (int j = 0; j < NCO; ++j) {
             const int cb = co0 + j * 16 + kq * 4;  // 4 consecutive output channels
             f4 v = acc[rr][j];
-            if (bias) {
-                v[0] += bias[cb];
-                v[1] += bias[cb + 1];
-                v[2] += bias[cb + 2];
-                v[3] += bias[cb + 3];
-            }
+            if (bias)
+                v += bj[j];
             if (out_f32) {
                 *reinterpret_cast<f4 *>(reinterpret_cast<float *>(out) + p * Co + cb) = v;
             } else {
@@ -621,8 +682,8 @@ void launch_fwd(const bf *in, const bf *w, const float *bias, void *out, int out
     const int nbx = (d.W + FC_X - 1) / FC_X, nby = (d.H + FC_Y - 1) / FC_Y, nbz = (d.D + FC_Z - 1) / FC_Z;
     const unsigned bricks = unsigned(d.B * nbx * nby * nbz);
     const unsigned groups = unsigned(d.Co / 16 / NCO);
-    hipLaunchKernelGGL(k_conv_fwd<NCO>, dim3(bricks, groups), dim3(256), 0, s, in, w, bias, out, out_f32, d,
-                       nbx, nby, nbz);
+    hipLaunchKernelGGL(k_conv_fwd<NCO>, dim3(bricks, groups), dim3(FC_THREADS), 0, s, in, w, bias, out,
+                       out_f32, d, nbx, nby, nbz);
 }
 
 }  // namespace
