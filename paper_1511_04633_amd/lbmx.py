@@ -85,6 +85,10 @@ def load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"HIP library not built: {LIB_PATH} is missing "
                           "(run python -m paper_1511_04633_amd.build)")
+    # PyTorch supplies the device memory and streams, so its HIP runtime must be
+    # the one the library binds to: load it first (its libamdhip64 has the
+    # library's soname), or the process would hold two runtimes.
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER(lbmx_params)
     i32, i64 = ctypes.c_int32, ctypes.c_int64
