@@ -291,6 +291,13 @@ lbmx_status lbmx_batch_info(const lbmx_batch *b, int32_t k, int32_t *state, int6
 /* Nu (Eqs. 39-41) of cavity k now (synchronises). */
 lbmx_status lbmx_batch_nusselt(lbmx_batch *b, int32_t k, lbmx_nu *out);
 
+/* Cavity k starts at t = 0 from the current state of cavity ks of batch src
+ * (src may be b itself, with ks != k), as lbmx_init_from_cavity does for
+ * single cavities (grid sequencing: a batch of half-size cavities run to
+ * steady starts the full-size batch); a retired cavity becomes active again.
+ * Synchronises both batches' streams.  Errors as lbmx_init_from_cavity. */
+lbmx_status lbmx_batch_init_from(lbmx_batch *b, int32_t k, lbmx_batch *src, int32_t ks);
+
 /* Macroscopic fields of cavity k, as lbmx_read_macro. */
 lbmx_status lbmx_batch_read_macro(lbmx_batch *b, int32_t k, double *rho, double *ux, double *uy,
                                   double *uz, double *theta);

@@ -569,6 +569,39 @@ lbmx_status lbmx_batch_nusselt(lbmx_batch *b, int32_t k, lbmx_nu *out)
     return LBMX_OK;
 }
 
+lbmx_status lbmx_batch_init_from(lbmx_batch *b, int32_t k, lbmx_batch *src, int32_t ks)
+{
+    lbmx_status s = check(b, k);
+    if (s != LBMX_OK)
+        return s;
+    s = check(src, ks);
+    if (s != LBMX_OK)
+        return s;
+    if (src == b && ks == k)
+        return fail(LBMX_EINVAL, "source and destination are the same cavity");
+    hipPointerAttribute_t as, ad;
+    HIP_TRY(hipPointerGetAttributes(&as, src->ws));
+    HIP_TRY(hipPointerGetAttributes(&ad, b->ws));
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (as.device != ad.device || ad.device != dev)
+        return fail(LBMX_EINVAL, "batches on devices %d and %d, current device %d", as.device,
+                    ad.device, dev);
+    // as lbmx_batch_init_rest: the cavity rejoins the lockstep at the batch's parity
+    b->cur[k] = b->parity;
+    s = init_from_state(view_of(b, k), b->storage, view_of(src, ks), src->storage,
+                        b->d[k].u_c / src->d[ks].u_c);
+    if (s != LBMX_OK)
+        return s;
+    b->t[k] = 0;
+    b->last[k] = lbmx_nu{};
+    if (b->state[k] != ST_ACTIVE) {
+        b->state[k] = ST_ACTIVE;
+        return build_tiles(b);
+    }
+    return LBMX_OK;
+}
+
 lbmx_status lbmx_batch_read_macro(lbmx_batch *b, int32_t k, double *rho, double *ux, double *uy,
                                   double *uz, double *theta)
 {

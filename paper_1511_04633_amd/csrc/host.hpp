@@ -386,5 +386,32 @@ struct DevBuf {
         }                                                                                      \
     }())
 
+// dst's state at t = 0 from src's current state: src's rho, u = j / rho,
+// theta (Eqs. 20, 25, 30) formed in FP64 on the device, resampled
+// trilinearly onto dst's nodes (SourceFields<double>), velocities scaled by
+// vscale and rho - 1 by vscale^2; f = f^eq(rho, u), g = g^eq(theta, u).
+// Synchronises both streams; the temporary buffer holds 5 src.n^3 doubles.
+inline lbmx_status init_from_state(const View &dst, int32_t dst_storage, const View &src,
+                                   int32_t src_storage, double vscale)
+{
+    const size_t mc = (size_t)src.n * src.n * src.n;
+    DevBuf buf;
+    HIP_TRY(hipMalloc(&buf.p, 5 * mc * sizeof(double)));
+    double *f5 = reinterpret_cast<double *>(buf.p);
+    lbmx_status s = LBMX_DISPATCH(src_storage, launch_macro, src, f5 + 4 * mc, f5, f5 + mc,
+                                  f5 + 2 * mc, f5 + 3 * mc);
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(src.stream));
+    s = LBMX_DISPATCH(dst_storage, unstream_fields, dst, (const double *)f5,
+                      (const double *)(f5 + mc), (const double *)(f5 + 2 * mc),
+                      (const double *)(f5 + 3 * mc), src.n, vscale,
+                      (const double *)(f5 + 4 * mc));
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(dst.stream));
+    return LBMX_OK;
+}
+
 }  // namespace host
 }  // namespace lbmx

@@ -507,24 +507,11 @@ lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src)
     if (as.device != ad.device || ad.device != dev)
         return fail(LBMX_EINVAL, "cavities on devices %d and %d, current device %d", as.device,
                     ad.device, dev);
-    const int m = src->p.n;
-    const size_t mc = (size_t)m * m * m;
-    DevBuf buf;
-    HIP_TRY(hipMalloc(&buf.p, 5 * mc * sizeof(double)));
-    double *f5 = reinterpret_cast<double *>(buf.p);
-    s = LBMX_DISPATCH(src->p.storage, launch_macro, view(src), f5 + 4 * mc, f5, f5 + mc,
-                      f5 + 2 * mc, f5 + 3 * mc);
-    if (s != LBMX_OK)
-        return s;
-    HIP_TRY(hipStreamSynchronize(src->stream));
     dst->cur = 0;
-    s = LBMX_DISPATCH(dst->p.storage, unstream_fields, view(dst), (const double *)f5,
-                      (const double *)(f5 + mc), (const double *)(f5 + 2 * mc),
-                      (const double *)(f5 + 3 * mc), m, dst->d.u_c / src->d.u_c,
-                      (const double *)(f5 + 4 * mc));
+    s = init_from_state(view(dst), dst->p.storage, view(src), src->p.storage,
+                        dst->d.u_c / src->d.u_c);
     if (s != LBMX_OK)
         return s;
-    HIP_TRY(hipStreamSynchronize(dst->stream));
     dst->t = 0;
     return LBMX_OK;
 }

@@ -9,9 +9,10 @@ library's batched launch until every cavity's hot-wall Nu is steady
 the library and stored with (log10 Ra, wall type) as the surrogate's
 training set.
 
-CLI: python -m paper_1511_04633_amd.dataset --out set.npz [--count 64]
+CLI: python -m paper_1511_04633_amd.dataset --out set.npz [--count 64] [--coarse]
 prints one JSON summary line (batch wall time, aggregate MLUPS, autotuned
-launch, and optionally the sequential per-cavity baseline).
+launch, and optionally the sequential per-cavity baseline); --coarse starts
+every cavity from a half-size batch run to steady first (grid sequencing).
 """
 from __future__ import annotations
 
@@ -42,13 +43,33 @@ def make_batch(cases, storage="f32", tune_cache=None, log=None):
 
 
 def generate(seed=1511, count=64, out_n=64, storage="f32", tol=1e-6, every=1000,
-             max_steps=300_000, tune_cache=None, log=None):
-    """Run the batch to steady and return the training set and timings."""
+             max_steps=300_000, tune_cache=None, log=None, coarse=False):
+    """Run the batch to steady and return the training set and timings.
+    With coarse, grid sequencing: a batch of the same cases at half the edge
+    length is run to steady first (same criterion) and each cavity starts
+    from its half-size twin's fields (``Batch.init_from``); the wall time
+    covers both solves and the transfer."""
     import torch
 
     cases = inputs.batch_cases(seed, count)
     b, us = make_batch(cases, storage, tune_cache, log)
+    cinfo = None
+    if coarse:
+        ccases = [dict(c, n=c["n"] // 2) for c in cases]
+        cb, _ = make_batch(ccases, storage, tune_cache, log)
     t0 = time.perf_counter()
+    if coarse:
+        cconv = cb.run_to_steady(tol=tol, every=every, max_steps=max_steps)
+        csteps = [cb.info(k)["t"] for k in range(count)]
+        for k in range(count):
+            b.init_from(k, cb, k)
+        cb.close()
+        torch.cuda.synchronize()
+        cinfo = {"converged": cconv, "wall_s": time.perf_counter() - t0,
+                 "node_steps": sum(c["n"] ** 3 * t for c, t in zip(ccases, csteps)),
+                 "max_steps": max(csteps)}
+        if log:
+            log(f"coarse batch: {cconv}/{count} converged in {cinfo['wall_s']:.1f} s")
     nconv = b.run_to_steady(tol=tol, every=every, max_steps=max_steps)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -71,7 +92,8 @@ def generate(seed=1511, count=64, out_n=64, storage="f32", tol=1e-6, every=1000,
         "summary": {"count": count, "converged": nconv, "wall_s": wall,
                     "node_steps": node_steps, "mlups": node_steps / wall / 1e6,
                     "launch": list(b.get_launch()), "autotune_us_per_step": us,
-                    "storage": storage, "tol": tol, "every": every, "max_steps": max_steps},
+                    "storage": storage, "tol": tol, "every": every, "max_steps": max_steps,
+                    "coarse": cinfo},
     }
     b.close()
     return out
@@ -115,10 +137,12 @@ def main(argv=None):
     ap.add_argument("--tune-cache", default=None)
     ap.add_argument("--sequential", action="store_true",
                     help="also time the same cavities run one by one")
+    ap.add_argument("--coarse", action="store_true",
+                    help="grid sequencing: start from a half-size batch run to steady")
     a = ap.parse_args(argv)
     log = lambda m: print(m, file=sys.stderr, flush=True)
     ds = generate(seed=a.seed, count=a.count, out_n=a.out_n, max_steps=a.max_steps,
-                  tune_cache=a.tune_cache, log=log)
+                  tune_cache=a.tune_cache, log=log, coarse=a.coarse)
     if a.out:
         save(a.out, ds)
     summ = dict(ds["summary"])

@@ -30,7 +30,8 @@ SYMBOLS = [
     "lbmx_step", "lbmx_step_timed", "lbmx_time",
     "lbmx_read_macro", "lbmx_nusselt", "lbmx_run_to_steady", "lbmx_set_launch",
     "lbmx_get_launch", "lbmx_strerror", "lbmx_last_error",
-    "lbmx_batch_create", "lbmx_batch_destroy", "lbmx_batch_init_rest", "lbmx_batch_step",
+    "lbmx_batch_create", "lbmx_batch_destroy", "lbmx_batch_init_rest", "lbmx_batch_init_from",
+    "lbmx_batch_step",
     "lbmx_batch_run_to_steady", "lbmx_batch_info", "lbmx_batch_nusselt",
     "lbmx_batch_read_macro", "lbmx_batch_resample", "lbmx_batch_set_launch",
     "lbmx_batch_get_launch", "lbmx_batch_autotune",
@@ -115,6 +116,7 @@ def load() -> ctypes.CDLL:
         "lbmx_get_launch": [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
         "lbmx_batch_create": [P, i32, _vp, ctypes.POINTER(_vp)],
         "lbmx_batch_init_rest": [_vp, i32, _dp],
+        "lbmx_batch_init_from": [_vp, i32, _vp, i32],
         "lbmx_batch_step": [_vp, i64],
         "lbmx_batch_run_to_steady": [_vp, ctypes.c_double, i64, i64, ctypes.POINTER(i32)],
         "lbmx_batch_info": [_vp, i32, ctypes.POINTER(i32), ctypes.POINTER(i64),
@@ -374,6 +376,12 @@ class Batch:
         if th is not None and th.size != self.n[k] ** 3:
             raise ValueError("theta0 needs n^3 values")
         _check(load().lbmx_batch_init_rest(self._h, int(k), _dptr(th)))
+        return self
+
+    def init_from(self, k, src: "Batch", ks):
+        """Cavity k at t = 0 from cavity ks of batch `src` (resampled on the
+        device, ``lbmx_batch_init_from``)."""
+        _check(load().lbmx_batch_init_from(self._h, int(k), src._h, int(ks)))
         return self
 
     def step(self, nsteps=1):

@@ -136,3 +136,69 @@ def test_grid_sequencing_reaches_the_same_steady_state_sooner(wall_type):
     assert rest["converged"] and seq["converged"] and seq["coarse"]["converged"]
     assert abs(seq["nu3d"] - rest["nu3d"]) <= 1e-3 * rest["nu3d"]
     assert seq["steps"] < 0.7 * rest["steps"] and seq["seconds"] < rest["seconds"]
+
+
+def test_batch_init_from_matches_single_cavities():
+    """lbmx_batch_init_from gives bit for bit the state lbmx_init_from_cavity
+    gives for the same cavities run alone, and the batch steps on in lockstep
+    from it."""
+    print("case: batch init_from vs single init_from_cavity", flush=True)
+    src_cases = [dict(n=8, wall_type=2, ra=1e4), dict(n=6, wall_type=3, ra=3e4)]
+    dst_cases = [dict(n=12, wall_type=2, ra=1e4), dict(n=11, wall_type=3, ra=3e4)]
+    sb, db = L.Batch(src_cases, storage="f32"), L.Batch(dst_cases, storage="f32")
+    for k, c in enumerate(src_cases):
+        sb.init_rest(k, inputs.theta_noise(c["n"], SEED + k))
+    sb.step(50)
+    db.step(3)  # the destination's parity and time are reset by init_from
+    for k in range(2):
+        db.init_from(k, sb, k)
+    singles = []
+    for k, (sc, dc) in enumerate(zip(src_cases, dst_cases)):
+        s = L.Cavity(storage="f32", theta0=inputs.theta_noise(sc["n"], SEED + k), **sc)
+        s.step(50)
+        d = L.Cavity(storage="f32", **dc)
+        d.init_from(s)
+        s.close()
+        singles.append(d)
+    for rounds in (0, 20):
+        if rounds:
+            db.step(rounds)
+            for d in singles:
+                d.step(rounds)
+        for k, d in enumerate(singles):
+            for a, b_ in zip(db.read_macro(k), d.read_macro()):
+                assert np.array_equal(np.asarray(a).reshape(-1), np.asarray(b_).reshape(-1)), (k, rounds)
+    with pytest.raises(L.LbmxError):
+        db.init_from(0, db, 0)
+    for d in singles:
+        d.close()
+    sb.close()
+    db.close()
+
+
+def test_batch_grid_sequencing_reaches_the_same_steady_state():
+    """Two cavities (64^3 Type 1, 48^3 Type 3, Ra 1e5) run to steady by the
+    batch from rest, and from a half-size batch run to steady first: the same
+    steady Nu (within 1e-3) in fewer fine steps."""
+    print("case: batch grid sequencing 32/24 -> 64/48", flush=True)
+    cases = [dict(n=64, wall_type=1, ra=1e5), dict(n=48, wall_type=3, ra=1e5)]
+    rest = L.Batch(cases, storage="f32")
+    for k, c in enumerate(cases):
+        rest.init_rest(k, inputs.theta_noise(c["n"], SEED))
+    rest.run_to_steady(tol=1e-6, every=1000, max_steps=400_000)
+    coarse = L.Batch([dict(c, n=c["n"] // 2) for c in cases], storage="f32")
+    for k, c in enumerate(cases):
+        coarse.init_rest(k, inputs.theta_noise(c["n"] // 2, SEED))
+    coarse.run_to_steady(tol=1e-6, every=1000, max_steps=400_000)
+    fine = L.Batch(cases, storage="f32")
+    for k in range(len(cases)):
+        fine.init_from(k, coarse, k)
+    fine.run_to_steady(tol=1e-6, every=1000, max_steps=400_000)
+    for k in range(len(cases)):
+        r, f = rest.info(k), fine.info(k)
+        print(k, r, f, coarse.info(k))
+        assert r["state"] == "converged" and f["state"] == "converged"
+        assert abs(f["nu3d"] - r["nu3d"]) <= 1e-3 * r["nu3d"]
+        assert f["t"] < r["t"]
+    for b in (rest, coarse, fine):
+        b.close()
