@@ -579,14 +579,9 @@ lbmx_status lbmx_batch_init_from(lbmx_batch *b, int32_t k, lbmx_batch *src, int3
         return s;
     if (src == b && ks == k)
         return fail(LBMX_EINVAL, "source and destination are the same cavity");
-    hipPointerAttribute_t as, ad;
-    HIP_TRY(hipPointerGetAttributes(&as, src->ws));
-    HIP_TRY(hipPointerGetAttributes(&ad, b->ws));
-    int dev = -1;
-    HIP_TRY(hipGetDevice(&dev));
-    if (as.device != ad.device || ad.device != dev)
-        return fail(LBMX_EINVAL, "batches on devices %d and %d, current device %d", as.device,
-                    ad.device, dev);
+    s = check_same_device(src->ws, b->ws, "batches");
+    if (s != LBMX_OK)
+        return s;
     // as lbmx_batch_init_rest: the cavity rejoins the lockstep at the batch's parity
     b->cur[k] = b->parity;
     s = init_from_state(view_of(b, k), b->storage, view_of(src, ks), src->storage,

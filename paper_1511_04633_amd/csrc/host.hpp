@@ -386,6 +386,20 @@ struct DevBuf {
         }                                                                                      \
     }())
 
+// EINVAL unless both device buffers live on the current device.
+inline lbmx_status check_same_device(const void *a, const void *b, const char *what)
+{
+    hipPointerAttribute_t pa, pb;
+    HIP_TRY(hipPointerGetAttributes(&pa, a));
+    HIP_TRY(hipPointerGetAttributes(&pb, b));
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (pa.device != pb.device || pb.device != dev)
+        return fail(LBMX_EINVAL, "%s on devices %d and %d, current device %d", what, pa.device,
+                    pb.device, dev);
+    return LBMX_OK;
+}
+
 // dst's state at t = 0 from src's current state: src's rho, u = j / rho,
 // theta (Eqs. 20, 25, 30) formed in FP64 on the device, resampled
 // trilinearly onto dst's nodes (SourceFields<double>), velocities scaled by

@@ -499,14 +499,9 @@ lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src)
         return s;
     if (src == dst)
         return fail(LBMX_EINVAL, "source and destination are the same cavity");
-    hipPointerAttribute_t as, ad;
-    HIP_TRY(hipPointerGetAttributes(&as, src->ws));
-    HIP_TRY(hipPointerGetAttributes(&ad, dst->ws));
-    int dev = -1;
-    HIP_TRY(hipGetDevice(&dev));
-    if (as.device != ad.device || ad.device != dev)
-        return fail(LBMX_EINVAL, "cavities on devices %d and %d, current device %d", as.device,
-                    ad.device, dev);
+    s = check_same_device(src->ws, dst->ws, "cavities");
+    if (s != LBMX_OK)
+        return s;
     dst->cur = 0;
     s = init_from_state(view(dst), dst->p.storage, view(src), src->p.storage,
                         dst->d.u_c / src->d.u_c);
