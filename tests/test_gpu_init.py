@@ -67,19 +67,21 @@ def test_init_fields_is_the_equilibrium_of_the_sampled_fields(storage, m, n):
 
 
 @pytest.mark.parametrize("storage", ["f64", "f32"])
-@pytest.mark.parametrize("m,n,ma", [(8, 12, 0.1), (10, 7, 0.05)])
-def test_init_from_cavity(storage, m, n, ma):
+@pytest.mark.parametrize("m,n,ma,force_model", [(8, 12, 0.1, 0), (10, 7, 0.05, 0), (9, 13, 0.1, 2)])
+def test_init_from_cavity(storage, m, n, ma, force_model):
     """A developed source cavity (20 steps from random fields, FP64 storage)
     initialises a cavity of another size, and with another Ma (velocities
-    scaled by s = u_c(dst) / u_c(src), Eq. 38, density variations by s^2)."""
-    print(f"case: init_from_cavity {m}^3 -> {n}^3 Ma {ma} {storage}", flush=True)
+    scaled by s = u_c(dst) / u_c(src), Eq. 38, density variations by s^2).
+    Under Guo's forcing the transferred velocity is the half-force one."""
+    print(f"case: init_from_cavity {m}^3 -> {n}^3 Ma {ma} force {force_model} {storage}",
+          flush=True)
     fld = inputs.random_fields(m, SEED + 7 * m)
-    src = L.Cavity(n=m, wall_type=2, ra=1e3, storage="f64")
+    src = L.Cavity(n=m, wall_type=2, ra=1e3, storage="f64", force_model=force_model)
     d = dev(fld)
     src.init_fields(d[0], d[1], d[2], d[3])
     src.step(20)
     before = src.get_populations()
-    dst = L.Cavity(n=n, wall_type=2, ra=1e3, ma=ma, storage=storage)
+    dst = L.Cavity(n=n, wall_type=2, ra=1e3, ma=ma, storage=storage, force_model=force_model)
     dst.step(3)
     dst.init_from(src)
     assert dst.t == 0
@@ -91,7 +93,7 @@ def test_init_from_cavity(storage, m, n, ma):
     src.close()
     dst.close()
 
-    ora = O.Oracle(m, 2, ra=1e3)
+    ora = O.Oracle(m, 2, ra=1e3, force_model=force_model)
     ora.set_state(*O.equilibrium_state(*fld.astype(np.float64)))
     ora.step(20)
     rho, ux, uy, uz, th = ora.macro()
@@ -99,10 +101,13 @@ def test_init_from_cavity(storage, m, n, ma):
     r = [O.resample(a, n) for a in (ux, uy, uz, th, rho)]
     fe, ge = O.equilibrium_state(r[0] * scale, r[1] * scale, r[2] * scale, r[3],
                                  rho=1 + scale ** 2 * (r[4] - 1))
-    # FP64: 20 steps of GPU-vs-oracle rounding; FP32: storage rounding
-    tol = 1e-12 if storage == "f64" else 1e-8
-    assert np.abs(f - fe).max() <= tol, np.abs(f - fe).max()
-    assert np.abs(g - ge).max() <= tol, np.abs(g - ge).max()
+    # FP64: 20 steps of GPU-vs-oracle rounding.  FP32: storage rounding of the
+    # offsets f - w (|f - w| < 0.02, ulp < 2e-9) and of g; at wall-adjacent
+    # nodes the stored energy value is 2 w theta_W - g (|.| < 0.4, ulp 3e-8)
+    # and pulling it back rounds once more, so one ulp of 0.4.
+    tol_f, tol_g = (1e-12, 1e-12) if storage == "f64" else (1e-8, 3e-8)
+    assert np.abs(f - fe).max() <= tol_f, np.abs(f - fe).max()
+    assert np.abs(g - ge).max() <= tol_g, np.abs(g - ge).max()
 
 
 def test_init_from_cavity_across_storage_formats():
