@@ -74,6 +74,26 @@ def test_batch_bitwise_equals_single_cavity(storage):
             assert np.array_equal(gb[i], gs[i]), (k, i)
 
 
+def test_batch_fixed_point_energy_equals_single_cavity():
+    """FP16 flow + stochastically rounded fixed-point energy: the rounding
+    stream is keyed by node and launch count, which for a batch started at
+    step 0 and stepped by direct launches is the cavity's own step, so the
+    batch reproduces the lone cavities bit for bit.  (A captured graph
+    replays its launches' keys every graph_steps steps instead.)"""
+    print("case: batch vs single f16_i16, direct launches", flush=True)
+    b = make_batch(CASES, "f16_i16", graph_steps=0)
+    b.step(90)
+    for k, c in enumerate(CASES):
+        s = L.Cavity(n=c["n"], wall_type=c["wall_type"], ra=c["ra"], storage="f16_i16",
+                     theta0=theta0(k, c["n"]))
+        s.step(90)
+        gb, gs = b.read_macro(k), s.read_macro()
+        for i in range(5):
+            assert np.array_equal(gb[i], gs[i]), (k, i)
+        s.close()
+    b.close()
+
+
 def test_graph_and_launch_shapes_are_bitwise_identical():
     print("case: batch graph / launch shapes", flush=True)
     ref = None

@@ -21,7 +21,8 @@ def _setup():
     L.load()
 
 
-@pytest.mark.parametrize("storage,n,wall_type", [("f32", 24, 2), ("f16_f32", 20, 3), ("f64", 17, 1)])
+@pytest.mark.parametrize("storage,n,wall_type", [("f32", 24, 2), ("f16_f32", 20, 3), ("f64", 17, 1),
+                                                  ("f16_i16", 18, 1)])
 def test_resume_is_bitwise(tmp_path, storage, n, wall_type):
     print(f"case: checkpoint {storage} n={n} T{wall_type}", flush=True)
     th0 = inputs.theta_noise(n, SEED)
