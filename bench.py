@@ -265,6 +265,15 @@ def main():
         line["storage_sweep"] = storage_sweep(n, args.wall_type, args.ra)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wall_type=args.wall_type, ra=args.ra)
+        # the GPU on the oracle's sample, same size and precision class (FP64)
+        c64 = lbmx.Cavity(n=64, wall_type=args.wall_type, ra=args.ra, storage="f64",
+                          theta0=inputs.theta_noise(64, 20151115))
+        c64.step(200)
+        ms = c64.step_timed(2000)
+        line["gpu_on_cpu_sample"] = {"workload": f"64^3 Type {args.wall_type} Ra {args.ra:g}",
+                                     "storage": "f64", "value": round(64 ** 3 * 2000 / ms / 1e3, 1),
+                                     "unit": "MLUPS"}
+        c64.close()
     print(json.dumps(line), flush=True)
 
 
