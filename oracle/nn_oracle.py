@@ -37,6 +37,24 @@ def conv3d(x, w, b=None):
     return out
 
 
+def conv3d_at(x, w, b, points):
+    """conv3d at the given output voxels only: out[k, co] for points[k] =
+    (b, z, y, x), the same sum taken voxel by voxel (for tensors too large
+    for the whole convolution)."""
+    x = np.asarray(x, np.float64)
+    w = np.asarray(w, np.float64)
+    B, D, H, W, _ = x.shape
+    out = np.zeros((len(points), w.shape[0]))
+    for k, (bi, z, y, xx) in enumerate(points):
+        acc = np.zeros(w.shape[0]) if b is None else np.array(b, np.float64)
+        for t, dx, dy, dz in taps():
+            zz, yy, xs = z + dz, y + dy, xx + dx
+            if 0 <= zz < D and 0 <= yy < H and 0 <= xs < W:
+                acc = acc + w[:, t, :] @ x[bi, zz, yy, xs]
+        out[k] = acc
+    return out
+
+
 def conv3d_dgrad(gout, w):
     """Gradient of sum(gout * conv3d(x, w)) with respect to x."""
     gout = np.asarray(gout, np.float64)

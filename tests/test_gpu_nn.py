@@ -86,6 +86,33 @@ def test_conv_forward(shape, ci, co):
     assert np.all(np.abs(from_bf(ob) - ref) <= 2 ** -8 * np.abs(ref) + bound)
 
 
+@pytest.mark.parametrize("ci,co", [(16, 16), (48, 16), (16, 32), (32, 96)])
+def test_conv_forward_many_bricks(ci, co):
+    """4 x 36 x 34 x 40 voxels: 972 bricks of 16 x 4 x 4 (ragged in x, y
+    and z), several waves of blocks on the GPU (one and several rounds of 16
+    input channels, one and two channel tiles per block, one and several
+    tile groups), at a size whose full FP64 convolution is too slow for the
+    oracle: checked on 600 seeded voxels plus the corners against the
+    oracle's pointwise sum."""
+    import torch
+    print(f"case: conv fwd many bricks {ci}->{co}", flush=True)
+    B, D, H, W = 4, 36, 34, 40
+    x, w, b = rnd((B, D, H, W, ci), 11), rnd((co, 27, ci), 12, 0.1), rnd((co,), 13)
+    tx, tw, tb = to_bf(x), to_bf(w), to_f32(b)
+    out = torch.empty((B, D, H, W, co), dtype=torch.float32, device="cuda")
+    call("lbmx_nn_conv3d_fwd", P(tx), P(tw), P(tb), P(out), 1, B, D, H, W, ci, co, S())
+    got = out.cpu().numpy()
+    rng = np.random.default_rng(14)
+    pts = [(int(rng.integers(B)), int(rng.integers(D)), int(rng.integers(H)), int(rng.integers(W)))
+           for _ in range(600)]
+    pts += [(bi, z, y, xx) for bi in (0, B - 1) for z in (0, D - 1) for y in (0, H - 1)
+            for xx in (0, W - 1)]
+    ref = N.conv3d_at(x, w, b, pts)
+    bound = 2e-5 * N.conv3d_at(np.abs(x), np.abs(w), np.abs(b), pts) + 1e-6
+    g = np.array([got[p] for p in pts])
+    assert np.all(np.abs(g - ref) <= bound), (np.abs(g - ref).max(), (np.abs(g - ref) / bound).max())
+
+
 @pytest.mark.parametrize("shape", SHAPES)
 @pytest.mark.parametrize("ci,co", [(16, 16), (48, 16), (32, 96), (160, 64)])
 def test_conv_data_gradient(shape, ci, co):

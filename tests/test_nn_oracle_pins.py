@@ -26,6 +26,20 @@ def test_conv_matches_torch():
     assert np.abs(N.conv3d(x, w, b) - torch_conv(x, w, b)).max() < 1e-12
 
 
+def test_conv_at_points_is_the_convolution():
+    """The pointwise form agrees with conv3d (itself pinned to torch above)
+    at interior, face, edge and corner voxels of a ragged shape."""
+    rng = np.random.default_rng(21)
+    x = rng.standard_normal((2, 5, 4, 7, 3))
+    w = rng.standard_normal((4, 27, 3))
+    b = rng.standard_normal(4)
+    full = N.conv3d(x, w, b)
+    pts = [(0, 0, 0, 0), (1, 4, 3, 6), (0, 2, 1, 3), (1, 0, 2, 6), (0, 4, 0, 2)]
+    got = N.conv3d_at(x, w, b, pts)
+    for k, (bi, z, y, xx) in enumerate(pts):
+        assert np.abs(got[k] - full[bi, z, y, xx]).max() < 1e-12
+
+
 def test_conv_gradients_match_torch_autograd():
     x, w, b = rnd(2, 4, 5, 3, 3, seed=4), rnd(5, 27, 3, seed=5), rnd(5, seed=6)
     g = rnd(2, 4, 5, 3, 5, seed=7)
