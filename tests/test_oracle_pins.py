@@ -328,6 +328,61 @@ def test_conduction_limit(wall_type):
         assert abs(nu[k] - 1) < 1e-11
 
 
+def _variation(th, axis):
+    """Largest deviation of theta from its mean along one axis ([z, y, x])."""
+    return np.abs(th - th.mean(axis=axis, keepdims=True)).max()
+
+
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
+def test_which_walls_are_isothermal(wall_type):
+    """Sec. 2, Eqs. (6)-(10), Sec. 4.3: which side walls hold a temperature.
+    Without buoyancy, from theta = 0, only the y walls (Eqs. 6-7) and the
+    walls that carry the linear profile (Eqs. 9-10) drive the transient, so
+    theta varies along an axis exactly when a wall normal to it is held:
+      Type 1: x and z walls adiabatic -> theta independent of x and of z;
+      Type 2: x and z walls linear    -> theta depends on both;
+      Type 3: x walls linear, z walls adiabatic -> on x, not on z.
+    The conduction limit cannot tell these apart (the linear profile is a
+    fixed point of every assignment); this transient does.  Type 2 is also
+    symmetric under exchanging x and z, Type 3 is not."""
+    n = 8
+    o = O.Oracle(n, wall_type, ra=1e4, buoyancy_scale=0.0)
+    o.step(40)
+    _, ux, uy, uz, th = o.macro()
+    assert np.abs(np.stack([ux, uy, uz])).max() == 0.0
+    vx, vz, vy = _variation(th, 2), _variation(th, 0), _variation(th, 1)
+    assert vy > 0.2  # the hot and cold walls always act
+    held = {1: (False, False), 2: (True, True), 3: (True, False)}[wall_type]
+    for v, h in zip((vx, vz), held):
+        assert (v > 0.05) if h else (v < 1e-15), (wall_type, vx, vz)
+    swap = np.transpose(th, (2, 1, 0))  # exchange x and z
+    if wall_type == 3:
+        assert np.abs(th - swap).max() > 0.05
+    else:
+        assert np.abs(th - swap).max() < 1e-15
+
+
+def test_nusselt_order_of_the_wall_types_at_steady_state():
+    """Sec. 4.3 (Tables 6-8): at equal Ra the hot-wall Nusselt number orders
+    as Nu(Type 2) < Nu(Type 3) < Nu(Type 1): linear side walls carry heat the
+    adiabatic ones do not.  The oracle run to steady at 16^3, Ra 1e4
+    (|dNu_3D| < 1e-6 per 1000 steps) must show the same order, with every
+    value above the conduction limit Nu = 1."""
+    nu = {}
+    for wt in (1, 2, 3):
+        o = O.Oracle(16, wt, ra=1e4)
+        prev = o.nusselt()["nu3d"]
+        for _ in range(40):
+            o.step(1000)
+            cur = o.nusselt()["nu3d"]
+            if abs(cur - prev) < 1e-6:
+                break
+            prev = cur
+        assert abs(cur - prev) < 1e-6, (wt, o.t)
+        nu[wt] = cur
+    assert 1.0 < nu[2] < nu[3] < nu[1], nu
+
+
 def test_conduction_limit_ignores_tau5_to_tau7():
     """End of Sec. 3.2: tau_5..tau_7 only change error terms; the conduction
     solution stays exact for other values."""
