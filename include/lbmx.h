@@ -26,6 +26,21 @@
  *   - Time: a fresh or re-initialised cavity is at t = 0; lbmx_step advances
  *     t.  Every read returns the state at the current t (pre-collision
  *     populations, i.e. after streaming and wall conditions).
+ *   - Device memory: a cavity holds two lattices (the current state and
+ *     the one the next step writes) and a small reduction scratch, all in
+ *     its workspace.  Between steps the second lattice is spare, and the
+ *     transfers and readbacks stage their data in it, so no call on a
+ *     cavity after lbmx_create allocates device memory (lbmx_save and
+ *     lbmx_load use a pinned host buffer of up to 64 MB).
+ *   - Failed cavities: a cavity fails when a Nu evaluation finds non-finite
+ *     values (LBMX_EUNSTABLE: the run diverged) or when a device call fails
+ *     while its state is being changed.  Until an initialisation succeeds
+ *     (lbmx_init_rest, lbmx_set_populations, lbmx_load, lbmx_init_fields,
+ *     lbmx_init_from_cavity with it as the destination), lbmx_step,
+ *     lbmx_step_timed, lbmx_run_to_steady, lbmx_save and
+ *     lbmx_init_from_cavity with it as the source return LBMX_ESTATE; the
+ *     reads (lbmx_read_macro, lbmx_get_populations, lbmx_nusselt,
+ *     lbmx_time) still work, to inspect what went wrong.
  */
 #ifndef LBMX_H
 #define LBMX_H
@@ -158,12 +173,14 @@ void lbmx_destroy(lbmx_cavity *h);
 lbmx_status lbmx_init_rest(lbmx_cavity *h, const double *theta0_host);
 
 /* Set the state at time t from host populations: f (19 n^3) and g (7 n^3)
- * doubles, population-major (as returned by lbmx_get_populations). */
+ * doubles, population-major (as returned by lbmx_get_populations).  Staged
+ * in the spare lattice by opposite-direction pairs. */
 lbmx_status lbmx_set_populations(lbmx_cavity *h, const double *f_host, const double *g_host,
                                  int64_t t);
 
 /* Copy the populations of the current state to host (19 n^3 and 7 n^3
- * doubles; either pointer may be NULL). */
+ * doubles; either pointer may be NULL), in passes of as many populations as
+ * the spare lattice holds (1 pass FP64, 2 FP32, up to 5 for 16-bit). */
 lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host);
 
 /* Checkpoints, for callers that resume long runs (the paper's runs to a
@@ -173,7 +190,10 @@ lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host)
  * lbmx_load reads such a file into a cavity created with the same parameter
  * set (the custom s, tau arrays are compared only when custom_rates = 1, the
  * Nu stencil not at all: it only reads the state), so
- * that stepping on continues bitwise as the saved cavity would.  The file is
+ * that stepping on continues bitwise as the saved cavity would.  lbmx_load
+ * reads the lattice into the cavity's spare lattice and switches to it only
+ * after the last byte has arrived, so a load that fails leaves the state as
+ * it was (a successful load also clears a failed state).  The file is
  * a 376-byte header (magic "LBMXCKPT", version 1, sizeof(lbmx_params), the
  * parameters, t, lattice bytes, nodes per slab; host byte order) followed by
  * the lattice; it is tied to this library's lattice layout and is not meant
@@ -201,10 +221,10 @@ lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *de
  * with s = u_c(dst) / u_c(src) (Eq. 38: 1 unless Ma differs) dst takes
  * f = f^eq(rho', s u) of Eq. (17), rho' = 1 + s^2 (rho - 1) (the density
  * variations are pressure, of order u_c^2), and g = g^eq(theta, s u).  src
- * is only read.  Both cavities must live on the current device.  Allocates
- * and frees a 40 src_n^3-byte device buffer; synchronises both streams.
- * Errors: EINVAL for a NULL, failed or identical handle or another device,
- * EDEVICE for a HIP failure. */
+ * is only read; its fields (5 src_n^3 doubles) are staged in src's spare
+ * lattice.  Both cavities must live on the current device.  Synchronises
+ * both streams.  Errors: EINVAL for a NULL or identical handle or another
+ * device, ESTATE for a failed src, EDEVICE for a HIP failure. */
 lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src);
 
 /* Advance nsteps >= 0 time steps (fused streaming + double-MRT collision,
@@ -220,7 +240,7 @@ lbmx_status lbmx_time(const lbmx_cavity *h, int64_t *t);
 
 /* Macroscopic fields at the current t to host arrays (n^3 doubles each,
  * any may be NULL): rho = sum f (Eq. 20), u = j / rho with j = sum e_i f_i,
- * theta = sum g (Eq. 30). */
+ * theta = sum g (Eq. 30).  Staged in the spare lattice. */
 lbmx_status lbmx_read_macro(lbmx_cavity *h, double *rho, double *ux, double *uy, double *uz,
                             double *theta);
 
@@ -228,7 +248,7 @@ lbmx_status lbmx_read_macro(lbmx_cavity *h, double *rho, double *ux, double *uy,
  * Nu = -n (9 theta_0 - theta_1 - 8 theta_hot)/3 from the two wall-adjacent
  * nodes (second order, exact for quadratic profiles); map_host (n*n doubles,
  * x fastest then z) may be NULL.  Returns EUNSTABLE (with *out filled) if any
- * local value is not finite. */
+ * local value is not finite, and the cavity is then failed (see above). */
 lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host);
 
 /* Step in chunks of `every` and stop once |Nu_3D(t) - Nu_3D(t - every)| < tol
@@ -239,9 +259,11 @@ lbmx_status lbmx_run_to_steady(lbmx_cavity *h, double tol, int64_t every, int64_
                                lbmx_nu *out);
 
 /* Launch shape of the step kernel: block = (bx, by) threads over (x, y),
- * grid covers the cube; bx*by must be a multiple of 64 (one wavefront) and
- * at most 1024, unless bx = n and by = 1.  0, 0 restores the default
- * (bx = min(n, 256), by = min(n, max(1, 256 / bx))). */
+ * grid covers the cube.  Any bx, by >= 1 with bx*by <= 1024 gives the same
+ * results (each thread finds its node and walls from its own indices);
+ * shapes whose rows span whole wavefronts (bx a multiple of 64, or bx = n)
+ * keep every load and store coalesced and run fastest.  EINVAL otherwise.
+ * 0, 0 restores the default (bx = min(n, 256), by = min(n, max(1, 256 / bx))). */
 lbmx_status lbmx_set_launch(lbmx_cavity *h, int32_t bx, int32_t by);
 lbmx_status lbmx_get_launch(const lbmx_cavity *h, int32_t *bx, int32_t *by);
 
@@ -298,13 +320,16 @@ lbmx_status lbmx_batch_nusselt(lbmx_batch *b, int32_t k, lbmx_nu *out);
  * Synchronises both batches' streams.  Errors as lbmx_init_from_cavity. */
 lbmx_status lbmx_batch_init_from(lbmx_batch *b, int32_t k, lbmx_batch *src, int32_t ks);
 
-/* Macroscopic fields of cavity k, as lbmx_read_macro. */
+/* Macroscopic fields of cavity k, as lbmx_read_macro (staged in cavity k's
+ * spare lattice). */
 lbmx_status lbmx_batch_read_macro(lbmx_batch *b, int32_t k, double *rho, double *ux, double *uy,
                                   double *uz, double *theta);
 
 /* u, v, w (lattice units) and theta of cavity k resampled trilinearly onto
  * an out_n^3 node-centred grid of the same cube (clamped at the outermost
- * node centres): host_uvwt holds 4 out_n^3 floats, field-major, x fastest. */
+ * node centres): host_uvwt holds 4 out_n^3 floats, field-major, x fastest.
+ * Allocates and frees device buffers of 32 n_k^3 + 16 out_n^3 bytes (a
+ * dataset-export call, not part of the stepping). */
 lbmx_status lbmx_batch_resample(lbmx_batch *b, int32_t k, int32_t out_n, float *host_uvwt);
 
 /* Launch shape: `block` threads (= nodes per tile, multiple of 64, <= 1024),

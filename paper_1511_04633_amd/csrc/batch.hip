@@ -63,11 +63,15 @@ struct lbmx_batch {
 
 namespace {
 
+// Cavity k's current lattice; the other one is spare between launches (the
+// next step of an active cavity overwrites it; a retired cavity's is idle).
 View view_of(lbmx_batch *b, int k)
 {
     const lbmx_params &p = b->p[k];
-    return make_view(b->ws + b->off[k] + (size_t)b->cur[k] * b->L[k].lattice, p, b->d[k], true,
-                     b->stream);
+    char *base = b->ws + b->off[k];
+    const size_t lat = b->L[k].lattice;
+    return make_view(base + (size_t)b->cur[k] * lat, base + (size_t)(1 - b->cur[k]) * lat, lat, p,
+                     b->d[k], true, b->stream);
 }
 
 double *scratch_of(lbmx_batch *b, int k) { return reinterpret_cast<double *>(b->ws + b->scr[k]); }
@@ -90,7 +94,8 @@ lbmx_status upload_cavs(lbmx_batch *b)
         BatchCav<T> &c = h[k];
         c.lat[0] = b->ws + b->off[k];
         c.lat[1] = b->ws + b->off[k] + b->L[k].lattice;
-        c.geo = geometry<St>(make_view(c.lat[0], b->p[k], b->d[k], true, b->stream));
+        c.geo = geometry<St>(make_view(c.lat[0], c.lat[1], b->L[k].lattice, b->p[k], b->d[k], true,
+                                       b->stream));
         c.rates = make_rates<T>(&b->p[k], b->d[k]);
         c.cells = uint32_t(b->p[k].n) * b->p[k].n * b->p[k].n;
         c.inv_n = 1.0f / float(b->p[k].n);
@@ -442,19 +447,11 @@ lbmx_status lbmx_batch_init_rest(lbmx_batch *b, int32_t k, const double *theta0_
     lbmx_status s = check(b, k);
     if (s != LBMX_OK)
         return s;
-    const size_t cells = size_t(b->p[k].n) * b->p[k].n * b->p[k].n;
-    DevBuf buf;
-    if (theta0_host) {
-        HIP_TRY(hipMalloc(&buf.p, cells * sizeof(double)));
-        HIP_TRY(hipMemcpyAsync(buf.p, theta0_host, cells * sizeof(double), hipMemcpyHostToDevice,
-                               b->stream));
-    }
     // A re-initialised cavity rejoins the lockstep at the batch's parity.
     b->cur[k] = b->parity;
-    s = LBMX_DISPATCH(b->storage, unstream_rest, view_of(b, k), reinterpret_cast<const double *>(buf.p));
+    s = LBMX_DISPATCH(b->storage, rest_from_host, view_of(b, k), theta0_host);
     if (s != LBMX_OK)
         return s;
-    HIP_TRY(hipStreamSynchronize(b->stream));
     b->t[k] = 0;
     b->last[k] = lbmx_nu{};
     if (b->state[k] != ST_ACTIVE) {
@@ -603,22 +600,7 @@ lbmx_status lbmx_batch_read_macro(lbmx_batch *b, int32_t k, double *rho, double 
     lbmx_status s = check(b, k);
     if (s != LBMX_OK)
         return s;
-    const size_t cells = size_t(b->p[k].n) * b->p[k].n * b->p[k].n;
-    double *host[5] = {rho, ux, uy, uz, theta};
-    DevBuf buf;
-    HIP_TRY(hipMalloc(&buf.p, 5 * cells * sizeof(double)));
-    double *dev[5];
-    for (int i = 0; i < 5; ++i)
-        dev[i] = host[i] ? reinterpret_cast<double *>(buf.p) + i * cells : nullptr;
-    s = LBMX_DISPATCH(b->storage, launch_macro, view_of(b, k), dev[0], dev[1], dev[2], dev[3], dev[4]);
-    if (s != LBMX_OK)
-        return s;
-    for (int i = 0; i < 5; ++i)
-        if (host[i])
-            HIP_TRY(hipMemcpyAsync(host[i], dev[i], cells * sizeof(double), hipMemcpyDeviceToHost,
-                                   b->stream));
-    HIP_TRY(hipStreamSynchronize(b->stream));
-    return LBMX_OK;
+    return LBMX_DISPATCH(b->storage, macro_to_host, view_of(b, k), rho, ux, uy, uz, theta);
 }
 
 lbmx_status lbmx_batch_resample(lbmx_batch *b, int32_t k, int32_t out_n, float *host_uvwt)

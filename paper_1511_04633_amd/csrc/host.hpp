@@ -6,6 +6,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
@@ -230,9 +231,15 @@ inline Layout layout_of(const lbmx_params *p)
 
 
 // A lattice seen by the launchers: `lat` is the lattice holding the current
-// state, `off32` selects 32-bit offsets.
+// state, `off32` selects 32-bit offsets.  `spare` is the cavity's other
+// lattice (spare_bytes long): the next step overwrites all of it, so between
+// steps it serves as the staging buffer of transfers and readbacks, which
+// therefore allocate no device memory.  A lattice holds at least 52 bytes
+// per node (26 16-bit populations), i.e. 6 doubles per node.
 struct View {
     char *lat;
+    char *spare;
+    size_t spare_bytes;
     int n, wall_type;
     double theta_hot, theta_cold;
     bool off32;
@@ -243,11 +250,13 @@ struct View {
     double d_yy;       // for the wall-flux Nu stencil
 };
 
-inline View make_view(char *lat, const lbmx_params &p, const Derived &d, bool off32,
-                      hipStream_t stream)
+inline View make_view(char *lat, char *spare, size_t spare_bytes, const lbmx_params &p,
+                      const Derived &d, bool off32, hipStream_t stream)
 {
     View v;
     v.lat = lat;
+    v.spare = spare;
+    v.spare_bytes = spare_bytes;
     v.n = p.n;
     v.wall_type = p.wall_type;
     v.theta_hot = p.theta_hot;
@@ -274,17 +283,19 @@ Geometry<typename St::T> geometry(const View &v)
     return g;
 }
 
+constexpr uint32_t kAllPops = (1u << 26) - 1;
+
 template <class St, typename Src>
-lbmx_status launch_unstream(const View &v, const Src &src)
+lbmx_status launch_unstream(const View &v, const Src &src, uint32_t mask = kAllPops)
 {
     const size_t cells = (size_t)v.n * v.n * v.n;
     const unsigned blocks = (unsigned)((cells + 255) / 256);
     if (v.off32)
         hipLaunchKernelGGL((k_unstream<St, true, Src>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
-                           geometry<St>(v), src);
+                           geometry<St>(v), src, mask);
     else
         hipLaunchKernelGGL((k_unstream<St, false, Src>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
-                           geometry<St>(v), src);
+                           geometry<St>(v), src, mask);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -305,17 +316,117 @@ lbmx_status launch_macro(const View &v, double *r, double *u, double *w3, double
 }
 
 template <class St>
-lbmx_status launch_pops(const View &v, double *f, double *g)
+lbmx_status launch_pops(const View &v, int first, int count, double *out)
 {
     const size_t cells = (size_t)v.n * v.n * v.n;
     const unsigned blocks = (unsigned)((cells + 255) / 256);
     if (v.off32)
         hipLaunchKernelGGL((k_pops<St, true>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
-                           geometry<St>(v), f, g);
+                           geometry<St>(v), first, count, out);
     else
         hipLaunchKernelGGL((k_pops<St, false>), dim3(blocks), dim3(256), 0, v.stream, v.lat,
-                           geometry<St>(v), f, g);
+                           geometry<St>(v), first, count, out);
     HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+// Doubles per node the spare lattice can stage (at least 6).
+inline size_t spare_doubles(const View &v)
+{
+    const size_t cells = (size_t)v.n * v.n * v.n;
+    return v.spare_bytes / (sizeof(double) * cells);
+}
+
+// Host population array of population p (flow 0..18, energy 19..25).
+template <typename D>
+D *host_pop(D *f, D *g, int p, size_t cells)
+{
+    return p < 19 ? f + (size_t)p * cells : g + (size_t)(p - 19) * cells;
+}
+
+// Populations of the current state to host (f: 19 n^3, g: 7 n^3 doubles;
+// either may be null), in passes of as many populations as the spare
+// lattice holds.  Synchronises the stream.
+template <class St>
+lbmx_status pops_to_host(const View &v, double *f, double *g)
+{
+    const size_t cells = (size_t)v.n * v.n * v.n;
+    const int cap = int(std::min<size_t>(26, spare_doubles(v)));
+    double *stage = reinterpret_cast<double *>(v.spare);
+    const int lo = f ? 0 : 19, hi = g ? 26 : 19;
+    for (int p0 = lo; p0 < hi; p0 += cap) {
+        const int count = std::min(cap, hi - p0);
+        lbmx_status s = launch_pops<St>(v, p0, count, stage);
+        if (s != LBMX_OK)
+            return s;
+        for (int k = 0; k < count; ++k)
+            HIP_TRY(hipMemcpyAsync(host_pop(f, g, p0 + k, cells), stage + (size_t)k * cells,
+                                   cells * sizeof(double), hipMemcpyDeviceToHost, v.stream));
+    }
+    HIP_TRY(hipStreamSynchronize(v.stream));
+    return LBMX_OK;
+}
+
+// State from host populations (f: 19 n^3, g: 7 n^3 doubles): each pass
+// stages whole opposite pairs (i, ibar) in the spare lattice and unstreams
+// those populations.  Synchronises the stream.
+template <class St>
+lbmx_status pops_from_host(const View &v, const double *f, const double *g)
+{
+    static const int pairs[14][2] = {{0, -1},  {1, 2},   {3, 4},   {5, 6},   {7, 10},
+                                     {8, 9},   {11, 14}, {12, 13}, {15, 18}, {16, 17},
+                                     {19, -1}, {20, 21}, {22, 23}, {24, 25}};
+    const size_t cells = (size_t)v.n * v.n * v.n;
+    const int cap = int(std::min<size_t>(26, spare_doubles(v)));
+    double *stage = reinterpret_cast<double *>(v.spare);
+    int q = 0;
+    while (q < 14) {
+        SourcePops src;
+        src.buf = stage;
+        src.cells = cells;
+        for (int p = 0; p < 26; ++p)
+            src.slot[p] = -1;
+        uint32_t mask = 0;
+        int used = 0;
+        for (; q < 14; ++q) {
+            const int need = pairs[q][1] < 0 ? 1 : 2;
+            if (used + need > cap)
+                break;
+            for (int m = 0; m < need; ++m) {
+                const int p = pairs[q][m];
+                src.slot[p] = (signed char)used;
+                mask |= 1u << p;
+                HIP_TRY(hipMemcpyAsync(stage + (size_t)used * cells, host_pop(f, g, p, cells),
+                                       cells * sizeof(double), hipMemcpyHostToDevice, v.stream));
+                ++used;
+            }
+        }
+        lbmx_status s = launch_unstream<St>(v, src, mask);
+        if (s != LBMX_OK)
+            return s;
+    }
+    HIP_TRY(hipStreamSynchronize(v.stream));
+    return LBMX_OK;
+}
+
+// Macroscopic fields of the current state to host arrays (any may be null),
+// staged in the spare lattice (5 doubles per node).  Synchronises the stream.
+template <class St>
+lbmx_status macro_to_host(const View &v, double *r, double *u, double *w3, double *w, double *th)
+{
+    const size_t cells = (size_t)v.n * v.n * v.n;
+    double *host[5] = {r, u, w3, w, th};
+    double *dev[5];
+    for (int k = 0; k < 5; ++k)
+        dev[k] = host[k] ? reinterpret_cast<double *>(v.spare) + k * cells : nullptr;
+    lbmx_status s = launch_macro<St>(v, dev[0], dev[1], dev[2], dev[3], dev[4]);
+    if (s != LBMX_OK)
+        return s;
+    for (int k = 0; k < 5; ++k)
+        if (host[k])
+            HIP_TRY(hipMemcpyAsync(host[k], dev[k], cells * sizeof(double), hipMemcpyDeviceToHost,
+                                   v.stream));
+    HIP_TRY(hipStreamSynchronize(v.stream));
     return LBMX_OK;
 }
 
@@ -344,10 +455,23 @@ lbmx_status unstream_rest(const View &v, const double *theta0)
     return launch_unstream<St>(v, SourceRest{theta0});
 }
 
+// Rest state with theta0 from the host (n^3 doubles, staged in the spare
+// lattice; null = theta 0).  Synchronises the stream.
 template <class St>
-lbmx_status unstream_pops(const View &v, const double *f, const double *g)
+lbmx_status rest_from_host(const View &v, const double *theta0_host)
 {
-    return launch_unstream<St>(v, SourcePops{f, g, (size_t)v.n * v.n * v.n});
+    const size_t cells = (size_t)v.n * v.n * v.n;
+    const double *th = nullptr;
+    if (theta0_host) {
+        HIP_TRY(hipMemcpyAsync(v.spare, theta0_host, cells * sizeof(double), hipMemcpyHostToDevice,
+                               v.stream));
+        th = reinterpret_cast<const double *>(v.spare);
+    }
+    lbmx_status s = unstream_rest<St>(v, th);
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(v.stream));
+    return LBMX_OK;
 }
 
 template <class St, class E>
@@ -404,14 +528,13 @@ inline lbmx_status check_same_device(const void *a, const void *b, const char *w
 // theta (Eqs. 20, 25, 30) formed in FP64 on the device, resampled
 // trilinearly onto dst's nodes (SourceFields<double>), velocities scaled by
 // vscale and rho - 1 by vscale^2; f = f^eq(rho, u), g = g^eq(theta, u).
-// Synchronises both streams; the temporary buffer holds 5 src.n^3 doubles.
+// Synchronises both streams; the 5 src.n^3 doubles of fields are staged in
+// src's spare lattice (src's state is only read).
 inline lbmx_status init_from_state(const View &dst, int32_t dst_storage, const View &src,
                                    int32_t src_storage, double vscale)
 {
     const size_t mc = (size_t)src.n * src.n * src.n;
-    DevBuf buf;
-    HIP_TRY(hipMalloc(&buf.p, 5 * mc * sizeof(double)));
-    double *f5 = reinterpret_cast<double *>(buf.p);
+    double *f5 = reinterpret_cast<double *>(src.spare);
     lbmx_status s = LBMX_DISPATCH(src_storage, launch_macro, src, f5 + 4 * mc, f5, f5 + mc,
                                   f5 + 2 * mc, f5 + 3 * mc);
     if (s != LBMX_OK)

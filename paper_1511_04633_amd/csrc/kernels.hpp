@@ -405,11 +405,21 @@ struct SourceRest {            // f = w_i, g = w_T,i theta0
     __device__ double g(int i, int c) const { return theta0 ? w7(i) * theta0[c] : 0.0; }
 };
 
-struct SourcePops {            // full population arrays f[19][n^3], g[7][n^3]
-    const double *fa, *ga;
+// Some of the 26 population arrays of a state (numbered 0..18 flow, 19..25
+// energy), each n^3 doubles: population p sits at buf + slot[p] * cells
+// (slot -1: not staged).  Unstreaming population i at a node needs only
+// S_i and S_ibar, so a transfer can stage the populations in opposite pairs
+// and write those pairs, pass after pass, through a buffer of a few
+// populations.
+struct SourcePops {
+    const double *buf;
     size_t cells;
-    __device__ double f(int i, int c) const { return fa[(size_t)i * cells + c] - w19(i); }
-    __device__ double g(int i, int c) const { return ga[(size_t)i * cells + c]; }
+    signed char slot[26];
+    __device__ double f(int i, int c) const
+    {
+        return buf[(size_t)slot[i] * cells + c] - w19(i);
+    }
+    __device__ double g(int i, int c) const { return buf[(size_t)slot[19 + i] * cells + c]; }
 };
 
 // Velocity / temperature (and optionally density) fields sampled
@@ -484,10 +494,13 @@ struct SourceFields {
 
 // "Unstream": write the post-collision lattice P whose pull reproduces S.
 // For population i at node y: if y + e_i is inside, P_i(y) = S_i(y + e_i);
-// otherwise P_i(y) is the value that the wall turns into S_ibar(y).
+// otherwise P_i(y) is the value that the wall turns into S_ibar(y).  Only
+// the populations whose bit is set in `mask` (bit p: population p, flow
+// 0..18, energy 19..25) are written.
 template <class St, bool kOff32, typename Src>
 __global__ __launch_bounds__(256) void k_unstream(char *__restrict__ dst,
-                                                  Geometry<typename St::T> geo, Src srcS)
+                                                  Geometry<typename St::T> geo, Src srcS,
+                                                  uint32_t mask)
 {
     using T = typename St::T;
     using SF = typename St::F;
@@ -502,6 +515,8 @@ __global__ __launch_bounds__(256) void k_unstream(char *__restrict__ dst,
         return;
     const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
     for (int i = 0; i < 19; ++i) {
+        if (!((mask >> i) & 1u))
+            continue;
         const int tx = x + ex19(i), ty = y + ey19(i), tz = z + ez19(i);
         const bool in = tx >= 0 && tx < n && ty >= 0 && ty < n && tz >= 0 && tz < n;
         double v = in ? srcS.f(i, tx + n * (ty + n * tz)) : srcS.f(opp19(i), int(c));
@@ -512,6 +527,8 @@ __global__ __launch_bounds__(256) void k_unstream(char *__restrict__ dst,
     const int gx[7] = {0, 1, -1, 0, 0, 0, 0}, gy[7] = {0, 0, 0, 1, -1, 0, 0},
               gz[7] = {0, 0, 0, 0, 0, 1, -1}, go[7] = {0, 2, 1, 4, 3, 6, 5};
     for (int i = 0; i < 7; ++i) {
+        if (!((mask >> (19 + i)) & 1u))
+            continue;
         const int tx = x + gx[i], ty = y + gy[i], tz = z + gz[i];
         double v;
         if (tx >= 0 && tx < n && ty >= 0 && ty < n && tz >= 0 && tz < n) {
@@ -567,10 +584,12 @@ __global__ __launch_bounds__(256) void k_macro(const char *__restrict__ src,
     if (theta) theta[c] = th;
 }
 
-// Populations at time t as plain doubles, population-major.
+// Populations first .. first + count - 1 (flow 0..18, energy 19..25) at
+// time t as plain doubles: out[(p - first) * n^3 + c].
 template <class St, bool kOff32>
 __global__ __launch_bounds__(256) void k_pops(const char *__restrict__ src,
-                                              Geometry<typename St::T> geo, double *fo, double *go)
+                                              Geometry<typename St::T> geo, int first, int count,
+                                              double *out)
 {
     using T = typename St::T;
     const int n = geo.n;
@@ -581,12 +600,10 @@ __global__ __launch_bounds__(256) void k_pops(const char *__restrict__ src,
     const int x = int(c % n), y = int((c / n) % n), z = int(c / ((long long)n * n));
     T f[19], g[7];
     pull<St, kOff32>(src, geo, x, y, z, f, g);
-    if (fo)
-        for (int i = 0; i < 19; ++i)
-            fo[(size_t)i * cells + c] = w19(i) + double(f[i]);
-    if (go)
-        for (int i = 0; i < 7; ++i)
-            go[(size_t)i * cells + c] = double(g[i]);
+    for (int k = 0; k < count; ++k) {
+        const int p = first + k;
+        out[(size_t)k * cells + c] = p < 19 ? w19(p) + double(f[p]) : double(g[p - 19]);
+    }
 }
 
 // --------------------------------------------------------- Nusselt number

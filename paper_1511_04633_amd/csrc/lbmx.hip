@@ -52,6 +52,11 @@ struct lbmx_cavity {
     int64_t t;
     int bx, by;
     bool off32;  // a lattice spans < 4 GiB: kernels use 32-bit byte offsets
+    // The state is unusable: a Nu evaluation found non-finite values, or a
+    // device call failed while the state was being changed.  Stepping,
+    // saving and using the cavity as a source return LBMX_ESTATE until an
+    // initialisation succeeds.
+    bool failed;
 };
 
 namespace {
@@ -62,7 +67,8 @@ double *scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L
 
 View view(lbmx_cavity *h)
 {
-    return make_view(lattice(h, h->cur), h->p, h->d, h->off32, h->stream);
+    return make_view(lattice(h, h->cur), lattice(h, 1 - h->cur), h->L.lattice, h->p, h->d, h->off32,
+                     h->stream);
 }
 
 // One row of up to 256 nodes along x per block row; up to 256 threads per
@@ -117,6 +123,31 @@ lbmx_status check_handle(const lbmx_cavity *h)
     if (!h)
         return fail(LBMX_EINVAL, "cavity handle is NULL");
     return LBMX_OK;
+}
+
+// As check_handle, and ESTATE for a failed cavity (calls that need a
+// usable state: stepping, saving, serving as a source).
+lbmx_status check_usable(const lbmx_cavity *h)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (h->failed)
+        return fail(LBMX_ESTATE, "the cavity's state is unusable (diverged or a device call failed); "
+                    "initialise it again");
+    return LBMX_OK;
+}
+
+// Run an initialisation that rewrites the state: the cavity is failed while
+// it runs and stays failed if it does not succeed.
+template <class Fn>
+lbmx_status reinit(lbmx_cavity *h, Fn fn)
+{
+    h->failed = true;
+    lbmx_status s = fn();
+    if (s == LBMX_OK)
+        h->failed = false;
+    return s;
 }
 
 // Checkpoint file header (no padding: 8 + 4 + 4 + 336 + 3 x 8 bytes).
@@ -266,6 +297,7 @@ lbmx_status lbmx_create(const lbmx_params *p, void *dev_workspace, size_t ws_byt
     h->L = L;
     h->cur = 0;
     h->t = 0;
+    h->failed = false;
     h->off32 = double(L.lattice) <= 4294967295.0;
     default_launch(p->n, &h->bx, &h->by);
     if (stream) {
@@ -321,20 +353,13 @@ lbmx_status lbmx_init_rest(lbmx_cavity *h, const double *theta0_host)
     lbmx_status s = check_handle(h);
     if (s != LBMX_OK)
         return s;
-    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
-    DevBuf buf;
-    if (theta0_host) {
-        HIP_TRY(hipMalloc(&buf.p, cells * sizeof(double)));
-        HIP_TRY(hipMemcpyAsync(buf.p, theta0_host, cells * sizeof(double), hipMemcpyHostToDevice,
-                               h->stream));
-    }
-    h->cur = 0;
-    s = LBMX_DISPATCH(h->p.storage, unstream_rest, view(h), reinterpret_cast<const double *>(buf.p));
-    if (s != LBMX_OK)
-        return s;
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    h->t = 0;
-    return LBMX_OK;
+    return reinit(h, [&]() -> lbmx_status {
+        h->cur = 0;
+        lbmx_status r = LBMX_DISPATCH(h->p.storage, rest_from_host, view(h), theta0_host);
+        if (r == LBMX_OK)
+            h->t = 0;
+        return r;
+    });
 }
 
 lbmx_status lbmx_set_populations(lbmx_cavity *h, const double *f_host, const double *g_host,
@@ -347,19 +372,12 @@ lbmx_status lbmx_set_populations(lbmx_cavity *h, const double *f_host, const dou
         return fail(LBMX_EINVAL, "population arrays must not be NULL");
     if (t < 0)
         return fail(LBMX_EINVAL, "t must be >= 0");
-    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
-    DevBuf buf;
-    HIP_TRY(hipMalloc(&buf.p, 26 * cells * sizeof(double)));
-    double *fd = reinterpret_cast<double *>(buf.p);
-    double *gd = fd + 19 * cells;
-    HIP_TRY(hipMemcpyAsync(fd, f_host, 19 * cells * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    HIP_TRY(hipMemcpyAsync(gd, g_host, 7 * cells * sizeof(double), hipMemcpyHostToDevice, h->stream));
-    s = LBMX_DISPATCH(h->p.storage, unstream_pops, view(h), fd, gd);
-    if (s != LBMX_OK)
-        return s;
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    h->t = t;
-    return LBMX_OK;
+    return reinit(h, [&]() -> lbmx_status {
+        lbmx_status r = LBMX_DISPATCH(h->p.storage, pops_from_host, view(h), f_host, g_host);
+        if (r == LBMX_OK)
+            h->t = t;
+        return r;
+    });
 }
 
 lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host)
@@ -367,25 +385,12 @@ lbmx_status lbmx_get_populations(lbmx_cavity *h, double *f_host, double *g_host)
     lbmx_status s = check_handle(h);
     if (s != LBMX_OK)
         return s;
-    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
-    DevBuf buf;
-    HIP_TRY(hipMalloc(&buf.p, 26 * cells * sizeof(double)));
-    double *fd = reinterpret_cast<double *>(buf.p);
-    double *gd = fd + 19 * cells;
-    s = LBMX_DISPATCH(h->p.storage, launch_pops, view(h), f_host ? fd : nullptr, g_host ? gd : nullptr);
-    if (s != LBMX_OK)
-        return s;
-    if (f_host)
-        HIP_TRY(hipMemcpyAsync(f_host, fd, 19 * cells * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    if (g_host)
-        HIP_TRY(hipMemcpyAsync(g_host, gd, 7 * cells * sizeof(double), hipMemcpyDeviceToHost, h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return LBMX_OK;
+    return LBMX_DISPATCH(h->p.storage, pops_to_host, view(h), f_host, g_host);
 }
 
 lbmx_status lbmx_save(lbmx_cavity *h, const char *path)
 {
-    lbmx_status s = check_handle(h);
+    lbmx_status s = check_usable(h);
     if (s != LBMX_OK)
         return s;
     if (!path)
@@ -453,10 +458,12 @@ lbmx_status lbmx_load(lbmx_cavity *h, const char *path)
                     sizeof hd + h->L.lattice);
     if (std::fseek(f.f, (long)sizeof hd, SEEK_SET) != 0)
         return fail(LBMX_EIO, "cannot seek in %s", path);
+    // Read into the spare lattice and switch to it only once every byte has
+    // arrived: a failed read leaves the current state as it was.
     HostBuf stage;
     const size_t chunk = std::min<size_t>(h->L.lattice, kCkptChunk);
     HIP_TRY(hipHostMalloc(&stage.p, chunk, hipHostMallocDefault));
-    char *lat = lattice(h, 0);
+    char *lat = lattice(h, 1 - h->cur);
     for (size_t off = 0; off < h->L.lattice; off += chunk) {
         const size_t len = std::min(chunk, h->L.lattice - off);
         if (std::fread(stage.p, 1, len, f.f) != len)
@@ -464,8 +471,9 @@ lbmx_status lbmx_load(lbmx_cavity *h, const char *path)
         HIP_TRY(hipMemcpyAsync(lat + off, stage.p, len, hipMemcpyHostToDevice, h->stream));
         HIP_TRY(hipStreamSynchronize(h->stream));
     }
-    h->cur = 0;
+    h->cur = 1 - h->cur;
     h->t = hd.t;
+    h->failed = false;
     return LBMX_OK;
 }
 
@@ -479,14 +487,16 @@ lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *de
         return fail(LBMX_EINVAL, "field pointers must not be NULL");
     if (src_n < 1 || src_n > 4096)
         return fail(LBMX_EINVAL, "src_n = %d outside [1, 4096]", src_n);
-    h->cur = 0;
-    s = LBMX_DISPATCH(h->p.storage, unstream_fields, view(h), dev_u, dev_v, dev_w, dev_theta, src_n,
-                      1.0, (const float *)nullptr);
-    if (s != LBMX_OK)
-        return s;
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    h->t = 0;
-    return LBMX_OK;
+    return reinit(h, [&]() -> lbmx_status {
+        h->cur = 0;
+        lbmx_status r = LBMX_DISPATCH(h->p.storage, unstream_fields, view(h), dev_u, dev_v, dev_w,
+                                      dev_theta, src_n, 1.0, (const float *)nullptr);
+        if (r != LBMX_OK)
+            return r;
+        HIP_TRY(hipStreamSynchronize(h->stream));
+        h->t = 0;
+        return LBMX_OK;
+    });
 }
 
 lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src)
@@ -494,7 +504,7 @@ lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src)
     lbmx_status s = check_handle(dst);
     if (s != LBMX_OK)
         return s;
-    s = check_handle(src);
+    s = check_usable(src);
     if (s != LBMX_OK)
         return s;
     if (src == dst)
@@ -502,28 +512,32 @@ lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src)
     s = check_same_device(src->ws, dst->ws, "cavities");
     if (s != LBMX_OK)
         return s;
-    dst->cur = 0;
-    s = init_from_state(view(dst), dst->p.storage, view(src), src->p.storage,
-                        dst->d.u_c / src->d.u_c);
-    if (s != LBMX_OK)
-        return s;
-    dst->t = 0;
-    return LBMX_OK;
+    return reinit(dst, [&]() -> lbmx_status {
+        dst->cur = 0;
+        lbmx_status r = init_from_state(view(dst), dst->p.storage, view(src), src->p.storage,
+                                        dst->d.u_c / src->d.u_c);
+        if (r == LBMX_OK)
+            dst->t = 0;
+        return r;
+    });
 }
 
 lbmx_status lbmx_step(lbmx_cavity *h, int64_t nsteps)
 {
-    lbmx_status s = check_handle(h);
+    lbmx_status s = check_usable(h);
     if (s != LBMX_OK)
         return s;
     if (nsteps < 0)
         return fail(LBMX_EINVAL, "nsteps must be >= 0");
-    return LBMX_DISPATCH(h->p.storage, launch_steps, h, nsteps);
+    s = LBMX_DISPATCH(h->p.storage, launch_steps, h, nsteps);
+    if (s != LBMX_OK)
+        h->failed = true;
+    return s;
 }
 
 lbmx_status lbmx_step_timed(lbmx_cavity *h, int64_t nsteps, double *ms)
 {
-    lbmx_status s = check_handle(h);
+    lbmx_status s = check_usable(h);
     if (s != LBMX_OK)
         return s;
     if (!ms || nsteps < 0)
@@ -543,8 +557,10 @@ lbmx_status lbmx_step_timed(lbmx_cavity *h, int64_t nsteps, double *ms)
         e = hipEventElapsedTime(&msf, a, b);
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
-    if (s != LBMX_OK)
+    if (s != LBMX_OK) {
+        h->failed = true;
         return s;
+    }
     if (e != hipSuccess)
         return fail(LBMX_EDEVICE, "event timing failed: %s", hipGetErrorString(e));
     *ms = msf;
@@ -568,22 +584,7 @@ lbmx_status lbmx_read_macro(lbmx_cavity *h, double *rho, double *ux, double *uy,
     lbmx_status s = check_handle(h);
     if (s != LBMX_OK)
         return s;
-    const size_t cells = (size_t)h->p.n * h->p.n * h->p.n;
-    double *host[5] = {rho, ux, uy, uz, theta};
-    DevBuf buf;
-    HIP_TRY(hipMalloc(&buf.p, 5 * cells * sizeof(double)));
-    double *dev[5];
-    for (int k = 0; k < 5; ++k)
-        dev[k] = host[k] ? reinterpret_cast<double *>(buf.p) + k * cells : nullptr;
-    s = LBMX_DISPATCH(h->p.storage, launch_macro, view(h), dev[0], dev[1], dev[2], dev[3], dev[4]);
-    if (s != LBMX_OK)
-        return s;
-    for (int k = 0; k < 5; ++k)
-        if (host[k])
-            HIP_TRY(hipMemcpyAsync(host[k], dev[k], cells * sizeof(double), hipMemcpyDeviceToHost,
-                                   h->stream));
-    HIP_TRY(hipStreamSynchronize(h->stream));
-    return LBMX_OK;
+    return LBMX_DISPATCH(h->p.storage, macro_to_host, view(h), rho, ux, uy, uz, theta);
 }
 
 lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host)
@@ -594,17 +595,17 @@ lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host)
     if (!out)
         return fail(LBMX_EINVAL, "out is NULL");
     const int n = h->p.n;
-    DevBuf mbuf;
-    if (map_host)
-        HIP_TRY(hipMalloc(&mbuf.p, (size_t)n * n * sizeof(double)));
-    s = LBMX_DISPATCH(h->p.storage, launch_nu, view(h), scratch(h), reinterpret_cast<double *>(mbuf.p));
+    const View v = view(h);
+    // the map is staged in the spare lattice (n^2 doubles)
+    double *map_dev = map_host ? reinterpret_cast<double *>(v.spare) : nullptr;
+    s = LBMX_DISPATCH(h->p.storage, launch_nu, v, scratch(h), map_dev);
     if (s != LBMX_OK)
         return s;
     double res[4];
     HIP_TRY(hipMemcpyAsync(res, scratch(h) + 4 * (size_t)n, sizeof(res), hipMemcpyDeviceToHost,
                            h->stream));
     if (map_host)
-        HIP_TRY(hipMemcpyAsync(map_host, mbuf.p, (size_t)n * n * sizeof(double),
+        HIP_TRY(hipMemcpyAsync(map_host, map_dev, (size_t)n * n * sizeof(double),
                                hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(hipStreamSynchronize(h->stream));
     out->nu3d = res[0];
@@ -612,16 +613,18 @@ lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host)
     out->numax = res[2];
     out->step = h->t;
     out->nonfinite = (int32_t)res[3];
-    if (out->nonfinite > 0 || !std::isfinite(res[0]))
+    if (out->nonfinite > 0 || !std::isfinite(res[0])) {
+        h->failed = true;
         return fail(LBMX_EUNSTABLE, "%d non-finite local Nu values at t = %lld", out->nonfinite,
                     (long long)h->t);
+    }
     return LBMX_OK;
 }
 
 lbmx_status lbmx_run_to_steady(lbmx_cavity *h, double tol, int64_t every, int64_t max_steps,
                                lbmx_nu *out)
 {
-    lbmx_status s = check_handle(h);
+    lbmx_status s = check_usable(h);
     if (s != LBMX_OK)
         return s;
     if (!out || !(tol > 0) || every < 1 || max_steps < 0)
@@ -658,7 +661,7 @@ lbmx_status lbmx_set_launch(lbmx_cavity *h, int32_t bx, int32_t by)
         return LBMX_OK;
     }
     if (bx < 1 || by < 1 || (long)bx * by > 1024)
-        return fail(LBMX_EINVAL, "launch (%d, %d) needs 1 <= bx*by <= 1024", bx, by);
+        return fail(LBMX_EINVAL, "launch (%d, %d) needs bx, by >= 1 and bx*by <= 1024", bx, by);
     h->bx = bx;
     h->by = by;
     return LBMX_OK;

@@ -75,21 +75,31 @@ def generate(seed=1511, count=64, out_n=64, storage="f32", tol=1e-6, every=1000,
     wall = time.perf_counter() - t0
     infos = [b.info(k) for k in range(count)]
     node_steps = sum(c["n"] ** 3 * i["t"] for c, i in zip(cases, infos))
-    fields = np.empty((count, 4, out_n, out_n, out_n), dtype=np.float32)
-    for k, c in enumerate(cases):
+    # Only steady fields are training targets: cavities that hit the step cap
+    # or diverged are left out (and listed).
+    keep = [k for k in range(count) if infos[k]["state"] == "converged"]
+    fields = np.empty((len(keep), 4, out_n, out_n, out_n), dtype=np.float32)
+    for j, k in enumerate(keep):
+        c = cases[k]
         f = b.resample(k, out_n)
         u_c = lbmx.derive(lbmx.make_params(n=c["n"], ra=c["ra"]))["u_c"]
-        fields[k, :3] = f[:3] / u_c
-        fields[k, 3] = f[3]
+        fields[j, :3] = f[:3] / u_c
+        fields[j, 3] = f[3]
+    if not np.isfinite(fields).all():
+        raise RuntimeError("non-finite values in the fields of converged cavities")
+    kept = [cases[k] for k in keep]
     out = {
-        "cases": cases,
+        "cases": kept,
         "fields": fields,
-        "log10_ra": np.array([np.log10(c["ra"]) for c in cases]),
-        "wall_type": np.array([c["wall_type"] for c in cases]),
-        "nu3d": np.array([i["nu3d"] for i in infos]),
-        "steps": np.array([i["t"] for i in infos]),
-        "state": [i["state"] for i in infos],
-        "summary": {"count": count, "converged": nconv, "wall_s": wall,
+        "log10_ra": np.array([np.log10(c["ra"]) for c in kept]),
+        "wall_type": np.array([c["wall_type"] for c in kept]),
+        "nu3d": np.array([infos[k]["nu3d"] for k in keep]),
+        "steps": np.array([infos[k]["t"] for k in keep]),
+        "dropped": [dict(cases[k], state=infos[k]["state"]) for k in range(count) if k not in keep],
+        "all_cases": cases,
+        "all_steps": np.array([i["t"] for i in infos]),
+        "all_nu3d": np.array([i["nu3d"] for i in infos]),
+        "summary": {"count": count, "converged": nconv, "kept": len(keep), "wall_s": wall,
                     "node_steps": node_steps, "mlups": node_steps / wall / 1e6,
                     "launch": list(b.get_launch()), "autotune_us_per_step": us,
                     "storage": storage, "tol": tol, "every": every, "max_steps": max_steps,
@@ -148,11 +158,13 @@ def main(argv=None):
     summ = dict(ds["summary"])
     if a.sequential:
         log("sequential baseline ...")
-        seq = sequential(ds["cases"], max_steps=a.max_steps)
+        seq = sequential(ds["all_cases"], max_steps=a.max_steps)
         summ["sequential_wall_s"] = seq["wall_s"]
         summ["speedup_vs_sequential"] = seq["wall_s"] / summ["wall_s"]
-        summ["max_nu_diff_vs_sequential"] = float(np.max(np.abs(np.array(seq["nu3d"]) - ds["nu3d"])))
-        summ["steps_equal_sequential"] = bool(np.array_equal(np.array(seq["steps"]), ds["steps"]))
+        summ["max_nu_diff_vs_sequential"] = float(np.max(np.abs(np.array(seq["nu3d"]) -
+                                                             ds["all_nu3d"])))
+        summ["steps_equal_sequential"] = bool(np.array_equal(np.array(seq["steps"]),
+                                                             ds["all_steps"]))
     print(json.dumps(summ), flush=True)
     return ds
 

@@ -35,6 +35,8 @@ def train_main(a):
                           tune_cache=a.tune_cache, log=log)
     t_data = time.perf_counter() - t0
     log(f"dataset: {ds['summary']}")
+    if len(ds["fields"]) == 0 or not np.isfinite(ds["fields"]).all():
+        raise RuntimeError("no usable steady fields to train on")
     net = unet.UNet(seed=a.net_seed, m=64)
     log(f"U-Net parameters: {net.nparams()}")
     res = unet.train(net, ds["fields"], ds["log10_ra"], ds["wall_type"], epochs=a.epochs,

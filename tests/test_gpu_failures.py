@@ -1,8 +1,11 @@
 """Failure handling on the GPU path, forced from the host: a step cap that is
 too small, and a cavity driven to blow up (buoyancy scaled by 1e5), whose
-non-finite values the Nu reduction must report (EUNSTABLE).  The kernels
-exit normally either way: NaN arithmetic does not change their control flow
-or addressing."""
+non-finite values the Nu reduction must report (EUNSTABLE) and which then
+refuses to step (ESTATE) until it is initialised again; launch-shape
+limits.  The kernels exit normally either way: NaN arithmetic does not
+change their control flow or addressing."""
+import os
+
 import numpy as np
 import pytest
 
@@ -59,3 +62,88 @@ def test_batch_retires_a_diverging_cavity():
     r = alone.run_to_steady(tol=1e-6, every=500, max_steps=200_000)
     assert r["converged"] and r["nu3d"] == i0["nu3d"] and r["step"] == i0["t"]
     b.close()
+
+
+def test_failed_cavity_refuses_to_step_until_reinitialised(tmp_path):
+    """A cavity whose Nu evaluation found non-finite values is failed: step,
+    step_timed, run_to_steady, save and serving as a source return ESTATE;
+    the reads still work; a checkpoint load or init_rest makes it usable
+    again and it then steps bitwise like a healthy cavity.  Two ways in: a
+    diverging run, and a NaN planted from the host in a wall-node population."""
+    print("case: ESTATE after divergence", flush=True)
+    th0 = inputs.theta_noise(16, SEED)
+    d = L.Cavity(n=16, wall_type=1, ra=1e4, storage="f32", buoyancy_scale=1e5, theta0=th0)
+    with pytest.raises(L.LbmxError) as e:
+        d.run_to_steady(tol=1e-6, every=50, max_steps=20_000)
+    assert e.value.status == 4
+    with pytest.raises(L.LbmxError) as e:
+        d.step(1)
+    assert e.value.status == 6  # LBMX_ESTATE
+    d.close()
+
+    print("case: ESTATE after a planted NaN", flush=True)
+    c = L.Cavity(n=16, wall_type=1, ra=1e4, storage="f32", theta0=th0)
+    c.step(50)
+    ckpt = str(tmp_path / "healthy.ckpt")
+    c.save(ckpt)
+    f, g = c.get_populations()
+    g[3, 3 + 16 * (0 + 16 * 5)] = np.nan  # node (3, 0, 5), next to the hot wall
+    c.set_populations(f, g, t=50)
+    with pytest.raises(L.LbmxError) as e:
+        c.nusselt()
+    assert e.value.status == 4
+    for call in (lambda: c.step(1), lambda: c.step_timed(1),
+                 lambda: c.run_to_steady(tol=1e-6, every=10, max_steps=10),
+                 lambda: c.save(str(tmp_path / "x.ckpt"))):
+        with pytest.raises(L.LbmxError) as e:
+            call()
+        assert e.value.status == 6
+    other = L.Cavity(n=16, wall_type=1, ra=1e4, storage="f32")
+    with pytest.raises(L.LbmxError) as e:
+        other.init_from(c)
+    assert e.value.status == 6
+    assert c.t == 50 and not os.path.exists(str(tmp_path / "x.ckpt"))
+    assert np.isnan(c.read_macro()[4]).sum() == 1  # the reads still work
+    assert c.nusselt(allow_unstable=True)["status"] == 4
+    # a checkpoint load makes it usable again
+    c.load(ckpt)
+    ref = L.Cavity(n=16, wall_type=1, ra=1e4, storage="f32")
+    ref.load(ckpt)
+    c.step(10)
+    ref.step(10)
+    assert c.t == ref.t == 60
+    fa, ga = c.get_populations()
+    fb, gb = ref.get_populations()
+    assert np.isfinite(fa).all() and np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    # and so does init_rest (after failing it again)
+    c.set_populations(f, g, t=50)
+    with pytest.raises(L.LbmxError):
+        c.nusselt()
+    c.init_rest(th0)
+    fresh = L.Cavity(n=16, wall_type=1, ra=1e4, storage="f32", theta0=th0)
+    c.step(20)
+    fresh.step(20)
+    assert c.t == 20
+    fa, ga = c.get_populations()
+    fb, gb = fresh.get_populations()
+    assert np.array_equal(fa, fb) and np.array_equal(ga, gb)
+    for x in (c, other, ref, fresh):
+        x.close()
+
+
+def test_launch_shape_limits():
+    """set_launch accepts any bx, by >= 1 with bx * by <= 1024 (results do not
+    depend on the shape) and rejects the rest without changing the shape."""
+    c = L.Cavity(n=8, wall_type=1, ra=1e4, storage="f32")
+    default = c.get_launch()
+    for bx, by in ((0, 5), (5, 0), (-1, 4), (33, 32), (1025, 1), (1, 1025)):
+        with pytest.raises(L.LbmxError) as e:
+            c.set_launch(bx, by)
+        assert e.value.status == 1 and c.get_launch() == default
+    for bx, by in ((1, 1), (5, 7), (32, 32), (1024, 1), (1, 1024)):
+        c.set_launch(bx, by)
+        assert c.get_launch() == (bx, by)
+        c.step(2)
+    c.set_launch(0, 0)
+    assert c.get_launch() == default
+    c.close()
