@@ -251,6 +251,20 @@ lbmx_status lbmx_read_macro(lbmx_cavity *h, double *rho, double *ux, double *uy,
  * local value is not finite, and the cavity is then failed (see above). */
 lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host);
 
+/* For callers that cannot allocate device memory, for instance code that
+ * runs between captured graph launches or a serving loop with a fixed
+ * memory budget: lbmx_nusselt without the cavity's workspace scratch.  The
+ * reduction's partial sums and results live in a static device array of the
+ * library (4 * 1024 + 8 doubles, 32.8 KB, one per GPU, held until the
+ * process ends); the map (if requested) is staged in the spare lattice as
+ * in lbmx_nusselt.  Allocates nothing.  The cavity must live on the current
+ * device.  Calls that overlap on one GPU (two host threads, or cavities on
+ * different streams with work in flight) share that array and race; calls
+ * that follow each other do not interfere: every call rewrites all the
+ * partial sums it reads.  Same results and errors as lbmx_nusselt, plus
+ * EINVAL for n > 1024 or a cavity on another device. */
+lbmx_status lbmx_nusselt_noalloc(lbmx_cavity *h, lbmx_nu *out, double *map_host);
+
 /* Step in chunks of `every` and stop once |Nu_3D(t) - Nu_3D(t - every)| < tol
  * (the paper gives no criterion; this is the criterion the library uses).
  * ENOTCONVERGED if max_steps pass first; EUNSTABLE on divergence.  *out holds

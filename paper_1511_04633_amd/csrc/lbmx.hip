@@ -13,6 +13,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -21,8 +22,23 @@
 using namespace lbmx;
 using namespace lbmx::host;
 
+// Reduction scratch of lbmx_nusselt_noalloc: the 4 per-row partial sums of
+// the hot-wall Nu reduction for up to kNoAllocMaxN rows, then the 4 results
+// (32.8 KB).  Every GPU the library runs on holds its own copy for the life
+// of the process.  In host code this name is not a device address: kernels
+// and copies get the address hipGetSymbolAddress returns for the current
+// device.
+constexpr int kNoAllocMaxN = 1024;
+constexpr size_t kScratchDoubles = 4 * size_t(kNoAllocMaxN) + 8;
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
 namespace {
 thread_local std::string g_last_error;
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+double *g_scratch_ptr[kMaxDevices];  // device address of `scratch`, per device
+
 }
 
 namespace lbmx {
@@ -63,7 +79,7 @@ namespace {
 
 char *lattice(lbmx_cavity *h, int k) { return h->ws + (size_t)k * h->L.lattice; }
 
-double *scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L.scratch_off); }
+double *nu_scratch(lbmx_cavity *h) { return reinterpret_cast<double *>(h->ws + h->L.scratch_off); }
 
 View view(lbmx_cavity *h)
 {
@@ -598,11 +614,11 @@ lbmx_status lbmx_nusselt(lbmx_cavity *h, lbmx_nu *out, double *map_host)
     const View v = view(h);
     // the map is staged in the spare lattice (n^2 doubles)
     double *map_dev = map_host ? reinterpret_cast<double *>(v.spare) : nullptr;
-    s = LBMX_DISPATCH(h->p.storage, launch_nu, v, scratch(h), map_dev);
+    s = LBMX_DISPATCH(h->p.storage, launch_nu, v, nu_scratch(h), map_dev);
     if (s != LBMX_OK)
         return s;
     double res[4];
-    HIP_TRY(hipMemcpyAsync(res, scratch(h) + 4 * (size_t)n, sizeof(res), hipMemcpyDeviceToHost,
+    HIP_TRY(hipMemcpyAsync(res, nu_scratch(h) + 4 * (size_t)n, sizeof(res), hipMemcpyDeviceToHost,
                            h->stream));
     if (map_host)
         HIP_TRY(hipMemcpyAsync(map_host, map_dev, (size_t)n * n * sizeof(double),
@@ -676,6 +692,57 @@ lbmx_status lbmx_get_launch(const lbmx_cavity *h, int32_t *bx, int32_t *by)
         return fail(LBMX_EINVAL, "NULL output");
     *bx = h->bx;
     *by = h->by;
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nusselt_noalloc(lbmx_cavity *h, lbmx_nu *out, double *map_host)
+{
+    lbmx_status s = check_handle(h);
+    if (s != LBMX_OK)
+        return s;
+    if (!out)
+        return fail(LBMX_EINVAL, "out is NULL");
+    const int n = h->p.n;
+    if (n > kNoAllocMaxN)
+        return fail(LBMX_EINVAL, "n = %d above the %d rows the static scratch holds", n, kNoAllocMaxN);
+    s = check_same_device(h->ws, h->ws, "cavity");
+    if (s != LBMX_OK)
+        return s;
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(LBMX_EDEVICE, "device %d beyond the %d the library tracks", dev, kMaxDevices);
+    double *scr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mutex);
+        if (!g_scratch_ptr[dev]) {
+            void *ptr = nullptr;
+            HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+            g_scratch_ptr[dev] = reinterpret_cast<double *>(ptr);
+        }
+        scr = g_scratch_ptr[dev];
+    }
+    const View v = view(h);
+    double *map_dev = map_host ? reinterpret_cast<double *>(v.spare) : nullptr;
+    s = LBMX_DISPATCH(h->p.storage, launch_nu, v, scr, map_dev);
+    if (s != LBMX_OK)
+        return s;
+    double res[4];
+    HIP_TRY(hipMemcpyAsync(res, scr + 4 * (size_t)n, sizeof(res), hipMemcpyDeviceToHost, h->stream));
+    if (map_host)
+        HIP_TRY(hipMemcpyAsync(map_host, map_dev, (size_t)n * n * sizeof(double),
+                               hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    out->nu3d = res[0];
+    out->nu2d = res[1];
+    out->numax = res[2];
+    out->step = h->t;
+    out->nonfinite = (int32_t)res[3];
+    if (out->nonfinite > 0 || !std::isfinite(res[0])) {
+        h->failed = true;
+        return fail(LBMX_EUNSTABLE, "%d non-finite local Nu values at t = %lld", out->nonfinite,
+                    (long long)h->t);
+    }
     return LBMX_OK;
 }
 

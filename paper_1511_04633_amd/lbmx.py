@@ -28,7 +28,8 @@ SYMBOLS = [
     "lbmx_create", "lbmx_destroy", "lbmx_init_rest", "lbmx_set_populations",
     "lbmx_get_populations", "lbmx_save", "lbmx_load", "lbmx_init_fields", "lbmx_init_from_cavity",
     "lbmx_step", "lbmx_step_timed", "lbmx_time",
-    "lbmx_read_macro", "lbmx_nusselt", "lbmx_run_to_steady", "lbmx_set_launch",
+    "lbmx_read_macro", "lbmx_nusselt", "lbmx_nusselt_noalloc", "lbmx_run_to_steady",
+    "lbmx_set_launch",
     "lbmx_get_launch", "lbmx_strerror", "lbmx_last_error",
     "lbmx_batch_create", "lbmx_batch_destroy", "lbmx_batch_init_rest", "lbmx_batch_init_from",
     "lbmx_batch_step",
@@ -111,6 +112,7 @@ def load() -> ctypes.CDLL:
         "lbmx_time": [_vp, ctypes.POINTER(i64)],
         "lbmx_read_macro": [_vp, _dp, _dp, _dp, _dp, _dp],
         "lbmx_nusselt": [_vp, ctypes.POINTER(lbmx_nu), _dp],
+        "lbmx_nusselt_noalloc": [_vp, ctypes.POINTER(lbmx_nu), _dp],
         "lbmx_run_to_steady": [_vp, ctypes.c_double, i64, i64, ctypes.POINTER(lbmx_nu)],
         "lbmx_set_launch": [_vp, i32, i32],
         "lbmx_get_launch": [_vp, ctypes.POINTER(i32), ctypes.POINTER(i32)],
