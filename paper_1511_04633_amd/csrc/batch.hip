@@ -50,7 +50,7 @@ struct lbmx_batch {
     size_t tiles_cap = 0;
     uint32_t ntiles = 0;
     int parity = 0;                // lattice index of every active cavity
-    uint64_t launches = 0;         // step launches so far (stochastic-rounding stream)
+    uint32_t *d_t = nullptr;       // per-cavity step counters, 2 x count (k_step_batch)
     int block = 256;               // threads per block = nodes per tile
     int grid = 0;                  // blocks; 0 = one per tile
     int graph_steps = 64;          // steps per captured graph; 0 = direct launches
@@ -149,26 +149,37 @@ lbmx_status launch_direct(lbmx_batch *b, int64_t nsteps)
     using T = typename St::T;
     const auto *cavs = reinterpret_cast<const BatchCav<T> *>(b->d_cavs);
     for (int64_t s = 0; s < nsteps; ++s) {
+        const uint32_t *t_in = b->d_t + (size_t)b->parity * b->count;
+        uint32_t *t_out = b->d_t + (size_t)(b->parity ^ 1) * b->count;
         switch (b->force_model) {
         case LBMX_FORCE_EQ15_RHO:
             hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_EQ15_RHO>), dim3(grid_blocks(b)),
                                dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity,
-                               uint32_t(b->launches + s));
+                               t_in, t_out);
             break;
         case LBMX_FORCE_GUO:
             hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_GUO>), dim3(grid_blocks(b)),
                                dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity,
-                               uint32_t(b->launches + s));
+                               t_in, t_out);
             break;
         default:
             hipLaunchKernelGGL((k_step_batch<St, LBMX_FORCE_EQ15>), dim3(grid_blocks(b)),
                                dim3(b->block), 0, b->stream, cavs, b->d_tiles, b->ntiles, b->parity,
-                               uint32_t(b->launches + s));
+                               t_in, t_out);
         }
         b->parity ^= 1;
     }
-    b->launches += uint64_t(nsteps);
     HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+// Cavity k restarts at step 0: its device step counter read by the next
+// launch (the batch's current parity) is cleared.
+lbmx_status reset_step(lbmx_batch *b, int k)
+{
+    static const uint32_t kZero = 0;
+    HIP_TRY(hipMemcpyAsync(b->d_t + (size_t)b->parity * b->count + k, &kZero, sizeof kZero,
+                           hipMemcpyHostToDevice, b->stream));
     return LBMX_OK;
 }
 
@@ -406,6 +417,13 @@ lbmx_status lbmx_batch_create(const lbmx_params *p, int32_t count, void *stream,
                     total, hipGetErrorString(e));
     }
     b->ws = reinterpret_cast<char *>(m);
+    e = hipMalloc(&b->d_t, 2 * sizeof(uint32_t) * count);
+    if (e == hipSuccess)
+        e = hipMemset(b->d_t, 0, 2 * sizeof(uint32_t) * count);
+    if (e != hipSuccess) {
+        lbmx_batch_destroy(b);
+        return fail(LBMX_EDEVICE, "step counters: %s", hipGetErrorString(e));
+    }
     lbmx_status s = LBMX_DISPATCH(b->storage, batch_upload_t, b);
     if (s == LBMX_OK)
         s = build_tiles(b);
@@ -435,6 +453,8 @@ void lbmx_batch_destroy(lbmx_batch *b)
         (void)hipFree(b->d_tiles);
     if (b->d_cavs)
         (void)hipFree(b->d_cavs);
+    if (b->d_t)
+        (void)hipFree(b->d_t);
     if (b->ws)
         (void)hipFree(b->ws);
     if (b->own_stream)
@@ -449,6 +469,9 @@ lbmx_status lbmx_batch_init_rest(lbmx_batch *b, int32_t k, const double *theta0_
         return s;
     // A re-initialised cavity rejoins the lockstep at the batch's parity.
     b->cur[k] = b->parity;
+    s = reset_step(b, k);
+    if (s != LBMX_OK)
+        return s;
     s = LBMX_DISPATCH(b->storage, rest_from_host, view_of(b, k), theta0_host);
     if (s != LBMX_OK)
         return s;
@@ -581,6 +604,9 @@ lbmx_status lbmx_batch_init_from(lbmx_batch *b, int32_t k, lbmx_batch *src, int3
         return s;
     // as lbmx_batch_init_rest: the cavity rejoins the lockstep at the batch's parity
     b->cur[k] = b->parity;
+    s = reset_step(b, k);
+    if (s != LBMX_OK)
+        return s;
     s = init_from_state(view_of(b, k), b->storage, view_of(src, ks), src->storage,
                         b->d[k].u_c / src->d[ks].u_c);
     if (s != LBMX_OK)
@@ -716,6 +742,9 @@ lbmx_status lbmx_batch_autotune(lbmx_batch *b, const char *cache_path, double *u
     // The timing steps advanced the cavities: put every cavity back at rest.
     for (int k = 0; k < b->count; ++k) {
         b->cur[k] = b->parity;
+        s = reset_step(b, k);
+        if (s != LBMX_OK)
+            return s;
         s = LBMX_DISPATCH(b->storage, unstream_rest, view_of(b, k), nullptr);
         if (s != LBMX_OK)
             return s;

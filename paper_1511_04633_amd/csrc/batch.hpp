@@ -44,15 +44,26 @@ __device__ __forceinline__ uint32_t div_small(uint32_t c, uint32_t n, float inv_
     return q;
 }
 
+// Each cavity's time step lives on the device, in two arrays used by turns:
+// a launch of parity p reads cavity k's step from t_in[k] (the stochastic-
+// rounding key of the fixed-point energy format, the same key a lone
+// cavity uses at that step) and the block that owns the cavity's first
+// tile writes step + 1 to t_out[k], which the next launch (parity 1 - p)
+// reads.  No launch writes what it reads, so a captured graph replays with
+// advancing steps.
 template <class St, int kForce>
 __global__ __launch_bounds__(1024) void k_step_batch(const BatchCav<typename St::T> *__restrict__ cavs,
                                                      const Tile *__restrict__ tiles, uint32_t ntiles,
-                                                     int parity, uint32_t step)
+                                                     int parity, const uint32_t *__restrict__ t_in,
+                                                     uint32_t *__restrict__ t_out)
 {
     using T = typename St::T;
     for (uint32_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
         const Tile tile = tiles[t];
         const BatchCav<T> *cv = cavs + tile.cav;
+        const uint32_t step = t_in[tile.cav];
+        if (tile.start == 0 && threadIdx.x == 0)
+            t_out[tile.cav] = step + 1u;
         const uint32_t c = tile.start + threadIdx.x;
         if (c >= cv->cells)
             continue;

@@ -74,19 +74,24 @@ def test_batch_bitwise_equals_single_cavity(storage):
             assert np.array_equal(gb[i], gs[i]), (k, i)
 
 
-def test_batch_fixed_point_energy_equals_single_cavity():
+@pytest.mark.parametrize("graph_steps", [0, 64])
+def test_batch_fixed_point_energy_equals_single_cavity(graph_steps):
     """FP16 flow + stochastically rounded fixed-point energy: the rounding
-    stream is keyed by node and launch count, which for a batch started at
-    step 0 and stepped by direct launches is the cavity's own step, so the
-    batch reproduces the lone cavities bit for bit.  (A captured graph
-    replays its launches' keys every graph_steps steps instead.)"""
-    print("case: batch vs single f16_i16, direct launches", flush=True)
-    b = make_batch(CASES, "f16_i16", graph_steps=0)
-    b.step(90)
+    stream is keyed by node and by the cavity's own step, which the batch
+    keeps per cavity on the device (advanced by the kernel itself, so graph
+    replays advance it too), so the batch reproduces the lone cavities bit
+    for bit, with direct launches and with captured graphs, also for a
+    cavity re-initialised while the others step on."""
+    print(f"case: batch vs single f16_i16, graph_steps {graph_steps}", flush=True)
+    b = make_batch(CASES, "f16_i16", graph_steps=graph_steps)
+    b.step(70)
+    b.init_rest(1, theta0(1, CASES[1]["n"]))  # cavity 1 restarts at step 0
+    b.step(131)  # graph replays plus a direct tail
     for k, c in enumerate(CASES):
         s = L.Cavity(n=c["n"], wall_type=c["wall_type"], ra=c["ra"], storage="f16_i16",
                      theta0=theta0(k, c["n"]))
-        s.step(90)
+        s.step(131 if k == 1 else 201)
+        assert b.info(k)["t"] == s.t
         gb, gs = b.read_macro(k), s.read_macro()
         for i in range(5):
             assert np.array_equal(gb[i], gs[i]), (k, i)
