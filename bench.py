@@ -17,6 +17,14 @@ time_to_steady: 128^3, Ra 1e5, FP32, wall types 1-3, wall time to |dNu_3D| <
 (warm start; inference and initialisation included), and by grid sequencing
 (the prediction run to steady on 64^3 first, that solve included).
 storage_sweep: every storage format at the same size and case (500 steps each).
+batch_to_steady: the 64-cavity batch (n uniform in {32, 48, 64, 80, 96}, Ra
+log-uniform in [1e3, 1e6], wall type uniform in {1, 2, 3}, seed 1511, FP32)
+run to steady in one persistent launch per step (autotuned launch shape,
+graph replay), wall time and aggregate MLUPS, and the same cases by grid
+sequencing (a half-size batch run to steady first).
+warm_start_192: a 192^3 cavity (Ra 3e5, Type 2, FP32) to steady from rest,
+from the U-Net's predicted fields, and from a 96^3 cavity started from them
+and run to steady (inference, coarse solve and initialisation timed).
 """
 from __future__ import annotations
 
@@ -107,6 +115,47 @@ def storage_sweep(n: int, wall_type: int, ra: float, steps: int = 500, warmup: i
     return out
 
 
+def batch_to_steady(coarse: bool):
+    """The 64-cavity batch to |dNu_3D| < 1e-6 per 1000 steps: wall time from
+    the first step to the last retirement (host clock), aggregate MLUPS
+    (sum over cavities of n^3 x steps / wall time), converged count and the
+    autotuned launch shape."""
+    from paper_1511_04633_amd import dataset
+
+    ds = dataset.generate(seed=1511, count=64, out_n=64, max_steps=300_000, coarse=coarse)
+    s = ds["summary"]
+    out = {"workload": "64 cavities, n in {32,48,64,80,96}, Ra log-uniform [1e3,1e6], "
+                       "types 1-3, seed 1511, f32",
+           "start": "half-size batch run to steady" if coarse else "rest",
+           "wall_s": round(s["wall_s"], 3), "mlups": round(s["mlups"], 1),
+           "node_steps": s["node_steps"], "converged": s["converged"], "count": s["count"],
+           "launch": s["launch"], "autotune_us_per_step": s["autotune_us_per_step"],
+           "max_steps_taken": int(max(ds["all_steps"]))}
+    if coarse and s.get("coarse"):
+        out["coarse_wall_s"] = round(s["coarse"]["wall_s"], 3)
+    return out
+
+
+def warm_start_192(net, ra: float = 3e5, wall_type: int = 2, n: int = 192, coarse: int = 96):
+    """The learned warm start at 192^3: rest start vs the network's fields vs grid sequencing
+    through a coarse^3 cavity started from them; all to |dNu_3D| < 1e-6 per
+    1000 steps, FP32, on this GPU."""
+    from paper_1511_04633_amd import warmstart
+
+    rest = warmstart.solve(n, ra, wall_type, None, max_steps=1_000_000)
+    warm = warmstart.solve(n, ra, wall_type, net, max_steps=1_000_000)
+    ml = warmstart.solve(n, ra, wall_type, net, coarse=coarse, max_steps=1_000_000)
+    rel = lambda r: abs(r["nu3d"] - rest["nu3d"]) / rest["nu3d"]
+    return {"workload": f"{n}^3 Type {wall_type} Ra {ra:g} f32",
+            "rest": {k: rest[k] for k in ("steps", "seconds", "converged", "nu3d")},
+            "warm_start": dict({k: warm[k] for k in ("steps", "seconds", "init_s", "converged",
+                                                      "nu3d")}, nu_rel_diff=rel(warm),
+                               time_ratio=round(warm["seconds"] / rest["seconds"], 3)),
+            "multilevel": dict({k: ml[k] for k in ("steps", "seconds", "init_s", "converged",
+                                                    "nu3d", "coarse")}, nu_rel_diff=rel(ml),
+                               time_ratio=round(ml["seconds"] / rest["seconds"], 3))}
+
+
 def counter_traffic(storage: str, n: int):
     """HBM bytes per step launch measured by rocprofv3 counters (profiles/traffic.json),
     or None when no measurement exists or the kernel sources changed since."""
@@ -171,6 +220,10 @@ def main():
                          "one halving of the 128^3 grid by default)")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the storage-format sweep at the benchmark size")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the 64-cavity batch run to steady")
+    ap.add_argument("--no-warm192", action="store_true",
+                    help="skip the 192^3 warm-start comparison")
     ap.add_argument("--force-model", type=int, default=0, choices=[0, 1, 2],
                     help="0 Eq. 15 (default), 1 Eq. 15 / rho, 2 Guo's forcing")
     ap.add_argument("--aniso", default="",
@@ -263,6 +316,16 @@ def main():
         line["time_to_steady"] = steady
     if not args.no_sweep and not variant:
         line["storage_sweep"] = storage_sweep(n, args.wall_type, args.ra)
+    if not args.no_batch:
+        print("bench: 64-cavity batch to steady", file=sys.stderr, flush=True)
+        line["batch_to_steady"] = [batch_to_steady(False), batch_to_steady(True)]
+    if not args.no_warm192:
+        print("bench: 192^3 warm start", file=sys.stderr, flush=True)
+        if net is None:
+            from paper_1511_04633_amd import warmstart
+            net = warmstart.load_net(os.path.join(ROOT, "paper_1511_04633_amd", "weights",
+                                                  "unet64.npz"))
+        line["warm_start_192"] = warm_start_192(net)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wall_type=args.wall_type, ra=args.ra)
         # the GPU on the oracle's sample, same size and precision class (FP64)

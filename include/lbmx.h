@@ -68,12 +68,14 @@ typedef enum {
  * from the lattice weights (Eq. 18), D3Q7 (energy) populations as g_i; in a
  * 16-bit format a population is stored divided by its weight (1/w_i, 1/w_T,i).
  * The mixed formats keep the flow lattice in 16 bits and the energy lattice
- * in FP32, or (LBMX_F16_I16) the energy populations as g_i / w_T,i in signed
- * 16-bit fixed point with 14 fraction bits (range +-2, saturating; the code
- * -32768 stands for NaN), rounded stochastically by the step (a
- * deterministic counter-based stream of node and step), so that increments
- * below one spacing are kept on average.  Bytes moved per node update: 416,
- * 208, 104, 104, 132, 132, 104. */
+ * in FP32, or (LBMX_F16_I16) the energy populations as g_i / (w_T,i Theta) in
+ * signed 16-bit fixed point with 15 fraction bits (range +-1, saturating; the
+ * code -32768 stands for NaN; Theta = the power of two at or above
+ * 2 max(|theta_hot|, |theta_cold|), 1 for walls at +-1/2), rounded
+ * stochastically by the step (a deterministic counter-based stream of node
+ * and step, 16 random bits per population), so that increments below one
+ * spacing are kept on average.  Bytes moved per node update: 416, 208, 104,
+ * 104, 132, 132, 104. */
 typedef enum {
     LBMX_F64 = 0,       /* flow FP64, energy FP64                      */
     LBMX_F32 = 1,       /* flow FP32, energy FP32                      */

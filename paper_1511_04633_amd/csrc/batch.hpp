@@ -75,7 +75,7 @@ __global__ __launch_bounds__(1024) void k_step_batch(const BatchCav<typename St:
         T f[19], g[7];
         pull<St, true>(cv->lat[parity], geo, x, y, int(z), f, g);
         collide<T, kForce>(f, g, cv->rates);
-        put<St, true>(cv->lat[parity ^ 1], c, step, f, g);
+        put<St, true>(cv->lat[parity ^ 1], c, step, f, g, geo.inv_escale);
     }
 }
 

@@ -270,6 +270,14 @@ inline View make_view(char *lat, char *spare, size_t spare_bytes, const lbmx_par
     return v;
 }
 
+// Theta of the fixed-point energy code: the power of two at or above
+// 2 max(|theta_hot|, |theta_cold|) (1 when both are 0).
+inline double energy_scale(double theta_hot, double theta_cold)
+{
+    const double m = 2.0 * std::max(std::fabs(theta_hot), std::fabs(theta_cold));
+    return m > 0.0 ? std::exp2(std::ceil(std::log2(m))) : 1.0;
+}
+
 template <class St>
 Geometry<typename St::T> geometry(const View &v)
 {
@@ -280,6 +288,9 @@ Geometry<typename St::T> geometry(const View &v)
     g.theta_hot = T(v.theta_hot);
     g.theta_cold = T(v.theta_cold);
     g.step = 0;
+    const double es = St::kScaledG ? energy_scale(v.theta_hot, v.theta_cold) : 1.0;
+    g.escale = T(es);
+    g.inv_escale = T(1.0 / es);
     return g;
 }
 

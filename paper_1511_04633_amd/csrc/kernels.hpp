@@ -95,17 +95,22 @@ __host__ __device__ constexpr int slab_shift_for(size_t flow_bytes)
     return flow_bytes >= 8 ? 10 : (flow_bytes == 4 ? 11 : 12);
 }
 
-// Fixed-point energy storage: g_i / w_T,i as a signed 16-bit integer in
-// units of 2^-14 (range +-2, uniform spacing 6.1e-5; FP16 spacing is 1.2e-4
-// to 2.4e-4 over the |g/w_T| = 0.25 .. 1 where the temperature signal lives).
+// Fixed-point energy storage: g_i / (w_T,i Theta) as a signed 16-bit integer
+// in units of 2^-15 (range +-1).  Theta is the power of two at or above
+// 2 max(|theta_hot|, |theta_cold|) (1 for the walls at +-1/2), so that
+// |g_i / w_T,i| = |theta (1 + 4 e_i.u)| + non-equilibrium part stays below
+// Theta; the spacing is then 3.1e-5 Theta, uniform (FP16's is 1.2e-4 to 2.4e-4
+// over the |g/w_T| = 0.25 .. 1 where the temperature signal lives).
 // The step kernels round stochastically (enc_r): up with probability equal to
 // the fraction below, so that a change smaller than one spacing per step is
 // kept on average instead of being rounded away every step (the slow thermal
-// drift would otherwise stall: with rounding to nearest this format's Nu
-// error at 64^3, Ra 1e6 was 4.3e-3, with stochastic rounding 1.5e-5).
-// Initialisation rounds to nearest (enc).
-// Finite values saturate at +-32767; -32768 encodes NaN, so that a diverging
-// run still reports non-finite values.
+// drift would otherwise stall: with rounding to nearest a 2^-14 code's Nu
+// error at 64^3, Ra 1e6 was 4.3e-3, with stochastic rounding 1.5e-5; 8
+// random bits instead of 16 left a 3.6e-4 bias at steady state).
+// Initialisation rounds to nearest (enc).  The weight arguments carry Theta
+// (w_T,i Theta to decode, 1/(w_T,i Theta) to encode; exact, Theta being a
+// power of two).  Finite values saturate at +-32767; -32768 encodes NaN, so
+// that a diverging run still reports non-finite values.
 struct Fix16 {
     short bits;
 };
@@ -116,7 +121,7 @@ struct Codec<Fix16> {
     template <typename T> static __device__ __forceinline__ T dec(Raw v, T w)
     {
         const short q = short(v);
-        return q == -32768 ? T(NAN) : T(q) * (w * T(1.0 / 16384.0));
+        return q == -32768 ? T(NAN) : T(q) * (w * T(1.0 / 32768.0));
     }
     static __device__ __forceinline__ Raw pack(float q)
     {
@@ -124,13 +129,18 @@ struct Codec<Fix16> {
     }
     template <typename T> static __device__ __forceinline__ Raw enc(T v, T inv_w)
     {
-        const float x = float(v * inv_w) * 16384.0f;
+        const float x = float(v * inv_w) * 32768.0f;
         return x == x ? pack(rintf(x)) : Raw(0x8000);
     }
-    // u16: 16 uniformly random bits, u = u16 / 2^16 in [0, 1)
+    // u16: 16 uniformly random bits, u = u16 / 2^16 in [0, 1).  Rounds up when
+    // u < x - floor(x), i.e. with probability frac(x) (to 2^-16).  Every
+    // operation here is exact (scaling by powers of two, floor, the
+    // difference of nearby floats), so the result does not depend on how the
+    // compiler contracts the arithmetic around it; floor(x + u) would round
+    // the sum to the spacing of x (2^-9 at |x| = 2^14) and bias the rounding.
     template <typename T> static __device__ __forceinline__ Raw enc_r(T v, T inv_w, uint32_t u16)
     {
-        const float x = float(v * inv_w) * 16384.0f;
+        const float x = float(v * inv_w) * 32768.0f;
         if (!(x == x))
             return Raw(0x8000);
         const float fl = floorf(x);
@@ -175,6 +185,8 @@ template <typename SF, typename SG>
 struct Store {
     using F = SF;
     using G = SG;
+    // the energy codec's weights carry the temperature scale Theta
+    static constexpr bool kScaledG = std::is_same<SG, Fix16>::value;
     static constexpr int kSlabShift = slab_shift_for(sizeof(SF));
     using T = typename std::conditional<std::is_same<SF, double>::value &&
                                             std::is_same<SG, double>::value,
@@ -219,6 +231,8 @@ struct Geometry {
     int wall_type;     // 1, 2, 3
     T theta_hot, theta_cold;
     uint32_t step;     // time step being written (stochastic-rounding stream)
+    T escale;          // Theta of the fixed-point energy code (1 otherwise)
+    T inv_escale;      // 1 / Theta (exact: Theta is a power of two)
 };
 
 // theta on a linear wall (Eqs. 9-10) at node height y: the crossing point of
@@ -320,9 +334,10 @@ __device__ __forceinline__ void pull(const char *__restrict__ src,
     const T th_lin = theta_linear(geo, y);
     const bool xd = x_wall_dirichlet(geo.wall_type);
     const bool zd = z_wall_dirichlet(geo.wall_type);
-    const T wg = T(w7(1));
+    const T es = St::kScaledG ? geo.escale : T(1);
+    const T wg = T(w7(1)) * es;
     auto ldg = [&](I e) { return Codec<SG>::dec(A::template ld<SG>(src, e), wg); };
-    g[0] = Codec<SG>::dec(A::template ld<SG>(src, Lt::g(idx, 0)), T(w7(0)));
+    g[0] = Codec<SG>::dec(A::template ld<SG>(src, Lt::g(idx, 0)), T(w7(0)) * es);
     {   // +x from x-1 | wall x = 0
         const T v = ldg(xl ? Lt::g(idx, 2) : Lt::g(idx - 1, 1));
         g[1] = xl ? (xd ? two_w * th_lin - v : v) : v;
@@ -352,7 +367,8 @@ __device__ __forceinline__ void pull(const char *__restrict__ src,
 // Write node c's 26 populations (post-collision values of step `step`).
 template <class St, bool kOff32>
 __device__ __forceinline__ void put(char *__restrict__ dst, size_t node, uint32_t step,
-                                    const typename St::T f[19], const typename St::T g[7])
+                                    const typename St::T f[19], const typename St::T g[7],
+                                    typename St::T inv_es)
 {
     using T = typename St::T;
     using SF = typename St::F;
@@ -368,7 +384,8 @@ __device__ __forceinline__ void put(char *__restrict__ dst, size_t node, uint32_
         const RoundBits rb(uint32_t(node), step);
 #pragma unroll
         for (int i = 0; i < 7; ++i)
-            A::template st<SG>(dst, Lt::g(c, i), Codec<SG>::enc_r(g[i], T(inv_w7(i)), rb.u16(i)));
+            A::template st<SG>(dst, Lt::g(c, i),
+                               Codec<SG>::enc_r(g[i], T(inv_w7(i)) * inv_es, rb.u16(i)));
     } else {
 #pragma unroll
         for (int i = 0; i < 7; ++i)
@@ -393,7 +410,8 @@ __global__ __launch_bounds__(1024) void k_step(const char *__restrict__ src, cha
     T f[19], g[7];
     pull<St, kOff32>(src, geo, x, y, z, f, g);
     collide<T, kForce>(f, g, rates);
-    put<St, kOff32>(dst, size_t(x) + size_t(geo.n) * (size_t(y) + size_t(geo.n) * z), geo.step, f, g);
+    put<St, kOff32>(dst, size_t(x) + size_t(geo.n) * (size_t(y) + size_t(geo.n) * z), geo.step, f, g,
+                    geo.inv_escale);
 }
 
 // --------------------------------------------------------- state sources
@@ -544,7 +562,8 @@ __global__ __launch_bounds__(256) void k_unstream(char *__restrict__ dst,
             // S_ibar = -P_i + 2 w theta_W (Dirichlet) or P_i (adiabatic)
             v = dir ? 2.0 * w7(go[i]) * tw - s_in : s_in;
         }
-        A::template st<SG>(dst, Lt::g(I(c), i), Codec<SG>::enc(T(v), T(inv_w7(i))));
+        const T inv_w = St::kScaledG ? T(inv_w7(i)) * geo.inv_escale : T(inv_w7(i));
+        A::template st<SG>(dst, Lt::g(I(c), i), Codec<SG>::enc(T(v), inv_w));
     }
 }
 

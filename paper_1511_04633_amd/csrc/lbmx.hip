@@ -168,7 +168,7 @@ lbmx_status reinit(lbmx_cavity *h, Fn fn)
 
 // Checkpoint file header (no padding: 8 + 4 + 4 + 336 + 3 x 8 bytes).
 constexpr char kCkptMagic[8] = {'L', 'B', 'M', 'X', 'C', 'K', 'P', 'T'};
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;  // 2: fixed-point energy in units of 2^-15 Theta
 constexpr size_t kCkptChunk = size_t(64) << 20;  // staging buffer bytes
 struct CkptHeader {
     char magic[8];

@@ -9,21 +9,24 @@
 //
 // Convolution = implicit GEMM on the matrix cores: out[p][co] =
 // sum_{tap, ci} W[co][tap][ci] in[p + off(tap)][ci] with M = co, N = voxels,
-// K = (tap, ci), one v_mfma_f32_16x16x16_bf16 per 16 input channels of a tap,
-// FP32 accumulation.  A wavefront owns 16 consecutive voxels and every output
-// channel; its operands are 8-byte vector loads (4 consecutive channels per
-// lane) straight from global memory, where the 27-fold re-read of a voxel
-// and the reuse of the weights by every wavefront are served by the caches.
-// MFMA operand layout (checked on the device): lane l holds A[l%16][4(l/16)+j]
-// and B[4(l/16)+j][l%16], j < 4, and gets D[4(l/16)+j][l%16].
-//
-// Backward: the data gradient is the same convolution of the output gradient
-// with the flipped, transposed weights (W'[ci][26-tap][co] = W[co][tap][ci]);
-// the weight gradient is a GEMM over voxels (K = voxels) for all 27 taps of a
-// brick of voxels at once, staged through LDS transposed to [channel][voxel]
-// so that every MFMA operand is one 8-byte LDS read, accumulated in FP32 and
-// added to the global gradient atomically (the bias gradient is one more
-// MFMA against ones).
+// K = (tap, ci), FP32 accumulation.  Both convolution kernels work on bricks
+// of 16 x 4 x 4 voxels staged in LDS, so that every MFMA operand is one
+// aligned LDS read and each staged element serves all 27 taps:
+//   - forward (and the data gradient, the same convolution of the output
+//     gradient with the flipped, transposed weights W'[ci][26-tap][co] =
+//     W[co][tap][ci]): a block stages its brick's input with a one-voxel halo
+//     and the weights of all taps per 16 input channels, channel-last, and
+//     runs v_mfma_f32_16x16x32_bf16 (gfx950), whose K = 32 covers two taps of
+//     the 16 channels; details at k_conv_fwd;
+//   - weight gradient: a block owns one (output-channel tile, input-channel
+//     tile) pair, walks the bricks, stages output gradient and input halo
+//     transposed to [channel][voxel], and accumulates all 27 taps with
+//     v_mfma_f32_16x16x16_bf16 (the bias gradient is one more MFMA against
+//     ones); the block's sums are added to the global gradient atomically;
+//     details at k_conv_wgrad.
+// MFMA operand layout (checked on the device): for the 16x16x16 form lane l
+// holds A[l%16][4(l/16)+j] and B[4(l/16)+j][l%16], j < 4, and gets
+// D[4(l/16)+j][l%16]; the 16x16x32 form holds 8 consecutive k per lane.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 

@@ -50,7 +50,8 @@ def sample_nodes(n, seed=7):
 
 
 # Stored mantissa bits of the flow and energy populations per storage format
-# (None: FP32 / FP64 storage; "fix": 16-bit fixed point in units of 2^-14).
+# (None: FP32 / FP64 storage; "fix": 16-bit fixed point in units of 2^-15 of
+# g / w_T (Theta = 1 for the walls at +-1/2)).
 FLOW_BITS = {"f64": None, "f32": None, "f16": 10, "bf16": 7, "f16_f32": 10, "bf16_f32": 7,
              "f16_i16": 10}
 ENERGY_BITS = {"f64": None, "f32": None, "f16": 10, "bf16": 7, "f16_f32": None,
@@ -63,11 +64,11 @@ def tolerance(bits, w, ref, fp_tol):
     storage rounding).  16-bit floating point: one ulp of the stored value
     ref / w - 1 (or ref / w), since the FP32 result may sit on the other side
     of a rounding boundary from the FP64 one, plus FP32 arithmetic.  Fixed
-    point with stochastic rounding: one spacing 2^-14 of g / w_T."""
+    point with stochastic rounding: one spacing 2^-15 of g / w_T."""
     if bits is None:
         return fp_tol
     if bits == "fix":
-        return w * 2.0 ** -14 + 1e-8
+        return w * 2.0 ** -15 + 1e-8
     return w * (2.0 ** -bits * np.abs(ref) + 2.0 ** -24) + 1e-8
 
 

@@ -205,10 +205,10 @@ def test_storage_codec_round_trip(storage, flow_fmt, energy_fmt):
     16-bit flow planes, g_i/w_T,i for 16-bit energy planes, f_i - w_i and g_i
     for FP32), the value first being rounded to FP32 (factor 1.001), with the
     FP16 subnormal spacing 2^-24 as the floor.  The 16-bit fixed-point energy
-    format (spacing 2^-14 of g_i/w_T,i) is off by at most half a spacing."""
+    format (spacing 2^-15 of g_i/w_T,i) is off by at most half a spacing."""
     print(f"case: codec round trip {storage}", flush=True)
     eps = {"f32": 2.0 ** -24, "f16": 2.0 ** -11, "bf16": 2.0 ** -8, "i16": 2.0 ** -24}
-    floor = {"f32": 1e-45, "f16": 2.0 ** -25, "bf16": 1e-38, "i16": 2.0 ** -15}
+    floor = {"f32": 1e-45, "f16": 2.0 ** -25, "bf16": 1e-38, "i16": 2.0 ** -16}
     n = 10
     ora = O.Oracle(n, 3, ra=1e5, theta0=inputs.theta_noise(n, SEED, amp=1e-2))
     ora.step(300)

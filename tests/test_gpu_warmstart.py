@@ -37,7 +37,7 @@ def test_prediction_is_physical(net):
     assert w[:, :8, :].mean() > 0 and w[:, -8:, :].mean() < 0
 
 
-@pytest.mark.parametrize("wall_type", [1, 3])
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
 def test_warm_start_needs_fewer_steps(net, wall_type):
     from paper_1511_04633_amd import warmstart
     print(f"case: warm vs rest n=96 Ra 3e5 type {wall_type}", flush=True)
