@@ -311,6 +311,7 @@ def main():
         from paper_1511_04633_amd import warmstart
         net = warmstart.load_net(os.path.join(ROOT, "paper_1511_04633_amd", "weights", "unet64.npz"))
     for wt in types:
+        print(f"bench: time to steady, 128^3 Type {wt}", file=sys.stderr, flush=True)
         steady.append(time_to_steady(wt, net, coarse=args.coarse))
     if steady:
         line["time_to_steady"] = steady
@@ -318,7 +319,9 @@ def main():
         line["storage_sweep"] = storage_sweep(n, args.wall_type, args.ra)
     if not args.no_batch:
         print("bench: 64-cavity batch to steady", file=sys.stderr, flush=True)
-        line["batch_to_steady"] = [batch_to_steady(False), batch_to_steady(True)]
+        line["batch_to_steady"] = [batch_to_steady(False)]
+        print("bench: 64-cavity batch by grid sequencing", file=sys.stderr, flush=True)
+        line["batch_to_steady"].append(batch_to_steady(True))
     if not args.no_warm192:
         print("bench: 192^3 warm start", file=sys.stderr, flush=True)
         if net is None:
@@ -327,6 +330,7 @@ def main():
                                                   "unet64.npz"))
         line["warm_start_192"] = warm_start_192(net)
     if not args.no_cpu_baseline:
+        print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wall_type=args.wall_type, ra=args.ra)
         # the GPU on the oracle's sample, same size and precision class (FP64)
         c64 = lbmx.Cavity(n=64, wall_type=args.wall_type, ra=args.ra, storage="f64",

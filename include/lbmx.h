@@ -60,7 +60,10 @@ typedef enum {
     LBMX_EUNSTABLE = 4,      /* non-finite values found (run diverged)       */
     LBMX_ENOTCONVERGED = 5,  /* run_to_steady hit max_steps                  */
     LBMX_ESTATE = 6,         /* call not valid in the handle's current state */
-    LBMX_EIO = 7             /* a checkpoint file could not be read/written  */
+    LBMX_EIO = 7,            /* a checkpoint file could not be read/written  */
+    LBMX_STATUS_RANGE_ = 0x7fffffff  /* not a status: makes every non-negative  */
+                                     /* 32-bit value a valid lbmx_status, so    */
+                                     /* lbmx_strerror accepts any code          */
 } lbmx_status;
 
 /* Population storage in HBM.  Collision arithmetic is FP64 for LBMX_F64 and
