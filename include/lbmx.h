@@ -384,6 +384,45 @@ lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias,
                                int32_t out_f32, int32_t B, int32_t D, int32_t H, int32_t W,
                                int32_t Ci, int32_t Co, void *stream);
 
+/* lbmx_nn_conv3d_fwd with a BF16 output (out, [B][D][H][W][Co] unless
+ * split) and fused epilogue options, each NULL / 0 when unused:
+ *   act:   also write a = silu(z) (BF16, [.][Co]) beside z = the convolution
+ *          plus bias in out: a forward layer without a separate SiLU pass;
+ *   gate:  BF16 [.][Co] pre-activations z' of the previous layer: out gets
+ *          bf16(bf16(conv) * silu'(z')) instead of the convolution, i.e. with
+ *          the flipped weights of lbmx_nn_conv3d_flip, that layer's gradient
+ *          dL/dz' without a separate SiLU-backward pass;
+ *   out2, split: output channels c >= split go to out2 ([.][Co - split],
+ *          channel c - split) and the others to out ([.][split]): the two
+ *          parts of the gradient of a concatenated input.
+ * act and gate exclude each other and out2; split is a multiple of 16 in
+ * (0, Co).  Results equal the separate kernels' bit for bit (same roundings
+ * to BF16 in the same order).  EINVAL otherwise, as lbmx_nn_conv3d_fwd. */
+lbmx_status lbmx_nn_conv3d_fwd_ep(const void *in, const void *w, const float *bias, void *out,
+                                  void *act, const void *gate, void *out2, int32_t split, int32_t B,
+                                  int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                                  void *stream);
+
+/* cat [B][2D][2H][2W][Ch + Cs] = [nearest x2 upsampling of h [B][D][H][W][Ch]
+ * | skip [B][2D][2H][2W][Cs]] in one pass (lbmx_nn_up2 then lbmx_nn_concat).
+ * Ch, Cs multiples of 16. */
+lbmx_status lbmx_nn_upcat(const void *h, const void *skip, void *cat, int32_t B, int32_t D, int32_t H,
+                          int32_t W, int32_t Ch, int32_t Cs, void *stream);
+
+/* Gradient through 2x2x2 average pooling with the optional extras of the
+ * U-Net's encoder outputs: gin [B][D][H][W][C] (even extents) =
+ * silu'(gate) * (bf16(gout[parent] / 8) + add), BF16 after each step as
+ * lbmx_nn_pool2 (backward), lbmx_nn_add and lbmx_nn_silu_bwd in sequence
+ * would round; add and gate may be NULL.  C a multiple of 16. */
+lbmx_status lbmx_nn_pool2_bwd_gate(const void *gout, const void *add, const void *gate, void *gin,
+                                   int32_t B, int32_t D, int32_t H, int32_t W, int32_t C, void *stream);
+
+/* Gradient through nearest x2 upsampling (sum over the 8 copies of each
+ * coarse voxel; gout on the 2D x 2H x 2W grid, gin on D x H x W) times the
+ * optional silu'(gate), BF16 after each step.  C a multiple of 16. */
+lbmx_status lbmx_nn_up2_bwd_gate(const void *gout, const void *gate, void *gin, int32_t B, int32_t D,
+                                 int32_t H, int32_t W, int32_t C, void *stream);
+
 /* wt[ci][26 - tap][co] = w[co][tap][ci]: with it, lbmx_nn_conv3d_fwd of an
  * output gradient (Co channels) gives the input gradient (Ci channels). */
 lbmx_status lbmx_nn_conv3d_flip(const void *w, void *wt, int32_t Ci, int32_t Co, void *stream);

@@ -46,6 +46,16 @@ using bf = unsigned short;  // BF16 bits
 __device__ __forceinline__ float bf2f(bf h) { return __uint_as_float(uint32_t(h) << 16); }
 __device__ __forceinline__ bf f2bf(float f) { return __bfloat16_as_ushort(__float2bfloat16(f)); }
 
+// SiLU a = z sigma(z) and its backward dz = da sigma(z) (1 + z (1 - sigma(z))),
+// shared by the elementwise kernels and the convolution epilogues so that the
+// fused and the separate paths compute the same expression.
+__device__ __forceinline__ float silu_f(float v) { return v / (1.f + __expf(-v)); }
+__device__ __forceinline__ float silu_grad_f(float ga, float v)
+{
+    const float sg = 1.f / (1.f + __expf(-v));
+    return ga * sg * (1.f + v * (1.f - sg));
+}
+
 struct Dims {
     int B, D, H, W;  // batch and spatial extent
     int Ci, Co;      // channels (multiples of 16)
@@ -88,12 +98,27 @@ constexpr int FC_THREADS = 256;                     // block size (the launcher'
 constexpr int FC_XITEMS = FC_HVOX * 2;              // 16-byte pieces of the input tile
 constexpr int FC_XITERS = (FC_XITEMS + FC_THREADS - 1) / FC_THREADS;
 
+// Epilogue options of a BF16 output (all null / 0 for the plain convolution):
+//   act:   also write a = silu(z) beside z = conv + bias (forward layers);
+//   gate:  write bf16(bf16(conv) * silu'(gate)) instead of the convolution:
+//          the data gradient of a layer times the SiLU derivative at the
+//          previous layer's pre-activation gate, i.e. that layer's dL/dz;
+//   out2, split: output channels >= split go to out2 (Co - split channels per
+//          voxel), the others to out (split per voxel): the two halves of a
+//          concatenated input's gradient.
+struct Epilogue {
+    bf *act;
+    const bf *gate;
+    bf *out2;
+    int split;
+};
+
 template <int NCO>
 __global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ in,
                                                          const bf *__restrict__ w,
                                                          const float *__restrict__ bias,
                                                          void *__restrict__ out, int out_f32, Dims d,
-                                                         int nbx, int nby, int nbz)
+                                                         int nbx, int nby, int nbz, Epilogue ep)
 {
     constexpr int WITEMS = 27 * NCO * 16 * 2;       // 16-byte pieces of the weight tile
     constexpr int WITERS = (WITEMS + FC_THREADS - 1) / FC_THREADS;
@@ -225,11 +250,29 @@ __global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ 
                 v += bj[j];
             if (out_f32) {
                 *reinterpret_cast<f4 *>(reinterpret_cast<float *>(out) + p * Co + cb) = v;
-            } else {
-                const uint2 pk = make_uint2(uint32_t(f2bf(v[0])) | (uint32_t(f2bf(v[1])) << 16),
-                                            uint32_t(f2bf(v[2])) | (uint32_t(f2bf(v[3])) << 16));
-                *reinterpret_cast<uint2 *>(reinterpret_cast<bf *>(out) + p * Co + cb) = pk;
+                continue;
             }
+            bf o[4] = {f2bf(v[0]), f2bf(v[1]), f2bf(v[2]), f2bf(v[3])};
+            if (ep.act) {
+                const uint2 pa = make_uint2(
+                    uint32_t(f2bf(silu_f(bf2f(o[0])))) | (uint32_t(f2bf(silu_f(bf2f(o[1])))) << 16),
+                    uint32_t(f2bf(silu_f(bf2f(o[2])))) | (uint32_t(f2bf(silu_f(bf2f(o[3])))) << 16));
+                *reinterpret_cast<uint2 *>(ep.act + p * Co + cb) = pa;
+            }
+            if (ep.gate) {
+                const uint2 zg = *reinterpret_cast<const uint2 *>(ep.gate + p * Co + cb);
+                const bf zz[4] = {bf(zg.x & 0xffffu), bf(zg.x >> 16), bf(zg.y & 0xffffu), bf(zg.y >> 16)};
+#pragma unroll
+                for (int k = 0; k < 4; ++k)
+                    o[k] = f2bf(silu_grad_f(bf2f(o[k]), bf2f(zz[k])));
+            }
+            const uint2 pk = make_uint2(uint32_t(o[0]) | (uint32_t(o[1]) << 16),
+                                        uint32_t(o[2]) | (uint32_t(o[3]) << 16));
+            if (ep.split > 0 && cb >= ep.split)
+                *reinterpret_cast<uint2 *>(ep.out2 + p * (Co - ep.split) + (cb - ep.split)) = pk;
+            else
+                *reinterpret_cast<uint2 *>(reinterpret_cast<bf *>(out) + p * (ep.split > 0 ? ep.split : Co) +
+                                           cb) = pk;
         }
     }
 }
@@ -411,20 +454,138 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
 __global__ __launch_bounds__(256) void k_silu_fwd(const bf *__restrict__ z, bf *__restrict__ a, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const float v = bf2f(z[i]);
-        a[i] = f2bf(v / (1.f + __expf(-v)));
-    }
+         i += (long long)gridDim.x * blockDim.x)
+        a[i] = f2bf(silu_f(bf2f(z[i])));
 }
 
 __global__ __launch_bounds__(256) void k_silu_bwd(const bf *__restrict__ z, const bf *__restrict__ ga,
                                                   bf *__restrict__ gz, long long n)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-         i += (long long)gridDim.x * blockDim.x) {
-        const float v = bf2f(z[i]);
-        const float s = 1.f / (1.f + __expf(-v));
-        gz[i] = f2bf(bf2f(ga[i]) * s * (1.f + v * (1.f - s)));
+         i += (long long)gridDim.x * blockDim.x)
+        gz[i] = f2bf(silu_grad_f(bf2f(ga[i]), bf2f(z[i])));
+}
+
+// The vector kernels below move 8 channels (16 bytes) per thread; every
+// channel count is a multiple of 16, so a vector never straddles a voxel or
+// a concatenation boundary.  Index arithmetic is 32-bit (the launchers check
+// the element counts).
+__device__ __forceinline__ void unpack8(const uint4 &v, float f[8])
+{
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        f[2 * k] = __uint_as_float(w[k] << 16);
+        f[2 * k + 1] = __uint_as_float(w[k] & 0xffff0000u);
+    }
+}
+__device__ __forceinline__ uint4 pack8(const float f[8])
+{
+    uint32_t w[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        w[k] = uint32_t(f2bf(f[2 * k])) | (uint32_t(f2bf(f[2 * k + 1])) << 16);
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
+// cat[p] = [up2(h)[p] (Ch channels) | skip[p] (Cs)] on the fine grid
+// (2D x 2H x 2W; h on D x H x W): nearest upsampling and concatenation in
+// one pass.
+__global__ __launch_bounds__(256) void k_upcat(const uint4 *__restrict__ h, const uint4 *__restrict__ skip,
+                                               uint4 *__restrict__ cat, int B, int D, int H, int W, int Ch8,
+                                               int Cs8)
+{
+    const int C8 = Ch8 + Cs8, Wo = 2 * W, Ho = 2 * H, Do = 2 * D;
+    const uint32_t n = uint32_t(B) * Do * Ho * Wo * C8;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const uint32_t c = i % C8, p = i / C8;
+        if (int(c) < Ch8) {
+            uint32_t r = p;
+            const uint32_t x = r % Wo; r /= Wo;
+            const uint32_t y = r % Ho; r /= Ho;
+            const uint32_t z = r % Do;
+            const uint32_t b = r / Do;
+            cat[i] = h[(((b * D + z / 2) * H + y / 2) * W + x / 2) * Ch8 + c];
+        } else {
+            cat[i] = skip[p * Cs8 + (c - Ch8)];
+        }
+    }
+}
+
+// Gradient through 2x2x2 average pooling, plus an optional second gradient
+// of the same tensor (add, the skip connection's), times the optional SiLU
+// derivative at z (gate): gin = silu'(z) * (bf16(gout[parent] / 8) + add),
+// rounded to BF16 after each step as the separate kernels round.
+__global__ __launch_bounds__(256) void k_pool2_bwd_gate(const uint4 *__restrict__ gout,
+                                                        const uint4 *__restrict__ add,
+                                                        const uint4 *__restrict__ gate,
+                                                        uint4 *__restrict__ gin, int B, int D, int H, int W,
+                                                        int C8)
+{
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const uint32_t n = uint32_t(B) * D * H * W * C8;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        uint32_t r = i;
+        const uint32_t c = r % C8; r /= C8;
+        const uint32_t x = r % W; r /= W;
+        const uint32_t y = r % H; r /= H;
+        const uint32_t z = r % D;
+        const uint32_t b = r / D;
+        float g[8], t[8];
+        unpack8(gout[(((b * Do + z / 2) * Ho + y / 2) * Wo + x / 2) * C8 + c], g);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+            g[k] = bf2f(f2bf(0.125f * g[k]));
+        if (add) {
+            unpack8(add[i], t);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                g[k] = bf2f(f2bf(g[k] + t[k]));
+        }
+        if (gate) {
+            unpack8(gate[i], t);
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                g[k] = silu_grad_f(g[k], t[k]);
+        }
+        gin[i] = pack8(g);
+    }
+}
+
+// Gradient through nearest x2 upsampling (the sum over the 8 copies), times
+// the optional SiLU derivative at z (gate), BF16 after each step.
+__global__ __launch_bounds__(256) void k_up2_bwd_gate(const uint4 *__restrict__ gout,
+                                                      const uint4 *__restrict__ gate,
+                                                      uint4 *__restrict__ gin, int B, int D, int H, int W,
+                                                      int C8)
+{
+    const int Do = 2 * D, Ho = 2 * H, Wo = 2 * W;
+    const uint32_t n = uint32_t(B) * D * H * W * C8;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        uint32_t r = i;
+        const uint32_t c = r % C8; r /= C8;
+        const uint32_t x = r % W; r /= W;
+        const uint32_t y = r % H; r /= H;
+        const uint32_t z = r % D;
+        const uint32_t b = r / D;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, t[8];
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t xo = 2 * x + (k & 1), yo = 2 * y + ((k >> 1) & 1), zo = 2 * z + (k >> 2);
+            unpack8(gout[(((b * Do + zo) * Ho + yo) * Wo + xo) * C8 + c], t);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                s[q] += t[q];
+        }
+        if (gate) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                s[q] = bf2f(f2bf(s[q]));
+            unpack8(gate[i], t);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                s[q] = silu_grad_f(s[q], t[q]);
+        }
+        gin[i] = pack8(s);
     }
 }
 
@@ -680,22 +841,19 @@ lbmx_status check_dims(int B, int D, int H, int W)
 }
 
 template <int NCO>
-void launch_fwd(const bf *in, const bf *w, const float *bias, void *out, int out_f32, Dims d, hipStream_t s)
+void launch_fwd(const bf *in, const bf *w, const float *bias, void *out, int out_f32, Dims d, hipStream_t s,
+                Epilogue ep)
 {
     const int nbx = (d.W + FC_X - 1) / FC_X, nby = (d.H + FC_Y - 1) / FC_Y, nbz = (d.D + FC_Z - 1) / FC_Z;
     const unsigned bricks = unsigned(d.B * nbx * nby * nbz);
     const unsigned groups = unsigned(d.Co / 16 / NCO);
     hipLaunchKernelGGL(k_conv_fwd<NCO>, dim3(bricks, groups), dim3(FC_THREADS), 0, s, in, w, bias, out,
-                       out_f32, d, nbx, nby, nbz);
+                       out_f32, d, nbx, nby, nbz, ep);
 }
 
-}  // namespace
-
-extern "C" {
-
-lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias, void *out,
-                               int32_t out_f32, int32_t B, int32_t D, int32_t H, int32_t W,
-                               int32_t Ci, int32_t Co, void *stream)
+lbmx_status conv_fwd(const void *in, const void *w, const float *bias, void *out, int32_t out_f32,
+                     int32_t B, int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co, void *stream,
+                     Epilogue ep)
 {
     lbmx_status st = check_dims(B, D, H, W);
     if (st != LBMX_OK)
@@ -707,6 +865,14 @@ lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias,
     if ((long long)B * D * H * W >= (1LL << 31))
         return fail(LBMX_EINVAL, "conv3d: %lld voxels exceed 32-bit voxel indices",
                     (long long)B * D * H * W);
+    if (out_f32 && (ep.act || ep.gate || ep.out2))
+        return fail(LBMX_EINVAL, "conv3d: epilogue options need a BF16 output");
+    if (ep.out2 && (ep.split <= 0 || ep.split >= Co || ep.split % 16 || ep.act || ep.gate))
+        return fail(LBMX_EINVAL, "conv3d: split must be a multiple of 16 in (0, Co), without act or gate");
+    if (ep.act && ep.gate)
+        return fail(LBMX_EINVAL, "conv3d: act and gate exclude each other");
+    if (!ep.out2)
+        ep.split = 0;
     const Dims d{B, D, H, W, Ci, Co};
     const bf *i = reinterpret_cast<const bf *>(in);
     const bf *wb = reinterpret_cast<const bf *>(w);
@@ -714,9 +880,85 @@ lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias,
     // two output channel tiles per block when Co/16 is even (weights of both
     // for all taps fit in LDS beside the input tile at two blocks per CU)
     if ((Co / 16) % 2 == 0)
-        launch_fwd<2>(i, wb, bias, out, out_f32, d, s);
+        launch_fwd<2>(i, wb, bias, out, out_f32, d, s, ep);
     else
-        launch_fwd<1>(i, wb, bias, out, out_f32, d, s);
+        launch_fwd<1>(i, wb, bias, out, out_f32, d, s, ep);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias, void *out,
+                               int32_t out_f32, int32_t B, int32_t D, int32_t H, int32_t W,
+                               int32_t Ci, int32_t Co, void *stream)
+{
+    return conv_fwd(in, w, bias, out, out_f32, B, D, H, W, Ci, Co, stream, Epilogue{});
+}
+
+lbmx_status lbmx_nn_conv3d_fwd_ep(const void *in, const void *w, const float *bias, void *out,
+                                  void *act, const void *gate, void *out2, int32_t split, int32_t B,
+                                  int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                                  void *stream)
+{
+    Epilogue ep{reinterpret_cast<bf *>(act), reinterpret_cast<const bf *>(gate),
+                reinterpret_cast<bf *>(out2), split};
+    return conv_fwd(in, w, bias, out, 0, B, D, H, W, Ci, Co, stream, ep);
+}
+
+lbmx_status lbmx_nn_upcat(const void *h, const void *skip, void *cat, int32_t B, int32_t D, int32_t H,
+                          int32_t W, int32_t Ch, int32_t Cs, void *stream)
+{
+    lbmx_status st = check_dims(B, D, H, W);
+    if (st != LBMX_OK)
+        return st;
+    if (!h || !skip || !cat || Ch < 16 || Ch % 16 || Cs < 16 || Cs % 16)
+        return fail(LBMX_EINVAL, "upcat: NULL tensor or channels not multiples of 16");
+    const long long n = 8LL * B * D * H * W * ((Ch + Cs) / 8);
+    if (n >= (1LL << 31))
+        return fail(LBMX_EINVAL, "upcat: %lld vectors exceed 32-bit indices", n);
+    hipLaunchKernelGGL(k_upcat, dim3(blocks_for(n)), dim3(256), 0, S(stream),
+                       reinterpret_cast<const uint4 *>(h), reinterpret_cast<const uint4 *>(skip),
+                       reinterpret_cast<uint4 *>(cat), B, D, H, W, Ch / 8, Cs / 8);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_pool2_bwd_gate(const void *gout, const void *add, const void *gate, void *gin,
+                                   int32_t B, int32_t D, int32_t H, int32_t W, int32_t C, void *stream)
+{
+    lbmx_status st = check_dims(B, D, H, W);
+    if (st != LBMX_OK)
+        return st;
+    if (!gout || !gin || C < 16 || C % 16 || D % 2 || H % 2 || W % 2)
+        return fail(LBMX_EINVAL, "pool2_bwd_gate: NULL tensor, channels or odd extent");
+    const long long n = (long long)B * D * H * W * (C / 8);
+    if (n >= (1LL << 31))
+        return fail(LBMX_EINVAL, "pool2_bwd_gate: %lld vectors exceed 32-bit indices", n);
+    hipLaunchKernelGGL(k_pool2_bwd_gate, dim3(blocks_for(n)), dim3(256), 0, S(stream),
+                       reinterpret_cast<const uint4 *>(gout), reinterpret_cast<const uint4 *>(add),
+                       reinterpret_cast<const uint4 *>(gate), reinterpret_cast<uint4 *>(gin), B, D, H, W,
+                       C / 8);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_up2_bwd_gate(const void *gout, const void *gate, void *gin, int32_t B, int32_t D,
+                                 int32_t H, int32_t W, int32_t C, void *stream)
+{
+    lbmx_status st = check_dims(B, D, H, W);
+    if (st != LBMX_OK)
+        return st;
+    if (!gout || !gin || C < 16 || C % 16)
+        return fail(LBMX_EINVAL, "up2_bwd_gate: NULL tensor or channels not a multiple of 16");
+    const long long n = 8LL * B * D * H * W * (C / 8);
+    if (n >= (1LL << 31))
+        return fail(LBMX_EINVAL, "up2_bwd_gate: %lld vectors exceed 32-bit indices", n);
+    hipLaunchKernelGGL(k_up2_bwd_gate, dim3(blocks_for(n / 8)), dim3(256), 0, S(stream),
+                       reinterpret_cast<const uint4 *>(gout), reinterpret_cast<const uint4 *>(gate),
+                       reinterpret_cast<uint4 *>(gin), B, D, H, W, C / 8);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }

@@ -52,6 +52,11 @@ def nn():
             "lbmx_nn_make_input": [_vp, _vp, _i32, _i32, _vp],
             "lbmx_nn_add": [_vp, _vp, _vp, _i64, _vp],
             "lbmx_nn_layout": [_vp, _vp, _i32, _i64, _i32, _i32, _i32, _vp, _vp],
+            "lbmx_nn_conv3d_fwd_ep": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32,
+                                      _i32, _i32, _i32, _vp],
+            "lbmx_nn_upcat": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_pool2_bwd_gate": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_up2_bwd_gate": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -147,15 +152,30 @@ class UNet:
         return torch.empty(shape, dtype=torch.bfloat16, device="cuda")
 
     # ---- forward -------------------------------------------------------------
+    # fused (default): the convolution kernels also apply SiLU (forward) and
+    # its derivative (data gradients), split concatenated gradients, and the
+    # decoder input is built by one upsample-and-concatenate pass; unfused:
+    # the separate elementwise kernels (kept to check the fused path against).
+    fused = True
+    # when a list, forward() and backward() append every convolution's GPU
+    # tensors (inputs, outputs, gradients) to it, for per-layer checks
+    record = None
+
     def _conv(self, conv, x, B, r, cache):
         """conv + SiLU on a [B, r, r, r, ci] BF16 tensor; returns the activation."""
         s = stream_ptr()
         z = self._bf(B, r, r, r, conv.co)
-        call("lbmx_nn_conv3d_fwd", P(x), P(conv.wb), P(conv.b), P(z), 0, B, r, r, r, conv.ci,
-             conv.co, s)
         a = self._bf(B, r, r, r, conv.co)
-        call("lbmx_nn_silu", P(z), P(a), z.numel(), s)
-        cache.append((conv, x, z, r))
+        if self.fused:
+            call("lbmx_nn_conv3d_fwd_ep", P(x), P(conv.wb), P(conv.b), P(z), P(a), None, None, 0,
+                 B, r, r, r, conv.ci, conv.co, s)
+        else:
+            call("lbmx_nn_conv3d_fwd", P(x), P(conv.wb), P(conv.b), P(z), 0, B, r, r, r, conv.ci,
+                 conv.co, s)
+            call("lbmx_nn_silu", P(z), P(a), z.numel(), s)
+        cache.append({"kind": "conv", "conv": conv, "x": x, "z": z, "r": r})
+        if self.record is not None:
+            self.record.append({"pass": "fwd", "conv": conv, "x": x, "z": z, "a": a, "r": r})
         return a
 
     def forward(self, cond, B, train=False):
@@ -178,18 +198,21 @@ class UNet:
                 skips.append((h, r))
                 p = self._bf(B, r // 2, r // 2, r // 2, cb.co)
                 call("lbmx_nn_pool2", P(h), P(p), B, r, r, r, cb.co, 0, s)
-                cache.append(("pool", h, p, r))
+                cache.append({"kind": "pool", "h": h, "r": r})
                 h = p
                 r //= 2
         for (ca, cb) in self.dec:
             sk, rs = skips.pop()
-            cu = h.shape[-1]
-            u = self._bf(B, 2 * r, 2 * r, 2 * r, cu)
-            call("lbmx_nn_up2", P(h), P(u), B, r, r, r, cu, 0, s)
+            cu, cs = h.shape[-1], sk.shape[-1]
+            cat = self._bf(B, 2 * r, 2 * r, 2 * r, cu + cs)
+            if self.fused:
+                call("lbmx_nn_upcat", P(h), P(sk), P(cat), B, r, r, r, cu, cs, s)
+            else:
+                u = self._bf(B, 2 * r, 2 * r, 2 * r, cu)
+                call("lbmx_nn_up2", P(h), P(u), B, r, r, r, cu, 0, s)
+                call("lbmx_nn_concat", P(u), P(sk), P(cat), B * (2 * r) ** 3, cu, cs, 0, s)
             r *= 2
-            cat = self._bf(B, r, r, r, cu + sk.shape[-1])
-            call("lbmx_nn_concat", P(u), P(sk), P(cat), B * r ** 3, cu, sk.shape[-1], 0, s)
-            cache.append(("upcat", h, sk, r, cu))
+            cache.append({"kind": "upcat", "r": r, "cu": cu, "cs": cs})
             h = self._conv(ca, cat, B, r, cache)
             h = self._conv(cb, h, B, r, cache)
         pred = torch.empty((B, m ** 3, 16), dtype=torch.float32, device="cuda")
@@ -199,6 +222,80 @@ class UNet:
         return pred
 
     # ---- backward ------------------------------------------------------------
+    def backward(self, gpred):
+        """gpred: BF16 [B, m^3, 16] gradient of the loss w.r.t. the predictions."""
+        if self.fused:
+            self._backward_fused(gpred)
+        else:
+            self._backward_unfused(gpred)
+        self._cache = None
+
+    def _backward_fused(self, gpred):
+        """Walks the layers backwards carrying dL/dz of the next convolution
+        to differentiate: every data gradient comes out of the convolution
+        kernel already multiplied by the SiLU derivative of the layer before
+        (or split into the upsampled and skip parts of a concatenated input),
+        the pooling and upsampling gradients fold in the skip gradient and
+        the SiLU derivative, and the first layer's data gradient (w.r.t. the
+        network input) is not computed."""
+        s = stream_ptr()
+        cache, hlast, B = self._cache
+        m = self.m
+        call("lbmx_nn_conv3d_wgrad", P(hlast), P(gpred), P(self.head.gw), P(self.head.gb), B, m,
+             m, m, self.head.ci, 16, s)
+        last = cache[-1]
+        g = self._bf(B, m, m, m, self.head.ci)
+        call("lbmx_nn_conv3d_fwd_ep", P(gpred), P(self.head.wflip), None, P(g), None, P(last["z"]),
+             None, 0, B, m, m, m, 16, self.head.ci, s)
+        skip_grads = []
+        for i in range(len(cache) - 1, -1, -1):
+            it = cache[i]
+            if it["kind"] == "conv":
+                conv, x, r = it["conv"], it["x"], it["r"]
+                call("lbmx_nn_conv3d_wgrad", P(x), P(g), P(conv.gw), P(conv.gb), B, r, r, r,
+                     conv.ci, conv.co, s)
+                rec = {"pass": "bwd", "conv": conv, "x": x, "gz": g, "r": r}
+                prev = cache[i - 1] if i > 0 else None
+                if prev is None:
+                    rec["dgrad"] = None
+                elif prev["kind"] == "conv":
+                    gn = self._bf(B, r, r, r, conv.ci)
+                    call("lbmx_nn_conv3d_fwd_ep", P(g), P(conv.wflip), None, P(gn), None,
+                         P(prev["z"]), None, 0, B, r, r, r, conv.co, conv.ci, s)
+                    rec["dgrad"], rec["gate"] = gn, prev["z"]
+                    g = gn
+                elif prev["kind"] == "pool":
+                    gn = self._bf(B, r, r, r, conv.ci)
+                    call("lbmx_nn_conv3d_fwd", P(g), P(conv.wflip), None, P(gn), 0, B, r, r, r,
+                         conv.co, conv.ci, s)
+                    rec["dgrad"] = gn
+                    g = gn
+                else:  # upcat: split the concatenated input's gradient
+                    cu, cs = prev["cu"], prev["cs"]
+                    gu = self._bf(B, r, r, r, cu)
+                    gs = self._bf(B, r, r, r, cs)
+                    call("lbmx_nn_conv3d_fwd_ep", P(g), P(conv.wflip), None, P(gu), None, None,
+                         P(gs), cu, B, r, r, r, conv.co, conv.ci, s)
+                    rec["dgrad"], rec["dgrad2"] = gu, gs
+                    skip_grads.append(gs)
+                    g = gu
+                if self.record is not None:
+                    self.record.append(rec)
+            elif it["kind"] == "pool":
+                h, r = it["h"], it["r"]
+                before = cache[i - 1]  # the convolution whose activation was pooled
+                gn = self._bf(B, r, r, r, h.shape[-1])
+                call("lbmx_nn_pool2_bwd_gate", P(g), P(skip_grads.pop()), P(before["z"]), P(gn),
+                     B, r, r, r, h.shape[-1], s)
+                g = gn
+            else:  # upcat
+                r, cu = it["r"], it["cu"]
+                before = cache[i - 1]  # the convolution whose activation was upsampled
+                gn = self._bf(B, r // 2, r // 2, r // 2, cu)
+                call("lbmx_nn_up2_bwd_gate", P(g), P(before["z"]), P(gn), B, r // 2, r // 2,
+                     r // 2, cu, s)
+                g = gn
+
     def _conv_bwd(self, conv, x, z, r, B, ga):
         s = stream_ptr()
         gz = self._bf(B, r, r, r, conv.co)
@@ -210,8 +307,7 @@ class UNet:
              conv.ci, s)
         return gx
 
-    def backward(self, gpred):
-        """gpred: BF16 [B, m^3, 16] gradient of the loss w.r.t. the predictions."""
+    def _backward_unfused(self, gpred):
         s = stream_ptr()
         cache, hlast, B = self._cache
         m = self.m
@@ -222,12 +318,10 @@ class UNet:
              self.head.ci, s)
         skip_grads = []   # gradients reaching the skip tensors, deepest first
         for item in reversed(cache):
-            if isinstance(item[0], Conv):
-                conv, x, z, r = item
-                g = self._conv_bwd(conv, x, z, r, B, g)
-            elif item[0] == "upcat":
-                _, hprev, sk, r, cu = item
-                cs = sk.shape[-1]
+            if item["kind"] == "conv":
+                g = self._conv_bwd(item["conv"], item["x"], item["z"], item["r"], B, g)
+            elif item["kind"] == "upcat":
+                r, cu, cs = item["r"], item["cu"], item["cs"]
                 gu = self._bf(B, r, r, r, cu)
                 gs = self._bf(B, r, r, r, cs)
                 call("lbmx_nn_concat", P(gu), P(gs), P(g), B * r ** 3, cu, cs, 1, s)
@@ -235,13 +329,12 @@ class UNet:
                 g = self._bf(B, r // 2, r // 2, r // 2, cu)
                 call("lbmx_nn_up2", P(gu), P(g), B, r // 2, r // 2, r // 2, cu, 1, s)
             else:  # pool
-                _, h, p, r = item
+                h, r = item["h"], item["r"]
                 gh = self._bf(B, r, r, r, h.shape[-1])
                 call("lbmx_nn_pool2", P(g), P(gh), B, r, r, r, h.shape[-1], 1, s)
                 gsk = skip_grads.pop()
                 call("lbmx_nn_add", P(gh), P(gsk), P(gh), gh.numel(), s)
                 g = gh
-        self._cache = None
 
     def adam(self, lr, wd=0.0):
         self.step_count += 1
@@ -358,3 +451,51 @@ def predict_fields(net, log10_ra, wall_type, u_c=1.0):
     call("lbmx_nn_layout", P(pred), P(out), 1, m ** 3, NOUT, 16, 0, P(sc), stream_ptr())
     torch.cuda.current_stream().synchronize()
     return out
+
+
+def bench_step(batch=4, m=64, steps=20, warmup=3, fused=True):
+    """Time one training step (forward, loss, backward, Adam) of the U-Net at
+    `batch` x m^3 on synthetic targets (seeded smooth fields); returns the
+    mean milliseconds per step (HIP events on torch's current stream)."""
+    import torch
+
+    net = UNet(seed=0, m=m)
+    net.fused = fused
+    V = m ** 3
+    ax = (np.arange(m) + 0.5) / m
+    zz, yy, xx = np.meshgrid(ax, ax, ax, indexing="ij")
+    fields = np.stack([np.sin(np.pi * yy) * np.cos(np.pi * zz), np.cos(np.pi * xx) * yy,
+                       np.sin(2 * np.pi * yy) * zz, 0.5 - yy], axis=-1).reshape(V, NOUT)
+    target = torch.tensor(np.broadcast_to(fields, (batch, V, NOUT)).astype(np.float32),
+                          device="cuda")
+    cond = cond_tensor(np.linspace(3.5, 5.5, batch), (np.arange(batch) % 3) + 1)
+    partial = torch.zeros(1024, dtype=torch.float64, device="cuda")
+
+    def one():
+        pred = net.forward(cond, batch, train=True)
+        grad, _ = mse_loss(pred, target, partial)
+        net.backward(grad)
+        net.adam(1e-4)
+
+    for _ in range(warmup):
+        one()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        one()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+if __name__ == "__main__":
+    import json
+    import sys
+
+    if "--bench-step" in sys.argv:
+        only = "--fused-only" in sys.argv
+        out = {"workload": "U-Net training step, batch 4, 64^3, BF16 MFMA",
+               "fused_ms": round(bench_step(fused=True), 4)}
+        if not only:
+            out["unfused_ms"] = round(bench_step(fused=False), 4)
+        print(json.dumps(out), flush=True)

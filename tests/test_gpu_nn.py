@@ -255,6 +255,221 @@ def test_silu_add_mse_adam_layout_input():
     assert np.all(xv[..., 7:] == 0)
 
 
+def ulp_bf(a):
+    """Spacing of BF16 at |a| (2^-7 relative to the power of two below)."""
+    a = np.abs(np.asarray(a, np.float64))
+    e = np.floor(np.log2(np.maximum(a, 2.0 ** -126)))
+    return 2.0 ** (e - 7)
+
+
+def bf_tensor(shape):
+    import torch
+    return torch.empty(shape, dtype=torch.bfloat16, device="cuda")
+
+
+@pytest.mark.parametrize("shape,ci,co", [((2, 6, 6, 6), 16, 32), ((1, 9, 10, 35), 48, 16),
+                                         ((1, 5, 4, 7), 32, 96)])
+def test_conv_epilogue_options(shape, ci, co):
+    """lbmx_nn_conv3d_fwd_ep: (act) z equals the plain convolution and a the
+    SiLU kernel applied to it; (gate) the output equals the convolution
+    followed by the SiLU-backward kernel; (split) the two outputs are the
+    plain output's channel ranges -- all bit for bit (same BF16 roundings in
+    the same order); and a, the gated output against the oracle on the
+    GPU's own z within one BF16 spacing."""
+    print(f"case: conv epilogue {shape} {ci}->{co}", flush=True)
+    B, D, H, W = shape
+    x, w, b = rnd((B, D, H, W, ci), 31), rnd((co, 27, ci), 32, 0.1), rnd((co,), 33)
+    zg = rnd((B, D, H, W, co), 34, 2.0)
+    tx, tw, tb, tzg = to_bf(x), to_bf(w), to_f32(b), to_bf(zg)
+    plain = bf_tensor((B, D, H, W, co))
+    call("lbmx_nn_conv3d_fwd", P(tx), P(tw), P(tb), P(plain), 0, B, D, H, W, ci, co, S())
+    n = plain.numel()
+    # act
+    z, a = bf_tensor(plain.shape), bf_tensor(plain.shape)
+    call("lbmx_nn_conv3d_fwd_ep", P(tx), P(tw), P(tb), P(z), P(a), None, None, 0, B, D, H, W, ci,
+         co, S())
+    a_sep = bf_tensor(plain.shape)
+    call("lbmx_nn_silu", P(plain), P(a_sep), n, S())
+    assert np.array_equal(bits_of(from_bf(z)), bits_of(from_bf(plain)))
+    assert np.array_equal(bits_of(from_bf(a)), bits_of(from_bf(a_sep)))
+    ref_a = N.silu(from_bf(z))
+    assert np.all(np.abs(from_bf(a) - ref_a) <= ulp_bf(ref_a) + 1e-30)
+    # gate
+    gated = bf_tensor(plain.shape)
+    call("lbmx_nn_conv3d_fwd_ep", P(tx), P(tw), P(tb), P(gated), None, P(tzg), None, 0, B, D, H,
+         W, ci, co, S())
+    g_sep = bf_tensor(plain.shape)
+    call("lbmx_nn_silu_bwd", P(tzg), P(plain), P(g_sep), n, S())
+    assert np.array_equal(bits_of(from_bf(gated)), bits_of(from_bf(g_sep)))
+    ref_g = N.silu_bwd(zg, from_bf(plain))
+    assert np.all(np.abs(from_bf(gated) - ref_g) <= ulp_bf(ref_g) + 1e-30)
+    # split
+    if co >= 32:
+        sp = 16
+        o1, o2 = bf_tensor((B, D, H, W, sp)), bf_tensor((B, D, H, W, co - sp))
+        call("lbmx_nn_conv3d_fwd_ep", P(tx), P(tw), P(tb), P(o1), None, None, P(o2), sp, B, D, H,
+             W, ci, co, S())
+        pv = from_bf(plain)
+        assert np.array_equal(from_bf(o1), pv[..., :sp]) and np.array_equal(from_bf(o2), pv[..., sp:])
+    # rejected combinations
+    from paper_1511_04633_amd import lbmx as LB
+    for args in ((P(a), P(tzg), None, 0), (None, None, P(a), 0), (None, None, P(a), 8),
+                 (P(a), None, P(a), 16)):
+        with pytest.raises(LB.LbmxError):
+            call("lbmx_nn_conv3d_fwd_ep", P(tx), P(tw), P(tb), P(z), *args, B, D, H, W, ci, co,
+                 S())
+
+
+def test_upcat_and_gated_gradients():
+    """lbmx_nn_upcat equals up2 + concat (and the oracle's definitions) bit
+    for bit; lbmx_nn_pool2_bwd_gate equals pool2 backward + add + SiLU
+    backward, lbmx_nn_up2_bwd_gate up2 backward + SiLU backward, bit for bit,
+    with and without the optional inputs; against the oracle within one BF16
+    spacing per rounding."""
+    import torch
+    print("case: upcat, gated pooling and upsampling gradients", flush=True)
+    B, D, H, W, Ch, Cs = 2, 3, 4, 5, 32, 16
+    h, sk = rnd((B, D, H, W, Ch), 41), rnd((B, 2 * D, 2 * H, 2 * W, Cs), 42)
+    th, tsk = to_bf(h), to_bf(sk)
+    cat = bf_tensor((B, 2 * D, 2 * H, 2 * W, Ch + Cs))
+    call("lbmx_nn_upcat", P(th), P(tsk), P(cat), B, D, H, W, Ch, Cs, S())
+    assert np.array_equal(from_bf(cat), np.concatenate([N.up2(h), sk], axis=-1))
+    # pooling gradient (fine grid 2D x 2H x 2W, coarse D x H x W), add and gate
+    C = 32
+    g = rnd((B, D, H, W, C), 43)
+    add, z = rnd((B, 2 * D, 2 * H, 2 * W, C), 44), rnd((B, 2 * D, 2 * H, 2 * W, C), 45, 2.0)
+    tg, tadd, tz = to_bf(g), to_bf(add), to_bf(z)
+    for use_add in (False, True):
+        for use_gate in (False, True):
+            fused = bf_tensor(add.shape)
+            call("lbmx_nn_pool2_bwd_gate", P(tg), P(tadd) if use_add else None,
+                 P(tz) if use_gate else None, P(fused), B, 2 * D, 2 * H, 2 * W, C, S())
+            sep = bf_tensor(add.shape)
+            call("lbmx_nn_pool2", P(tg), P(sep), B, 2 * D, 2 * H, 2 * W, C, 1, S())
+            ref = N.pool2_bwd(g)
+            if use_add:
+                call("lbmx_nn_add", P(sep), P(tadd), P(sep), sep.numel(), S())
+                ref = N.bf16_round(ref + add)
+            if use_gate:
+                s2 = bf_tensor(add.shape)
+                call("lbmx_nn_silu_bwd", P(tz), P(sep), P(s2), sep.numel(), S())
+                sep = s2
+                ref = N.silu_bwd(z, ref)
+            assert np.array_equal(bits_of(from_bf(fused)), bits_of(from_bf(sep))), (use_add, use_gate)
+            assert np.all(np.abs(from_bf(fused) - ref) <= 2 * ulp_bf(ref) + 1e-30)
+    # upsampling gradient and gate
+    gf = rnd((B, 2 * D, 2 * H, 2 * W, C), 46)
+    zc = rnd((B, D, H, W, C), 47, 2.0)
+    tgf, tzc = to_bf(gf), to_bf(zc)
+    for use_gate in (False, True):
+        fused = bf_tensor((B, D, H, W, C))
+        call("lbmx_nn_up2_bwd_gate", P(tgf), P(tzc) if use_gate else None, P(fused), B, D, H, W,
+             C, S())
+        sep = bf_tensor((B, D, H, W, C))
+        call("lbmx_nn_up2", P(tgf), P(sep), B, D, H, W, C, 1, S())
+        ref = N.up2_bwd(gf)
+        if use_gate:
+            s2 = bf_tensor((B, D, H, W, C))
+            call("lbmx_nn_silu_bwd", P(tzc), P(sep), P(s2), sep.numel(), S())
+            sep = s2
+            ref = N.silu_bwd(zc, N.bf16_round(ref))
+        assert np.array_equal(bits_of(from_bf(fused)), bits_of(from_bf(sep))), use_gate
+        assert np.all(np.abs(from_bf(fused) - ref) <= 2 * ulp_bf(ref) + 1e-6)
+
+
+def test_unet_layers_elementwise_against_oracle():
+    """Every layer of a training step (16^3, batch 2, fused kernels) replayed
+    in the oracle on the GPU's own BF16 inputs, element by element: forward
+    z = conv(x) + b and a = silu(z); weight and bias gradients from the
+    GPU's x and dL/dz; data gradients (times the previous layer's SiLU
+    derivative where fused, split where the input was a concatenation).
+    Bounds: FP32 accumulation, 2e-5 of the same sum of absolute terms, plus
+    one BF16 spacing per rounding to BF16."""
+    import torch
+    from paper_1511_04633_amd import unet
+
+    print("case: unet per-layer replay 16^3 batch 2", flush=True)
+    m, B = 16, 2
+    net = unet.UNet(seed=3, m=m)
+    net.record = []
+    cond = to_f32(np.array([[0.3, 1.0], [-0.6, 3.0]]))
+    target = to_f32(np.random.default_rng(21).standard_normal((B, m ** 3, 4)) * 0.5)
+    pred = net.forward(cond, B, train=True)
+    part = torch.zeros(1024, dtype=torch.float64, device="cuda")
+    grad, cnt = unet.mse_loss(pred, target, part)
+    net.backward(grad)
+    torch.cuda.synchronize()
+    W = {id(c): N.bf16_round(c.w.cpu().numpy()) for c in net.convs()}
+    Bv = {id(c): c.b.cpu().numpy().astype(np.float64) for c in net.convs()}
+    nf = nb = 0
+    for rec in net.record:
+        c = rec["conv"]
+        x = from_bf(rec["x"])
+        w = W[id(c)]
+        if rec["pass"] == "fwd":
+            ref = N.conv3d(x, w, Bv[id(c)])
+            bnd = 2e-5 * N.conv3d(np.abs(x), np.abs(w), np.abs(Bv[id(c)])) + 1e-6 + ulp_bf(ref)
+            z = from_bf(rec["z"])
+            assert np.all(np.abs(z - ref) <= bnd), (c.ci, c.co, (np.abs(z - ref) / bnd).max())
+            ra = N.silu(z)
+            assert np.all(np.abs(from_bf(rec["a"]) - ra) <= ulp_bf(ra) + 1e-30)
+            nf += 1
+            continue
+        gz = from_bf(rec["gz"])
+        gw_ref, gb_ref = N.conv3d_wgrad(x, gz)
+        bw, bb = N.conv3d_wgrad(np.abs(x), np.abs(gz))
+        gw, gb = c.gw.cpu().numpy(), c.gb.cpu().numpy()
+        assert np.all(np.abs(gw - gw_ref) <= 2e-5 * bw + 1e-6), (c.ci, c.co, "gw")
+        assert np.all(np.abs(gb - gb_ref) <= 2e-5 * bb + 1e-6), (c.ci, c.co, "gb")
+        nb += 1
+        if rec["dgrad"] is None:
+            continue  # the first layer: no gradient w.r.t. the network input
+        d = N.conv3d_dgrad(gz, w)
+        bd = 2e-5 * N.conv3d_dgrad(np.abs(gz), np.abs(w)) + 1e-6
+        if "gate" in rec:
+            zp = from_bf(rec["gate"])
+            ref = N.silu_bwd(zp, N.bf16_round(d))
+            dmax = 1.1 * (bd + ulp_bf(d))  # |silu'| < 1.1
+            got = from_bf(rec["dgrad"])
+            assert np.all(np.abs(got - ref) <= dmax + ulp_bf(ref)), (c.ci, c.co, "gated")
+        else:
+            got = from_bf(rec["dgrad"])
+            if "dgrad2" in rec:
+                got = np.concatenate([got, from_bf(rec["dgrad2"])], axis=-1)
+            assert np.all(np.abs(got - d) <= bd + ulp_bf(d)), (c.ci, c.co, "dgrad")
+    assert nf == 14 and nb == 14
+
+
+def test_unet_fused_matches_unfused():
+    """The fused training step (epilogues, upsample-and-concatenate, gated
+    pooling and upsampling gradients) against the separate kernels: the same
+    prediction bit for bit, and the same weight gradients up to the order of
+    the FP32 atomic additions."""
+    import torch
+    from paper_1511_04633_amd import unet
+
+    print("case: unet fused vs unfused 16^3 batch 2", flush=True)
+    m, B = 16, 2
+    cond = to_f32(np.array([[0.1, 2.0], [0.8, 1.0]]))
+    target = to_f32(np.random.default_rng(5).standard_normal((B, m ** 3, 4)) * 0.5)
+    out = []
+    for fused in (True, False):
+        net = unet.UNet(seed=7, m=m)
+        net.fused = fused
+        pred = net.forward(cond, B, train=True)
+        part = torch.zeros(1024, dtype=torch.float64, device="cuda")
+        grad, _ = unet.mse_loss(pred, target, part)
+        net.backward(grad)
+        torch.cuda.synchronize()
+        out.append((pred.cpu().numpy(), [(c.gw.cpu().numpy(), c.gb.cpu().numpy())
+                                          for c in net.convs()]))
+    assert np.array_equal(out[0][0], out[1][0])
+    for (gw1, gb1), (gw2, gb2) in zip(out[0][1], out[1][1]):
+        sc = np.abs(gw2).max() + 1e-30
+        assert np.abs(gw1 - gw2).max() <= 1e-4 * sc
+        assert np.abs(gb1 - gb2).max() <= 1e-4 * (np.abs(gb2).max() + 1e-30)
+
+
 def _oracle_unet_grads(net, cond_np, target, m):
     """The same network evaluated with the oracle in FP64, rounding to BF16
     wherever the GPU stores BF16; returns the loss and weight gradients."""
