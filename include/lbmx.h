@@ -427,6 +427,12 @@ lbmx_status lbmx_nn_up2_bwd_gate(const void *gout, const void *gate, void *gin, 
  * output gradient (Co channels) gives the input gradient (Ci channels). */
 lbmx_status lbmx_nn_conv3d_flip(const void *w, void *wt, int32_t Ci, int32_t Co, void *stream);
 
+/* lbmx_nn_conv3d_flip for `count` (<= 32) layers in one launch: layer l's
+ * weights [co[l]][27][ci[l]] start at element offsets[l] of w and its
+ * flipped copy at the same offset of wt (offsets, ci, co: host arrays). */
+lbmx_status lbmx_nn_conv3d_flip_many(const void *w, void *wt, int32_t count, const int64_t *offsets,
+                                     const int32_t *ci, const int32_t *co, void *stream);
+
 /* gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci] and, if gb is
  * not NULL, gb[co] += sum_p gout[p][co] (FP32, accumulated atomically, so
  * the summation order varies between runs).  16 <= Ci, Co <= 1024,

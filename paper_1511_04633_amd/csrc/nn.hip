@@ -290,6 +290,30 @@ __global__ __launch_bounds__(256) void k_conv_flip(const bf *__restrict__ w, bf 
     wt[((long long)ci * 27 + (26 - tap)) * Co + co] = w[i];
 }
 
+// The flips of many layers in one launch: blockIdx.y selects the layer,
+// whose weights start at w + off[l] and whose flipped copy at wt + off[l].
+constexpr int FLIP_MAX = 32;
+struct FlipSet {
+    int count;
+    long long off[FLIP_MAX];
+    int ci[FLIP_MAX], co[FLIP_MAX];
+};
+
+__global__ __launch_bounds__(256) void k_conv_flip_many(const bf *__restrict__ w, bf *__restrict__ wt,
+                                                        FlipSet fs)
+{
+    const int l = blockIdx.y;
+    const int Ci = fs.ci[l], Co = fs.co[l];
+    const long long n = (long long)Co * 27 * Ci;
+    const bf *wl = w + fs.off[l];
+    bf *tl = wt + fs.off[l];
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int ci = int(i % Ci), tap = int((i / Ci) % 27), co = int(i / (27LL * Ci));
+        tl[((long long)ci * 27 + (26 - tap)) * Co + co] = wl[i];
+    }
+}
+
 // gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci], gb[co] += sum_p gout[p][co].
 //
 // A block owns one (co tile, ci tile) pair (blockIdx.y) and walks bricks of
@@ -629,6 +653,35 @@ __global__ __launch_bounds__(256) void k_pool2_bwd(const bf *__restrict__ gout, 
     }
 }
 
+// 2x2x2 average pooling, 8 channels (16 bytes) per thread; the same sums in
+// the same order as k_pool2_fwd.
+__global__ __launch_bounds__(256) void k_pool2_fwd8(const uint4 *__restrict__ in, uint4 *__restrict__ out,
+                                                    int B, int D, int H, int W, int C8)
+{
+    const int Do = D / 2, Ho = H / 2, Wo = W / 2;
+    const uint32_t n = uint32_t(B) * Do * Ho * Wo * C8;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        uint32_t r = i;
+        const uint32_t c = r % C8; r /= C8;
+        const uint32_t x = r % Wo; r /= Wo;
+        const uint32_t y = r % Ho; r /= Ho;
+        const uint32_t z = r % Do;
+        const uint32_t b = r / Do;
+        float s[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, t[8];
+        for (int k = 0; k < 8; ++k) {
+            const uint32_t xi = 2 * x + (k & 1), yi = 2 * y + ((k >> 1) & 1), zi = 2 * z + (k >> 2);
+            unpack8(in[(((b * D + zi) * H + yi) * W + xi) * C8 + c], t);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                s[q] += t[q];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            s[q] *= 0.125f;
+        out[i] = pack8(s);
+    }
+}
+
 // Nearest-neighbour x2 upsampling (out is 2D x 2H x 2W) and its gradient.
 __global__ __launch_bounds__(256) void k_up2_fwd(const bf *__restrict__ in, bf *__restrict__ out, int B,
                                                  int D, int H, int W, int C)
@@ -732,6 +785,40 @@ __global__ __launch_bounds__(256) void k_mse(const float *__restrict__ pred, con
         partial[blockIdx.x] = red[0];
 }
 
+// The same loss and gradient, one voxel per thread for C % 8 == 0 and
+// K <= 8: only the K predicted channels are read, and the gradient row is
+// written 8 channels (16 bytes) at a time.
+__global__ __launch_bounds__(256) void k_mse_v(const float *__restrict__ pred, const float *__restrict__ target,
+                                               uint4 *__restrict__ grad, double *__restrict__ partial,
+                                               long long nv, int C, int K, float scale)
+{
+    __shared__ double red[256];
+    double s = 0.0;
+    const int C8 = C / 8;
+    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < nv;
+         p += (long long)gridDim.x * blockDim.x) {
+        float g[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < K; ++c) {
+            const float e = pred[p * C + c] - target[p * K + c];
+            s += double(e) * e;
+            g[c] = 2.f * e * scale;
+        }
+        grad[p * C8] = pack8(g);
+        const uint4 zero = make_uint4(0, 0, 0, 0);
+        for (int c8 = 1; c8 < C8; ++c8)
+            grad[p * C8 + c8] = zero;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o)
+            red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+        partial[blockIdx.x] = red[0];
+}
+
 // Adam with decoupled weight decay on FP32 master weights; refreshes the
 // BF16 copy (nullable) and clears the gradient.
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, float *__restrict__ g,
@@ -784,8 +871,9 @@ __global__ __launch_bounds__(256) void k_make_input(const float *__restrict__ co
         ch[4] = (2.f * x + 1.f) / m - 1.f;
         ch[5] = (2.f * y + 1.f) / m - 1.f;
         ch[6] = (2.f * z + 1.f) / m - 1.f;
-        for (int c = 0; c < 16; ++c)
-            out[p * 16 + c] = f2bf(ch[c]);
+        uint4 *o = reinterpret_cast<uint4 *>(out + p * 16);  // 32 bytes per voxel
+        o[0] = pack8(ch);
+        o[1] = pack8(ch + 8);
     }
 }
 
@@ -974,6 +1062,28 @@ lbmx_status lbmx_nn_conv3d_flip(const void *w, void *wt, int32_t Ci, int32_t Co,
     return LBMX_OK;
 }
 
+lbmx_status lbmx_nn_conv3d_flip_many(const void *w, void *wt, int32_t count, const int64_t *offsets,
+                                     const int32_t *ci, const int32_t *co, void *stream)
+{
+    if (!w || !wt || !offsets || !ci || !co || count < 1 || count > FLIP_MAX)
+        return fail(LBMX_EINVAL, "conv3d_flip_many: bad arguments (1 <= count <= %d)", FLIP_MAX);
+    FlipSet fs;
+    fs.count = count;
+    long long most = 0;
+    for (int l = 0; l < count; ++l) {
+        if (ci[l] < 1 || co[l] < 1 || offsets[l] < 0)
+            return fail(LBMX_EINVAL, "conv3d_flip_many: layer %d has bad shape or offset", l);
+        fs.off[l] = offsets[l];
+        fs.ci[l] = ci[l];
+        fs.co[l] = co[l];
+        most = std::max(most, (long long)co[l] * 27 * ci[l]);
+    }
+    hipLaunchKernelGGL(k_conv_flip_many, dim3(blocks_for(most), unsigned(count)), dim3(256), 0, S(stream),
+                       reinterpret_cast<const bf *>(w), reinterpret_cast<bf *>(wt), fs);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
 lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, float *gb, int32_t B,
                                  int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co, void *stream)
 {
@@ -1036,6 +1146,10 @@ lbmx_status lbmx_nn_pool2(const void *in, void *out, int32_t B, int32_t D, int32
     if (backward)  // in = gradient of the pooled tensor, out = gradient of the input
         hipLaunchKernelGGL(k_pool2_bwd, dim3(blocks_for(n)), dim3(256), 0, S(stream),
                            reinterpret_cast<const bf *>(in), reinterpret_cast<bf *>(out), B, D, H, W, C);
+    else if (C % 8 == 0 && n < (1LL << 31))
+        hipLaunchKernelGGL(k_pool2_fwd8, dim3(blocks_for(n / 64)), dim3(256), 0, S(stream),
+                           reinterpret_cast<const uint4 *>(in), reinterpret_cast<uint4 *>(out), B, D, H, W,
+                           C / 8);
     else
         hipLaunchKernelGGL(k_pool2_fwd, dim3(blocks_for(n / 8)), dim3(256), 0, S(stream),
                            reinterpret_cast<const bf *>(in), reinterpret_cast<bf *>(out), B, D, H, W, C);
@@ -1086,8 +1200,12 @@ lbmx_status lbmx_nn_mse(const float *pred, const float *target, void *grad, doub
     if (!pred || !target || !grad || !partial || npartial < 1 || npartial > 4096 || K < 1 || K > C)
         return fail(LBMX_EINVAL, "mse: bad arguments");
     const float scale = 1.0f / float(double(nvox) * K);
-    hipLaunchKernelGGL(k_mse, dim3(npartial), dim3(256), 0, S(stream), pred, target,
-                       reinterpret_cast<bf *>(grad), partial, (long long)nvox, C, K, scale);
+    if (C % 8 == 0 && K <= 8)
+        hipLaunchKernelGGL(k_mse_v, dim3(npartial), dim3(256), 0, S(stream), pred, target,
+                           reinterpret_cast<uint4 *>(grad), partial, (long long)nvox, C, K, scale);
+    else
+        hipLaunchKernelGGL(k_mse, dim3(npartial), dim3(256), 0, S(stream), pred, target,
+                           reinterpret_cast<bf *>(grad), partial, (long long)nvox, C, K, scale);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }

@@ -57,6 +57,9 @@ def nn():
             "lbmx_nn_upcat": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_pool2_bwd_gate": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_up2_bwd_gate": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_conv3d_flip_many": [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_int64),
+                                         ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(ctypes.c_int32), _vp],
         }
         for name, args in sig.items():
             fn = getattr(L, name)
@@ -135,6 +138,50 @@ class UNet:
         self.head = Conv(c0, 16, rng, act=False)
         self.step_count = 0
         self.scale = None  # per-output-channel target scale (device FP32 [4])
+        self._flatten()
+
+    def _flatten(self):
+        """Put every layer's parameters, gradients, Adam moments and BF16 /
+        flipped copies into flat buffers (the layers keep views), so that one
+        Adam launch per kind (weights, biases) and one flip launch update the
+        whole network."""
+        import torch
+
+        convs = self.convs()
+        nw = [c.w.numel() for c in convs]
+        nb = [c.b.numel() for c in convs]
+        ow = np.concatenate([[0], np.cumsum(nw)[:-1]]).astype(np.int64)
+        ob = np.concatenate([[0], np.cumsum(nb)[:-1]]).astype(np.int64)
+        f32 = dict(dtype=torch.float32, device="cuda")
+        bf = dict(dtype=torch.bfloat16, device="cuda")
+        W, Bn = int(sum(nw)), int(sum(nb))
+        self._fw, self._fgw = torch.empty(W, **f32), torch.zeros(W, **f32)
+        self._fmw, self._fvw = torch.zeros(W, **f32), torch.zeros(W, **f32)
+        self._fwb, self._fwflip = torch.empty(W, **bf), torch.empty(W, **bf)
+        self._fb, self._fgb = torch.empty(Bn, **f32), torch.zeros(Bn, **f32)
+        self._fmb, self._fvb = torch.zeros(Bn, **f32), torch.zeros(Bn, **f32)
+        for c, o, n, q, m in zip(convs, ow, nw, ob, nb):
+            o, n, q, m = int(o), int(n), int(q), int(m)
+            self._fw[o:o + n].copy_(c.w.reshape(-1))
+            self._fb[q:q + m].copy_(c.b)
+            c.w = self._fw[o:o + n].view(c.co, 27, c.ci)
+            c.gw = self._fgw[o:o + n].view(c.co, 27, c.ci)
+            c.mw, c.vw = self._fmw[o:o + n].view(c.co, 27, c.ci), self._fvw[o:o + n].view(c.co, 27, c.ci)
+            c.wb = self._fwb[o:o + n].view(c.co, 27, c.ci)
+            c.wflip = self._fwflip[o:o + n].view(c.ci, 27, c.co)
+            c.b, c.gb = self._fb[q:q + m], self._fgb[q:q + m]
+            c.mb, c.vb = self._fmb[q:q + m], self._fvb[q:q + m]
+        k = len(convs)
+        self._flip_args = ((ctypes.c_int64 * k)(*ow.tolist()),
+                           (ctypes.c_int32 * k)(*[c.ci for c in convs]),
+                           (ctypes.c_int32 * k)(*[c.co for c in convs]))
+        self._sync_all()
+
+    def _sync_all(self):
+        s = stream_ptr()
+        call("lbmx_nn_to_bf16", P(self._fw), P(self._fwb), self._fw.numel(), s)
+        call("lbmx_nn_conv3d_flip_many", P(self._fwb), P(self._fwflip), len(self.convs()),
+             *self._flip_args, s)
 
     def convs(self):
         out = []
@@ -336,10 +383,17 @@ class UNet:
                 call("lbmx_nn_add", P(gh), P(gsk), P(gh), gh.numel(), s)
                 g = gh
 
-    def adam(self, lr, wd=0.0):
+    def adam(self, lr, wd=0.0, b1=0.9, b2=0.999, eps=1e-8):
+        """One Adam step on every layer (as Conv.adam per layer, in three
+        launches over the flat buffers)."""
         self.step_count += 1
-        for c in self.convs():
-            c.adam(lr, self.step_count, wd=wd)
+        s = stream_ptr()
+        call("lbmx_nn_adam", P(self._fw), P(self._fgw), P(self._fmw), P(self._fvw), P(self._fwb),
+             self._fw.numel(), lr, b1, b2, eps, self.step_count, wd, s)
+        call("lbmx_nn_adam", P(self._fb), P(self._fgb), P(self._fmb), P(self._fvb), None,
+             self._fb.numel(), lr, b1, b2, eps, self.step_count, 0.0, s)
+        call("lbmx_nn_conv3d_flip_many", P(self._fwb), P(self._fwflip), len(self.convs()),
+             *self._flip_args, s)
 
     # ---- persistence -----------------------------------------------------------
     def state(self):
@@ -356,7 +410,7 @@ class UNet:
         for k, c in enumerate(self.convs()):
             c.w.copy_(torch.tensor(d[f"w{k}"]))
             c.b.copy_(torch.tensor(d[f"b{k}"]))
-            c.sync_bf16()
+        self._sync_all()
         if "scale" in d:
             self.scale = torch.tensor(np.asarray(d["scale"], np.float32), device="cuda")
 

@@ -255,6 +255,39 @@ def test_silu_add_mse_adam_layout_input():
     assert np.all(xv[..., 7:] == 0)
 
 
+def test_flip_many_and_mse_paths():
+    """lbmx_nn_conv3d_flip_many equals the per-layer flips bit for bit; the
+    loss kernel's vector path (C % 8 == 0, K <= 8) and scalar path give the
+    oracle's loss and gradient."""
+    import ctypes
+    import torch
+    shapes = [(16, 16), (48, 16), (32, 96)]
+    ws = [rnd((co, 27, ci), 60 + k) for k, (ci, co) in enumerate(shapes)]
+    flat = np.concatenate([w.reshape(-1) for w in ws])
+    offs = np.concatenate([[0], np.cumsum([w.size for w in ws])[:-1]])
+    tf = to_bf(flat)
+    out = torch.empty_like(tf)
+    call("lbmx_nn_conv3d_flip_many", P(tf), P(out), len(shapes),
+         (ctypes.c_int64 * 3)(*offs.tolist()), (ctypes.c_int32 * 3)(*[c for c, _ in shapes]),
+         (ctypes.c_int32 * 3)(*[c for _, c in shapes]), S())
+    for k, (ci, co) in enumerate(shapes):
+        one = torch.empty((ci, 27, co), dtype=torch.bfloat16, device="cuda")
+        tw = to_bf(ws[k])
+        call("lbmx_nn_conv3d_flip", P(tw), P(one), ci, co, S())
+        o = int(offs[k])
+        assert np.array_equal(from_bf(out)[o:o + ws[k].size], from_bf(one).reshape(-1))
+    for C, K in ((16, 4), (24, 5), (12, 3)):
+        V = 3001
+        pr, tg = np.random.default_rng(C).standard_normal((V, C)), np.random.default_rng(K).standard_normal((V, K))
+        tp, tt = to_f32(pr), to_f32(tg)
+        grad = torch.empty((V, C), dtype=torch.bfloat16, device="cuda")
+        part = torch.zeros(64, dtype=torch.float64, device="cuda")
+        call("lbmx_nn_mse", P(tp), P(tt), P(grad), P(part), 64, V, C, K, S())
+        loss, g = N.mse(pr.astype(np.float32), tg.astype(np.float32), K)
+        assert abs(part.cpu().numpy().sum() / (V * K) - loss) <= 1e-6 * loss
+        assert np.all(np.abs(from_bf(grad) - g) <= 2 ** -8 * np.abs(g) + 1e-12)
+
+
 def ulp_bf(a):
     """Spacing of BF16 at |a| (2^-7 relative to the power of two below)."""
     a = np.abs(np.asarray(a, np.float64))
