@@ -389,30 +389,51 @@ __global__ __launch_bounds__(256) void k_conv_flip_many(const bf *__restrict__ w
 // gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci], gb[co] += sum_p gout[p][co].
 //
 // A block owns one (co tile, ci tile) pair (blockIdx.y) and walks bricks of
-// 16 x 4 x 4 voxels (in the order of brick_walk), all 27 taps
-// per brick, so each operand is read from global memory once per brick
-// instead of once per tap.  Per brick it stages in LDS, transposed to
-// [channel][voxel] so that every MFMA operand is one aligned 8-byte read:
+// 16 x 4 x 4 voxels (in the order of brick_walk), all 27 taps per brick, so
+// each operand is read from global memory once per brick instead of once
+// per tap.  The reduction runs over voxels, so both MFMA operands need 8
+// consecutive voxels of one channel: per brick the block stages in LDS,
+// transposed to [channel][voxel]:
 //   gT: the brick's gout tile, 16 channels x 256 voxels;
 //   iT: the input tile on the brick plus a one-voxel halo in y and z, in
 //       three copies shifted by dx = -1, 0, +1 along x (copy dx holds
-//       in[x + dx] at x), so a tap's 4 consecutive voxels never straddle an
-//       8-byte boundary.
-// Channel planes are padded by 4 elements (8 bytes), which puts the 16
-// channels read by one quarter-wavefront on distinct LDS banks.
-// Wave w runs the taps w, w + 4, ... (7 or 6) over the brick's 16 rows of 16
-// voxels, reusing the gout operand across its taps; wave 3's free slot
-// accumulates the bias gradient as an MFMA against ones (every wave issues 7
-// MFMAs per row with no branch).  Partial sums stay
-// in registers across the block's bricks and are added to gw / gb
+//       in[x + dx] at x), so a tap's 8 consecutive voxels are one aligned
+//       16-byte read.
+// The transpose packs two x-neighbours of one channel into each 32-bit LDS
+// word, and consecutive lanes write consecutive words.  Channel rows are
+// padded by 8 elements (16 bytes), which puts the 8 channels read by one
+// 8-lane phase of a 16-byte read on distinct banks.
+// The products run on v_mfma_f32_16x16x32_bf16 with K = 32 voxels, two brick
+// rows (lanes 0-31 row 2q, lanes 32-63 row 2q + 1, 8 voxels per lane).  Wave
+// w runs the taps w, w + 4, ... (7 or 6) over the brick's 8 row pairs,
+// reusing the gout operand across its taps; wave 3's free slot accumulates
+// the bias gradient as an MFMA against an LDS block of ones.  Each lane's
+// operand addresses are computed once per launch, a row pair step is an
+// immediate offset, so the inner loop is LDS reads and MFMAs only.  Partial
+// sums stay in registers across the block's bricks and are added to gw / gb
 // atomically at the end.  Voxel and element indices are 32-bit (the host
 // checks B D H W C < 2^31).
 constexpr int WB_X = 16, WB_Y = 4, WB_Z = 4, WB_V = WB_X * WB_Y * WB_Z;
 constexpr int WB_HROWS = (WB_Y + 2) * (WB_Z + 2);   // halo rows of 16 voxels
-constexpr int WB_PLANE = WB_HROWS * WB_X + 4;       // one channel of one shifted copy
-constexpr int WB_GROW = WB_V + 4;                   // one channel of the gout tile
+constexpr int WB_PLANE = WB_HROWS * WB_X + 8;       // one channel of one shifted copy
+constexpr int WB_GROW = WB_V + 8;                   // one channel of the gout tile
 constexpr int WB_SLOTS = 7;                         // taps per wave (27 = 7 + 7 + 7 + 6)
+constexpr int WB_ONES = (3 * 6 + 2) * WB_X + 16;    // ones block: the bias slot's 8 row-pair reads
+constexpr int WB_ITASKS = WB_HROWS * (WB_X / 2) * 2;   // (halo row, x pair, channel half) = 576
+constexpr int WB_ITERS = (WB_ITASKS + 255) / 256;
 constexpr long long WG_TARGET_BLOCKS = 512;         // blocks per launch, all channel pairs
+
+// 32-bit words (channel c of voxel A, channel c of voxel B) for the 8
+// channels of two 16-byte channel-last pieces, low voxel in the low half.
+__device__ __forceinline__ void pair_words(const uint4 &a, const uint4 &b, uint32_t w[8])
+{
+    const uint32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        w[2 * k] = (av[k] & 0xffffu) | (bv[k] << 16);
+        w[2 * k + 1] = (av[k] >> 16) | (bv[k] & 0xffff0000u);
+    }
+}
 
 __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, const bf *__restrict__ gout,
                                                     float *__restrict__ gw, float *__restrict__ gb, Dims d,
@@ -420,6 +441,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
 {
     __shared__ __attribute__((aligned(16))) bf gT[16 * WB_GROW];
     __shared__ __attribute__((aligned(16))) bf iT[3 * 16 * WB_PLANE];
+    __shared__ __attribute__((aligned(16))) bf oT[WB_ONES];
     const int Ci = d.Ci, Co = d.Co;
     const int CIT = Ci / 16;
     const int ct = blockIdx.y / CIT, it = blockIdx.y % CIT;
@@ -427,109 +449,113 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
     const int col = lane & 15, kq = lane >> 4;
     const bool do_bias = gb != nullptr && it == 0;
     const int nbricks = d.B * nbx * nby * nbz;
-    const s4 ones = s4{0x3f80, 0x3f80, 0x3f80, 0x3f80};  // BF16 1.0
-    // LDS offset of each slot's input operand at brick row 0; slot s runs tap
-    // wv + 4 s, except wave 3's last slot, which runs the bias (operand ones;
-    // its offset is any valid one and the value is not used).
-    int boff[WB_SLOTS];
+
+    // Operand addresses of this lane at row pair 0: the gout operand (row
+    // kq >> 1, voxels 8 (kq & 1) ..) and, per slot, the input operand of tap
+    // wv + 4 s at the same voxels; wave 3's last slot reads the ones block.
+    // Row pair q adds (q / 2) 6 + 2 (q % 2) halo rows to every input address.
+    const bf *ap = gT + col * WB_GROW + kq * 8;
+    const bf *bp[WB_SLOTS];
 #pragma unroll
     for (int s = 0; s < WB_SLOTS; ++s) {
-        const int tap = min(wv + 4 * s, 26);
+        const int tap = wv + 4 * s;
         const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
-        boff[s] = ((dx + 1) * 16 + col) * WB_PLANE + ((1 + dz) * (WB_Y + 2) + (1 + dy)) * WB_X + kq * 4;
+        const int hrow = (1 + dz) * (WB_Y + 2) + (kq >> 1) + 1 + dy;
+        bp[s] = tap < 27 ? iT + ((dx + 1) * 16 + col) * WB_PLANE + hrow * WB_X + (kq & 1) * 8 : oT;
     }
     f4 acc[WB_SLOTS];
 #pragma unroll
     for (int s = 0; s < WB_SLOTS; ++s)
         acc[s] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int i = threadIdx.x; i < WB_ONES / 2; i += 256)
+        reinterpret_cast<uint32_t *>(oT)[i] = 0x3f803f80u;  // BF16 1.0, 1.0
 
-    // Software pipeline: the global loads of the block's next brick are
-    // issued into registers before this brick's MFMAs and stored to LDS
-    // afterwards.
-    // Thread t holds the gout row of voxel t and halo voxels t, t + 256,
-    // t + 512 (of 18 x 36 = 648).
-    constexpr int NH = (18 * WB_HROWS + 255) / 256;
-    uint4 g_lo, g_hi, h_lo[NH], h_hi[NH];
+    // Staging tasks.  gout: thread t packs voxels 2p, 2p + 1 (p = t & 127) of
+    // channel half t >> 7.  Input: task k = (x pair a = k & 7, halo row
+    // r = (k >> 3) % 36, channel half k / 288) loads the four voxels x0 + 2a
+    // - 1 .. x0 + 2a + 2 of its row and writes positions 2a, 2a + 1 of the
+    // three shifted copies.  The next brick's loads are issued before this
+    // brick's MFMAs and written to LDS afterwards.
+    uint4 gl[2], il[WB_ITERS][4];
     auto load_brick = [&](int br) {
-        int r = br;
-        const int bx = r % nbx; r /= nbx;
-        const int by = r % nby; r /= nby;
-        const int bz = r % nbz;
-        const int b = r / nbz;
+        int rr = br;
+        const int bx = rr % nbx; rr /= nbx;
+        const int by = rr % nby; rr /= nby;
+        const int bz = rr % nbz;
+        const int b = rr / nbz;
         const int x0 = bx * WB_X, y0 = by * WB_Y, z0 = bz * WB_Z;
         {
-            const int v = threadIdx.x;
+            const int p = threadIdx.x & 127, h = threadIdx.x >> 7;
+            const int v = 2 * p;
             const int x = x0 + (v & 15), y = y0 + ((v >> 4) & 3), z = z0 + (v >> 6);
-            g_lo = g_hi = make_uint4(0, 0, 0, 0);
-            if (x < d.W && y < d.H && z < d.D) {
-                const int p = ((b * d.D + z) * d.H + y) * d.W + x;
-                const uint4 *src = reinterpret_cast<const uint4 *>(gout + p * Co + ct * 16);
-                g_lo = src[0];
-                g_hi = src[1];
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                gl[m] = make_uint4(0, 0, 0, 0);
+                if (x + m < d.W && y < d.H && z < d.D) {
+                    const int q = ((b * d.D + z) * d.H + y) * d.W + x + m;
+                    gl[m] = *reinterpret_cast<const uint4 *>(gout + q * Co + ct * 16 + h * 8);
+                }
             }
         }
 #pragma unroll
-        for (int k = 0; k < NH; ++k) {
-            const int i = threadIdx.x + 256 * k;
-            h_lo[k] = h_hi[k] = make_uint4(0, 0, 0, 0);
-            if (i < 18 * WB_HROWS) {
-                const int hx = i % 18 - 1, row = i / 18;
-                const int hy = row % (WB_Y + 2), hz = row / (WB_Y + 2);
-                const int x = x0 + hx, y = y0 + hy - 1, z = z0 + hz - 1;
-                if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
-                    const int q = ((b * d.D + z) * d.H + y) * d.W + x;
-                    const uint4 *src = reinterpret_cast<const uint4 *>(in + q * Ci + it * 16);
-                    h_lo[k] = src[0];
-                    h_hi[k] = src[1];
-                }
+        for (int k = 0; k < WB_ITERS; ++k) {
+            const int task = threadIdx.x + 256 * k;
+            const int a = task & 7, r = (task >> 3) % WB_HROWS, h = task / (8 * WB_HROWS);
+            const int y = y0 + r % (WB_Y + 2) - 1, z = z0 + r / (WB_Y + 2) - 1;
+            const bool row_ok = task < WB_ITASKS && y >= 0 && y < d.H && z >= 0 && z < d.D;
+            const int q0 = ((b * d.D + z) * d.H + y) * d.W;
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int x = x0 + 2 * a - 1 + m;
+                il[k][m] = make_uint4(0, 0, 0, 0);
+                if (row_ok && x >= 0 && x < d.W)
+                    il[k][m] = *reinterpret_cast<const uint4 *>(in + (q0 + x) * Ci + it * 16 + h * 8);
             }
         }
     };
+    auto store_brick = [&]() {
+        {
+            const int p = threadIdx.x & 127, h = threadIdx.x >> 7;
+            uint32_t w[8];
+            pair_words(gl[0], gl[1], w);
+#pragma unroll
+            for (int c = 0; c < 8; ++c)
+                reinterpret_cast<uint32_t *>(gT + (h * 8 + c) * WB_GROW)[p] = w[c];
+        }
+#pragma unroll
+        for (int k = 0; k < WB_ITERS; ++k) {
+            const int task = threadIdx.x + 256 * k;
+            if (task >= WB_ITASKS)
+                continue;
+            const int a = task & 7, r = (task >> 3) % WB_HROWS, h = task / (8 * WB_HROWS);
+#pragma unroll
+            for (int c3 = 0; c3 < 3; ++c3) {  // copy c3 holds in[x + (c3 - 1)] at x
+                uint32_t w[8];
+                pair_words(il[k][c3], il[k][c3 + 1], w);
+#pragma unroll
+                for (int c = 0; c < 8; ++c)
+                    reinterpret_cast<uint32_t *>(iT + (c3 * 16 + h * 8 + c) * WB_PLANE + r * WB_X)[a] = w[c];
+            }
+        }
+    };
+
     const BrickWalk bw = brick_walk(nbricks);
     if (bw.count > 0)
         load_brick(bw.first);
-
     for (int n = 0; n < bw.count; ++n) {
         __syncthreads();  // the previous brick's reads are done
-        {   // gout tile: thread = voxel
-            const int v = threadIdx.x;
-            const uint32_t w8[8] = {g_lo.x, g_lo.y, g_lo.z, g_lo.w, g_hi.x, g_hi.y, g_hi.z, g_hi.w};
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-                gT[c * WB_GROW + v] = bf((w8[c >> 1] >> (16 * (c & 1))) & 0xffff);
-        }
-#pragma unroll
-        for (int k = 0; k < NH; ++k) {  // input tile with halo, three x-shifted copies
-            const int i = threadIdx.x + 256 * k;
-            if (i >= 18 * WB_HROWS)
-                continue;
-            const int hx = i % 18 - 1, row = i / 18;
-            const uint32_t w8[8] = {h_lo[k].x, h_lo[k].y, h_lo[k].z, h_lo[k].w,
-                                    h_hi[k].x, h_hi[k].y, h_hi[k].z, h_hi[k].w};
-#pragma unroll
-            for (int c3 = 0; c3 < 3; ++c3) {  // copy c3 holds in[x + (c3 - 1)] at x
-                const int xs = hx - (c3 - 1);
-                if (xs >= 0 && xs < WB_X) {
-#pragma unroll
-                    for (int c = 0; c < 16; ++c)
-                        iT[(c3 * 16 + c) * WB_PLANE + row * WB_X + xs] =
-                            bf((w8[c >> 1] >> (16 * (c & 1))) & 0xffff);
-                }
-            }
-        }
+        store_brick();
         __syncthreads();
         if (n + 1 < bw.count)
             load_brick(bw.first + (n + 1) * bw.stride);
-#pragma unroll 4
-        for (int g = 0; g < WB_Y * WB_Z; ++g) {  // brick row (gy, gz) of 16 voxels
-            const int rowoff = ((g / WB_Y) * (WB_Y + 2) + g % WB_Y) * WB_X;
-            const s4 av = *reinterpret_cast<const s4 *>(gT + col * WB_GROW + g * 16 + kq * 4);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {  // row pair (2q, 2q + 1)
+            const bf8v av = *reinterpret_cast<const bf8v *>(ap + q * 32);
+            const int roff = ((q / 2) * (WB_Y + 2) + 2 * (q % 2)) * WB_X;
 #pragma unroll
             for (int s = 0; s < WB_SLOTS; ++s) {
-                s4 bv = *reinterpret_cast<const s4 *>(iT + boff[s] + rowoff);
-                if (s == WB_SLOTS - 1)
-                    bv = wv == 3 ? ones : bv;
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[s], 0, 0, 0);
+                const bf8v bv = *reinterpret_cast<const bf8v *>(bp[s] + roff);
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[s], 0, 0, 0);
             }
         }
     }
