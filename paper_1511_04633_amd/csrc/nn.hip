@@ -200,8 +200,11 @@ __global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ 
         wrow[k] = i < WITEMS ? ((co0 + co) * 27 + tap) * Ci + (i & 1) * 8 : -1;
     }
 
+    // With one round per brick (Ci = 16) the weights are the same for every
+    // item: they are loaded and staged with the block's first item only.
+    const bool w_once = R == 1;
     uint4 xv[FC_XITERS], wt[WITERS];
-    auto load_round = [&](int j, int c0) {
+    auto load_round = [&](int j, int c0, bool with_w) {
         int b, x0, y0, z0;
         brick_at(j, b, x0, y0, z0);
 #pragma unroll
@@ -217,18 +220,22 @@ __global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ 
             }
             xv[k] = v;
         }
+        if (!with_w)
+            return;
 #pragma unroll
         for (int k = 0; k < WITERS; ++k)  // [tap][co][2 x 8 ch]
             wt[k] = wrow[k] >= 0 ? *reinterpret_cast<const uint4 *>(w + size_t(wrow[k]) + c0)
                                  : make_uint4(0, 0, 0, 0);
     };
-    auto store_round = [&]() {
+    auto store_round = [&](bool with_w) {
 #pragma unroll
         for (int k = 0; k < FC_XITERS; ++k)
             if (hpk[k] >= 0) {
                 const int i = threadIdx.x + k * FC_THREADS;
                 *reinterpret_cast<uint4 *>(xs + fc_slot(i >> 1, i & 1, hpk[k] & 0xff)) = xv[k];
             }
+        if (!with_w)
+            return;
 #pragma unroll
         for (int k = 0; k < WITERS; ++k) {
             const int i = threadIdx.x + k * FC_THREADS;
@@ -266,17 +273,17 @@ __global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ 
     const BrickWalk bw = brick_walk(nbricks);
     const int nitems = bw.count * R;  // (brick, round) pairs of this block
     if (nitems > 0)
-        load_round(bw.first, 0);
+        load_round(bw.first, 0, true);
     int b = 0, x0 = 0, y0 = 0, z0 = 0;
     for (int item = 0; item < nitems; ++item) {
         const int round = item % R;
         if (round == 0)
             brick_at(bw.first + (item / R) * bw.stride, b, x0, y0, z0);
         __syncthreads();  // the previous round's operands are no longer read
-        store_round();
+        store_round(!w_once || item == 0);
         __syncthreads();
         if (item + 1 < nitems)
-            load_round(bw.first + ((item + 1) / R) * bw.stride, ((item + 1) % R) * 16);
+            load_round(bw.first + ((item + 1) / R) * bw.stride, ((item + 1) % R) * 16, !w_once);
 #pragma unroll
         for (int pr = 0; pr < 14; ++pr) {
             bf8v a[NCO];
@@ -1084,8 +1091,11 @@ lbmx_status conv_fwd(const void *in, const void *w, const float *bias, void *out
     const bf *wb = reinterpret_cast<const bf *>(w);
     hipStream_t s = S(stream);
     // two output channel tiles per block when Co/16 is even (the input tile
-    // is staged once for both)
-    if ((Co / 16) % 2 == 0)
+    // is staged once for both), unless that leaves fewer than two blocks per
+    // CU (small grids: more blocks hide more latency)
+    const long long bricks =
+        (long long)B * ((W + FC_X - 1) / FC_X) * ((H + FC_Y - 1) / FC_Y) * ((D + FC_Z - 1) / FC_Z);
+    if ((Co / 16) % 2 == 0 && bricks * (Co / 32) >= 512)
         launch_fwd<2>(i, wb, bias, out, out_f32, d, s, ep);
     else
         launch_fwd<1>(i, wb, bias, out, out_f32, d, s, ep);
