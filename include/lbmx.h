@@ -403,6 +403,17 @@ lbmx_status lbmx_nn_conv3d_fwd_ep(const void *in, const void *w, const float *bi
                                   int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
                                   void *stream);
 
+/* A decoder layer's forward convolution with the upsample-and-concatenate
+ * input read in place: the input is cat = [nearest x2 upsampling of low
+ * [B][D/2][H/2][W/2][Cu] | skip [B][D][H][W][Cs]] (what lbmx_nn_upcat would
+ * write), never materialised; w is [Co][27][Cu + Cs]; out (and act, if not
+ * NULL) as lbmx_nn_conv3d_fwd_ep.  Cu, Cs multiples of 16, D H W even.
+ * Equals lbmx_nn_upcat followed by lbmx_nn_conv3d_fwd_ep bit for bit.
+ * EINVAL otherwise. */
+lbmx_status lbmx_nn_conv3d_fwd_upcat(const void *low, const void *skip, const void *w, const float *bias,
+                                     void *out, void *act, int32_t B, int32_t D, int32_t H, int32_t W,
+                                     int32_t Cu, int32_t Cs, int32_t Co, void *stream);
+
 /* cat [B][2D][2H][2W][Ch + Cs] = [nearest x2 upsampling of h [B][D][H][W][Ch]
  * | skip [B][2D][2H][2W][Cs]] in one pass (lbmx_nn_up2 then lbmx_nn_concat).
  * Ch, Cs multiples of 16. */
@@ -440,6 +451,13 @@ lbmx_status lbmx_nn_conv3d_flip_many(const void *w, void *wt, int32_t count, con
 lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, float *gb, int32_t B,
                                  int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
                                  void *stream);
+
+/* lbmx_nn_conv3d_wgrad of a decoder layer whose input is the concatenation
+ * of lbmx_nn_conv3d_fwd_upcat (low, skip, Cu, Cs, D H W even), read in
+ * place; gw is [Co][27][Cu + Cs]. */
+lbmx_status lbmx_nn_conv3d_wgrad_upcat(const void *low, const void *skip, const void *gout, float *gw,
+                                       float *gb, int32_t B, int32_t D, int32_t H, int32_t W, int32_t Cu,
+                                       int32_t Cs, int32_t Co, void *stream);
 
 /* a = z sigmoid(z) elementwise (n BF16 values), and its gradient
  * gz = ga sigmoid(z) (1 + z (1 - sigmoid(z))). */

@@ -113,6 +113,36 @@ __device__ __forceinline__ int fc_slot(int row, int part, int sx)
     return row * 16 + 8 * (part ^ ((sx >> 2) & 1));
 }
 
+// floor(j / n) for 0 <= j < 2^24 from the float reciprocal: the float
+// quotient is within one of the true one, so one correction is exact.
+__device__ __forceinline__ int fdiv_small(int j, int n, float inv_n)
+{
+    int q = int(float(j) * inv_n);
+    const int r = j - q * n;
+    if (r < 0)
+        --q;
+    else if (r >= n)
+        ++q;
+    return q;
+}
+
+// Brick j of a [B][nbz][nby][nbx] grid of bricks (x fastest): batch index
+// and the brick's first voxel (brick counts are below 2^23).
+struct BrickGrid {
+    int nbx, nby, nbz;
+    float inx, iny, inz;
+    __device__ BrickGrid(int x, int y, int z)
+        : nbx(x), nby(y), nbz(z), inx(1.f / x), iny(1.f / y), inz(1.f / z)
+    {
+    }
+    __device__ __forceinline__ void at(int j, int sx, int sy, int sz, int &b, int &x0, int &y0, int &z0) const
+    {
+        const int r1 = fdiv_small(j, nbx, inx), r2 = fdiv_small(r1, nby, iny);
+        b = fdiv_small(r2, nbz, inz);
+        x0 = (j - r1 * nbx) * sx, y0 = (r1 - r2 * nby) * sy, z0 = (r2 - b * nbz) * sz;
+    }
+};
+
 // The bricks a block walks.  Workgroup i runs on XCD i mod 8 (for a grid
 // whose x extent is a multiple of 8 this is blockIdx.x mod 8), and each XCD
 // has its own L2; a block takes bricks first, first + stride, ... of its
@@ -141,6 +171,17 @@ __device__ __forceinline__ BrickWalk brick_walk(int nbricks)
     return r;
 }
 
+// The convolution input: channel-last in[B][D][H][W][Ci], or for a decoder
+// layer the concatenation of the nearest x2 upsampling of low
+// [B][D/2][H/2][W/2][cu] (channels 0 .. cu-1) with skip [B][D][H][W][Ci-cu]
+// (channels cu .. Ci-1), read in place: a 16-channel round or tile lies in
+// one of the two (cu is a multiple of 16), so the choice is uniform.
+struct ConvIn {
+    const bf *in;   // the input, or the skip part
+    const bf *low;  // null for a plain input
+    int cu;         // channels taken from low (0 for a plain input)
+};
+
 // Epilogue options of a BF16 output (all null / 0 for the plain convolution):
 //   act:   also write a = silu(z) beside z = conv + bias (forward layers);
 //   gate:  write bf16(bf16(conv) * silu'(gate)) instead of the convolution:
@@ -156,12 +197,12 @@ struct Epilogue {
     int split;
 };
 
+// Occupancy is register-bound: 3 waves per SIMD for one channel tile (no
+// spills; 4 would spill), 2 for two.
 template <int NCO>
-__global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ in,
-                                                         const bf *__restrict__ w,
-                                                         const float *__restrict__ bias,
-                                                         void *__restrict__ out, int out_f32, Dims d,
-                                                         int nbx, int nby, int nbz, Epilogue ep)
+__global__ __launch_bounds__(FC_THREADS) __attribute__((amdgpu_waves_per_eu(NCO == 1 ? 3 : 2))) void
+k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias, void *__restrict__ out,
+           int out_f32, Dims d, int nbx, int nby, int nbz, Epilogue ep)
 {
     constexpr int WITEMS = 27 * NCO * 16 * 2;       // 16-byte pieces of the weight tile
     constexpr int WITERS = (WITEMS + FC_THREADS - 1) / FC_THREADS;
@@ -169,29 +210,31 @@ __global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ 
     __shared__ __attribute__((aligned(16))) bf ws[28 * NCO * 16 * 16];
     __shared__ __attribute__((aligned(16))) bf zs[FC_ZERO];
     const int Ci = d.Ci, Co = d.Co;
+    const int cs = Ci - src.cu;  // channel stride of src.in
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int h = kq >> 1, part = kq & 1;   // tap parity and channel half of this lane's K slice
     const int co0 = blockIdx.y * NCO * 16;
     const int nbricks = d.B * nbx * nby * nbz;
     const int R = Ci / 16;  // rounds of 16 input channels per brick
+    const BrickGrid grid(nbx, nby, nbz);
     auto brick_at = [&](int j, int &bb, int &xx, int &yy, int &zz) {
-        int r = j;
-        const int bx = r % nbx; r /= nbx;
-        const int by = r % nby; r /= nby;
-        const int bz = r % nbz;
-        bb = r / nbz;
-        xx = bx * FC_X, yy = by * FC_Y, zz = bz * FC_Z;
+        grid.at(j, FC_X, FC_Y, FC_Z, bb, xx, yy, zz);
     };
 
-    // This thread's input pieces: halo coordinates packed as hx | hy << 8 |
-    // hz << 16 (-1: none) and its weight pieces' row offsets in w (-1: none).
-    int hpk[FC_XITERS], wrow[WITERS];
+    // This thread's input pieces i = threadIdx.x + k FC_THREADS (halo voxel
+    // i / 2, channel half i % 2): their element offsets from the brick's
+    // first voxel; and its weight pieces' row offsets in w (-1: none).
+    auto halo_of = [&](int k, int &hx, int &hy, int &hz) {
+        const int hv = (int(threadIdx.x) + k * FC_THREADS) >> 1, hrow = hv / FC_HX;
+        hx = hv % FC_HX, hy = hrow % FC_HY, hz = hrow / FC_HY;
+    };
+    int rel[FC_XITERS], wrow[WITERS];
 #pragma unroll
     for (int k = 0; k < FC_XITERS; ++k) {
-        const int i = threadIdx.x + k * FC_THREADS;
-        const int hv = i >> 1, hx = hv % FC_HX, hrow = hv / FC_HX;
-        hpk[k] = i < FC_XITEMS ? hx | (hrow % FC_HY) << 8 | (hrow / FC_HY) << 16 : -1;
+        int hx, hy, hz;
+        halo_of(k, hx, hy, hz);
+        rel[k] = (((hz - 1) * d.H + (hy - 1)) * d.W + (hx - 1)) * cs + (threadIdx.x & 1) * 8;
     }
 #pragma unroll
     for (int k = 0; k < WITERS; ++k) {
@@ -207,18 +250,42 @@ __global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ 
     auto load_round = [&](int j, int c0, bool with_w) {
         int b, x0, y0, z0;
         brick_at(j, b, x0, y0, z0);
+        const bf *base = src.in + size_t(((b * d.D + z0) * d.H + y0) * d.W + x0) * cs + (c0 - src.cu);
+        const bool interior = x0 >= 1 && x0 + FC_X < d.W && y0 >= 1 && y0 + FC_Y < d.H && z0 >= 1 &&
+                              z0 + FC_Z < d.D;
+        if (c0 < src.cu) {  // upsampled channels: voxel (x, y, z) reads low at (x/2, y/2, z/2)
+            const int Dl = d.D >> 1, Hl = d.H >> 1, Wl = d.W >> 1;
 #pragma unroll
-        for (int k = 0; k < FC_XITERS; ++k) {
-            uint4 v = make_uint4(0, 0, 0, 0);
-            if (hpk[k] >= 0) {
-                const int x = x0 + (hpk[k] & 0xff) - 1, y = y0 + ((hpk[k] >> 8) & 0xff) - 1,
-                          z = z0 + (hpk[k] >> 16) - 1;
-                if (x >= 0 && x < d.W && y >= 0 && y < d.H && z >= 0 && z < d.D) {
-                    const int q = ((b * d.D + z) * d.H + y) * d.W + x;
-                    v = *reinterpret_cast<const uint4 *>(in + size_t(q) * Ci + c0 + (threadIdx.x & 1) * 8);
+            for (int k = 0; k < FC_XITERS; ++k) {
+                uint4 v = make_uint4(0, 0, 0, 0);
+                int hx, hy, hz;
+                halo_of(k, hx, hy, hz);
+                const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+                if (int(threadIdx.x) + k * FC_THREADS < FC_XITEMS && x >= 0 && x < d.W && y >= 0 &&
+                    y < d.H && z >= 0 && z < d.D) {
+                    const int l = ((b * Dl + (z >> 1)) * Hl + (y >> 1)) * Wl + (x >> 1);
+                    v = *reinterpret_cast<const uint4 *>(src.low + size_t(l) * src.cu + c0 +
+                                                         (threadIdx.x & 1) * 8);
                 }
+                xv[k] = v;
             }
-            xv[k] = v;
+        } else if (interior) {  // the whole halo is inside the volume
+#pragma unroll
+            for (int k = 0; k < FC_XITERS; ++k)
+                if (int(threadIdx.x) + k * FC_THREADS < FC_XITEMS)
+                    xv[k] = *reinterpret_cast<const uint4 *>(base + rel[k]);
+        } else {
+#pragma unroll
+            for (int k = 0; k < FC_XITERS; ++k) {
+                uint4 v = make_uint4(0, 0, 0, 0);
+                int hx, hy, hz;
+                halo_of(k, hx, hy, hz);
+                const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
+                if (int(threadIdx.x) + k * FC_THREADS < FC_XITEMS && x >= 0 && x < d.W && y >= 0 &&
+                    y < d.H && z >= 0 && z < d.D)
+                    v = *reinterpret_cast<const uint4 *>(base + rel[k]);
+                xv[k] = v;
+            }
         }
         if (!with_w)
             return;
@@ -229,11 +296,11 @@ __global__ __launch_bounds__(FC_THREADS) void k_conv_fwd(const bf *__restrict__ 
     };
     auto store_round = [&](bool with_w) {
 #pragma unroll
-        for (int k = 0; k < FC_XITERS; ++k)
-            if (hpk[k] >= 0) {
-                const int i = threadIdx.x + k * FC_THREADS;
-                *reinterpret_cast<uint4 *>(xs + fc_slot(i >> 1, i & 1, hpk[k] & 0xff)) = xv[k];
-            }
+        for (int k = 0; k < FC_XITERS; ++k) {
+            const int i = threadIdx.x + k * FC_THREADS;
+            if (i < FC_XITEMS)
+                *reinterpret_cast<uint4 *>(xs + fc_slot(i >> 1, i & 1, (i >> 1) % FC_HX)) = xv[k];
+        }
         if (!with_w)
             return;
 #pragma unroll
@@ -431,18 +498,20 @@ constexpr int WB_ITERS = (WB_ITASKS + 255) / 256;
 constexpr long long WG_TARGET_BLOCKS = 512;         // blocks per launch, all channel pairs
 
 // 32-bit words (channel c of voxel A, channel c of voxel B) for the 8
-// channels of two 16-byte channel-last pieces, low voxel in the low half.
+// channels of two 16-byte channel-last pieces, low voxel in the low half:
+// one v_perm_b32 per word (selector bytes 0-3 pick from the second operand,
+// 4-7 from the first).
 __device__ __forceinline__ void pair_words(const uint4 &a, const uint4 &b, uint32_t w[8])
 {
     const uint32_t av[4] = {a.x, a.y, a.z, a.w}, bv[4] = {b.x, b.y, b.z, b.w};
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-        w[2 * k] = (av[k] & 0xffffu) | (bv[k] << 16);
-        w[2 * k + 1] = (av[k] >> 16) | (bv[k] & 0xffff0000u);
+        w[2 * k] = __builtin_amdgcn_perm(bv[k], av[k], 0x05040100u);      // a.lo | b.lo << 16
+        w[2 * k + 1] = __builtin_amdgcn_perm(bv[k], av[k], 0x07060302u);  // a.hi | b.hi << 16
     }
 }
 
-__global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, const bf *__restrict__ gout,
+__global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__restrict__ gout,
                                                     float *__restrict__ gw, float *__restrict__ gb, Dims d,
                                                     int nbx, int nby, int nbz)
 {
@@ -456,6 +525,9 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
     const int col = lane & 15, kq = lane >> 4;
     const bool do_bias = gb != nullptr && it == 0;
     const int nbricks = d.B * nbx * nby * nbz;
+    const int cs = Ci - src.cu;            // channel stride of src.in
+    const bool up = it * 16 < src.cu;      // this block's input channels come from src.low
+    const int cin = it * 16 - src.cu;      // channel offset in src.in (when !up)
 
     // Operand addresses of this lane at row pair 0: the gout operand (row
     // kq >> 1, voxels 8 (kq & 1) ..) and, per slot, the input operand of tap
@@ -483,14 +555,38 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
     // - 1 .. x0 + 2a + 2 of its row and writes positions 2a, 2a + 1 of the
     // three shifted copies.  The next brick's loads are issued before this
     // brick's MFMAs and written to LDS afterwards.
+    // Element offsets from the brick's first voxel: the gout pair of this
+    // thread, and voxel x0 + 2a - 1 of each input task (+ m Ci for voxel m).
+    const BrickGrid grid(nbx, nby, nbz);
+    int goff, ioff[WB_ITERS];
+    {
+        const int v = 2 * (threadIdx.x & 127);
+        goff = (((v >> 6) * d.H + ((v >> 4) & 3)) * d.W + (v & 15)) * Co + ct * 16 + (threadIdx.x >> 7) * 8;
+    }
+#pragma unroll
+    for (int k = 0; k < WB_ITERS; ++k) {
+        const int task = threadIdx.x + 256 * k;
+        const int a = task & 7, r = (task >> 3) % WB_HROWS, h = task / (8 * WB_HROWS);
+        const int hy = r % (WB_Y + 2), hz = r / (WB_Y + 2);
+        ioff[k] = (((hz - 1) * d.H + (hy - 1)) * d.W + (2 * a - 1)) * cs + cin + h * 8;
+    }
     uint4 gl[2], il[WB_ITERS][4];
     auto load_brick = [&](int br) {
-        int rr = br;
-        const int bx = rr % nbx; rr /= nbx;
-        const int by = rr % nby; rr /= nby;
-        const int bz = rr % nbz;
-        const int b = rr / nbz;
-        const int x0 = bx * WB_X, y0 = by * WB_Y, z0 = bz * WB_Z;
+        int b, x0, y0, z0;
+        grid.at(br, WB_X, WB_Y, WB_Z, b, x0, y0, z0);
+        const int vb = ((b * d.D + z0) * d.H + y0) * d.W + x0;
+        if (!up && x0 >= 1 && x0 + WB_X < d.W && y0 >= 1 && y0 + WB_Y < d.H && z0 >= 1 && z0 + WB_Z < d.D) {
+            // the whole halo is inside the volume
+            gl[0] = *reinterpret_cast<const uint4 *>(gout + vb * Co + goff);
+            gl[1] = *reinterpret_cast<const uint4 *>(gout + vb * Co + goff + Co);
+#pragma unroll
+            for (int k = 0; k < WB_ITERS; ++k)
+                if (threadIdx.x + 256 * k < WB_ITASKS)
+#pragma unroll
+                    for (int m = 0; m < 4; ++m)
+                        il[k][m] = *reinterpret_cast<const uint4 *>(src.in + vb * cs + ioff[k] + m * cs);
+            return;
+        }
         {
             const int p = threadIdx.x & 127, h = threadIdx.x >> 7;
             const int v = 2 * p;
@@ -511,12 +607,15 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(const bf *__restrict__ in, c
             const int y = y0 + r % (WB_Y + 2) - 1, z = z0 + r / (WB_Y + 2) - 1;
             const bool row_ok = task < WB_ITASKS && y >= 0 && y < d.H && z >= 0 && z < d.D;
             const int q0 = ((b * d.D + z) * d.H + y) * d.W;
+            const int l0 = ((b * (d.D >> 1) + (z >> 1)) * (d.H >> 1) + (y >> 1)) * (d.W >> 1);
 #pragma unroll
             for (int m = 0; m < 4; ++m) {
                 const int x = x0 + 2 * a - 1 + m;
                 il[k][m] = make_uint4(0, 0, 0, 0);
                 if (row_ok && x >= 0 && x < d.W)
-                    il[k][m] = *reinterpret_cast<const uint4 *>(in + (q0 + x) * Ci + it * 16 + h * 8);
+                    il[k][m] = up ? *reinterpret_cast<const uint4 *>(src.low + (l0 + (x >> 1)) * src.cu +
+                                                                     it * 16 + h * 8)
+                                  : *reinterpret_cast<const uint4 *>(src.in + (q0 + x) * cs + cin + h * 8);
             }
         }
     };
@@ -1036,7 +1135,7 @@ lbmx_status check_dims(int B, int D, int H, int W)
 }
 
 template <int NCO>
-void launch_fwd(const bf *in, const bf *w, const float *bias, void *out, int out_f32, Dims d, hipStream_t s,
+void launch_fwd(ConvIn src, const bf *w, const float *bias, void *out, int out_f32, Dims d, hipStream_t s,
                 Epilogue ep)
 {
     const int nbx = (d.W + FC_X - 1) / FC_X, nby = (d.H + FC_Y - 1) / FC_Y, nbz = (d.D + FC_Z - 1) / FC_Z;
@@ -1060,18 +1159,30 @@ void launch_fwd(const bf *in, const bf *w, const float *bias, void *out, int out
     unsigned grid = std::max(1u, std::min(bricks, resident));
     if (grid >= 8)
         grid -= grid % 8;
-    hipLaunchKernelGGL(k_conv_fwd<NCO>, dim3(grid, groups), dim3(FC_THREADS), 0, s, in, w, bias, out,
+    hipLaunchKernelGGL(k_conv_fwd<NCO>, dim3(grid, groups), dim3(FC_THREADS), 0, s, src, w, bias, out,
                        out_f32, d, nbx, nby, nbz, ep);
 }
 
-lbmx_status conv_fwd(const void *in, const void *w, const float *bias, void *out, int32_t out_f32,
+// Rejects an upsample-and-concatenate input whose low part is malformed.
+lbmx_status check_upcat(const ConvIn &src, int32_t D, int32_t H, int32_t W, int32_t Ci, const char *what)
+{
+    if (!src.low)
+        return LBMX_OK;
+    if (src.cu < 16 || src.cu % 16 || src.cu >= Ci)
+        return fail(LBMX_EINVAL, "%s: need upsampled channels a multiple of 16 below the total", what);
+    if (D % 2 || H % 2 || W % 2)
+        return fail(LBMX_EINVAL, "%s: upsampling needs even D, H, W", what);
+    return LBMX_OK;
+}
+
+lbmx_status conv_fwd(ConvIn src, const void *w, const float *bias, void *out, int32_t out_f32,
                      int32_t B, int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co, void *stream,
                      Epilogue ep)
 {
     lbmx_status st = check_dims(B, D, H, W);
     if (st != LBMX_OK)
         return st;
-    if (!in || !w || !out)
+    if (!src.in || !w || !out)
         return fail(LBMX_EINVAL, "conv3d: NULL tensor");
     if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 1024)
         return fail(LBMX_EINVAL, "conv3d: need Ci, Co multiples of 16 in [16, 1024]");
@@ -1086,8 +1197,9 @@ lbmx_status conv_fwd(const void *in, const void *w, const float *bias, void *out
         return fail(LBMX_EINVAL, "conv3d: act and gate exclude each other");
     if (!ep.out2)
         ep.split = 0;
+    if ((st = check_upcat(src, D, H, W, Ci, "conv3d")) != LBMX_OK)
+        return st;
     const Dims d{B, D, H, W, Ci, Co};
-    const bf *i = reinterpret_cast<const bf *>(in);
     const bf *wb = reinterpret_cast<const bf *>(w);
     hipStream_t s = S(stream);
     // two output channel tiles per block when Co/16 is even (the input tile
@@ -1096,9 +1208,9 @@ lbmx_status conv_fwd(const void *in, const void *w, const float *bias, void *out
     const long long bricks =
         (long long)B * ((W + FC_X - 1) / FC_X) * ((H + FC_Y - 1) / FC_Y) * ((D + FC_Z - 1) / FC_Z);
     if ((Co / 16) % 2 == 0 && bricks * (Co / 32) >= 512)
-        launch_fwd<2>(i, wb, bias, out, out_f32, d, s, ep);
+        launch_fwd<2>(src, wb, bias, out, out_f32, d, s, ep);
     else
-        launch_fwd<1>(i, wb, bias, out, out_f32, d, s, ep);
+        launch_fwd<1>(src, wb, bias, out, out_f32, d, s, ep);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
@@ -1111,7 +1223,8 @@ lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias,
                                int32_t out_f32, int32_t B, int32_t D, int32_t H, int32_t W,
                                int32_t Ci, int32_t Co, void *stream)
 {
-    return conv_fwd(in, w, bias, out, out_f32, B, D, H, W, Ci, Co, stream, Epilogue{});
+    return conv_fwd(ConvIn{reinterpret_cast<const bf *>(in), nullptr, 0}, w, bias, out, out_f32, B, D, H, W, Ci,
+                    Co, stream, Epilogue{});
 }
 
 lbmx_status lbmx_nn_conv3d_fwd_ep(const void *in, const void *w, const float *bias, void *out,
@@ -1121,7 +1234,19 @@ lbmx_status lbmx_nn_conv3d_fwd_ep(const void *in, const void *w, const float *bi
 {
     Epilogue ep{reinterpret_cast<bf *>(act), reinterpret_cast<const bf *>(gate),
                 reinterpret_cast<bf *>(out2), split};
-    return conv_fwd(in, w, bias, out, 0, B, D, H, W, Ci, Co, stream, ep);
+    return conv_fwd(ConvIn{reinterpret_cast<const bf *>(in), nullptr, 0}, w, bias, out, 0, B, D, H, W, Ci, Co,
+                    stream, ep);
+}
+
+lbmx_status lbmx_nn_conv3d_fwd_upcat(const void *low, const void *skip, const void *w, const float *bias,
+                                     void *out, void *act, int32_t B, int32_t D, int32_t H, int32_t W,
+                                     int32_t Cu, int32_t Cs, int32_t Co, void *stream)
+{
+    if (!low)
+        return fail(LBMX_EINVAL, "conv3d_upcat: NULL tensor");
+    Epilogue ep{reinterpret_cast<bf *>(act), nullptr, nullptr, 0};
+    return conv_fwd(ConvIn{reinterpret_cast<const bf *>(skip), reinterpret_cast<const bf *>(low), Cu}, w, bias,
+                    out, 0, B, D, H, W, Cu + Cs, Co, stream, ep);
 }
 
 lbmx_status lbmx_nn_upcat(const void *h, const void *skip, void *cat, int32_t B, int32_t D, int32_t H,
@@ -1212,16 +1337,22 @@ lbmx_status lbmx_nn_conv3d_flip_many(const void *w, void *wt, int32_t count, con
     return LBMX_OK;
 }
 
-lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, float *gb, int32_t B,
-                                 int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co, void *stream)
+}  // extern "C"
+
+namespace {
+
+lbmx_status conv_wgrad(ConvIn src, const void *gout, float *gw, float *gb, int32_t B, int32_t D, int32_t H,
+                       int32_t W, int32_t Ci, int32_t Co, void *stream)
 {
     lbmx_status st = check_dims(B, D, H, W);
     if (st != LBMX_OK)
         return st;
-    if (!in || !gout || !gw)
+    if (!src.in || !gout || !gw)
         return fail(LBMX_EINVAL, "conv3d_wgrad: NULL tensor");
     if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 1024)
         return fail(LBMX_EINVAL, "conv3d_wgrad: need Ci, Co multiples of 16 in [16, 1024]");
+    if ((st = check_upcat(src, D, H, W, Ci, "conv3d_wgrad")) != LBMX_OK)
+        return st;
     const Dims d{B, D, H, W, Ci, Co};
     const long long nv = (long long)B * D * H * W;
     if (nv * (Ci > Co ? Ci : Co) >= (1LL << 31))
@@ -1235,11 +1366,31 @@ lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, fl
     if (gx > nbricks) gx = nbricks;
     if (gx >= 8) gx -= gx % 8;  // x extent a multiple of 8: XCD-aware brick order
     if (gx < 1) gx = 1;
-    hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned(gx), unsigned(pairs)), dim3(256), 0, S(stream),
-                       reinterpret_cast<const bf *>(in), reinterpret_cast<const bf *>(gout), gw, gb, d,
-                       nbx, nby, nbz);
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned(gx), unsigned(pairs)), dim3(256), 0, S(stream), src,
+                       reinterpret_cast<const bf *>(gout), gw, gb, d, nbx, nby, nbz);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, float *gb, int32_t B,
+                                 int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co, void *stream)
+{
+    return conv_wgrad(ConvIn{reinterpret_cast<const bf *>(in), nullptr, 0}, gout, gw, gb, B, D, H, W, Ci, Co,
+                      stream);
+}
+
+lbmx_status lbmx_nn_conv3d_wgrad_upcat(const void *low, const void *skip, const void *gout, float *gw,
+                                       float *gb, int32_t B, int32_t D, int32_t H, int32_t W, int32_t Cu,
+                                       int32_t Cs, int32_t Co, void *stream)
+{
+    if (!low)
+        return fail(LBMX_EINVAL, "conv3d_wgrad_upcat: NULL tensor");
+    return conv_wgrad(ConvIn{reinterpret_cast<const bf *>(skip), reinterpret_cast<const bf *>(low), Cu}, gout,
+                      gw, gb, B, D, H, W, Cu + Cs, Co, stream);
 }
 
 lbmx_status lbmx_nn_silu(const void *z, void *a, int64_t n, void *stream)

@@ -55,6 +55,10 @@ def nn():
             "lbmx_nn_conv3d_fwd_ep": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32,
                                       _i32, _i32, _i32, _vp],
             "lbmx_nn_upcat": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_conv3d_fwd_upcat": [_vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32,
+                                         _i32, _i32, _i32, _vp],
+            "lbmx_nn_conv3d_wgrad_upcat": [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32,
+                                           _i32, _i32, _i32, _vp],
             "lbmx_nn_pool2_bwd_gate": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_up2_bwd_gate": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_conv3d_flip_many": [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_int64),
@@ -200,29 +204,36 @@ class UNet:
 
     # ---- forward -------------------------------------------------------------
     # fused (default): the convolution kernels also apply SiLU (forward) and
-    # its derivative (data gradients), split concatenated gradients, and the
-    # decoder input is built by one upsample-and-concatenate pass; unfused:
+    # its derivative (data gradients), split concatenated gradients, and read
+    # a decoder layer's upsampled-and-concatenated input in place; unfused:
     # the separate elementwise kernels (kept to check the fused path against).
     fused = True
     # when a list, forward() and backward() append every convolution's GPU
     # tensors (inputs, outputs, gradients) to it, for per-layer checks
     record = None
 
-    def _conv(self, conv, x, B, r, cache):
-        """conv + SiLU on a [B, r, r, r, ci] BF16 tensor; returns the activation."""
+    def _conv(self, conv, x, B, r, cache, up=None):
+        """conv + SiLU on a [B, r, r, r, ci] BF16 tensor x, or (fused) on the
+        concatenation [up2(low) | skip] read in place, up = (low, skip, cu, cs);
+        returns the activation."""
         s = stream_ptr()
         z = self._bf(B, r, r, r, conv.co)
         a = self._bf(B, r, r, r, conv.co)
-        if self.fused:
+        if up is not None:
+            low, skip, cu, cs = up
+            call("lbmx_nn_conv3d_fwd_upcat", P(low), P(skip), P(conv.wb), P(conv.b), P(z), P(a),
+                 B, r, r, r, cu, cs, conv.co, s)
+        elif self.fused:
             call("lbmx_nn_conv3d_fwd_ep", P(x), P(conv.wb), P(conv.b), P(z), P(a), None, None, 0,
                  B, r, r, r, conv.ci, conv.co, s)
         else:
             call("lbmx_nn_conv3d_fwd", P(x), P(conv.wb), P(conv.b), P(z), 0, B, r, r, r, conv.ci,
                  conv.co, s)
             call("lbmx_nn_silu", P(z), P(a), z.numel(), s)
-        cache.append({"kind": "conv", "conv": conv, "x": x, "z": z, "r": r})
+        cache.append({"kind": "conv", "conv": conv, "x": x, "up": up, "z": z, "r": r})
         if self.record is not None:
-            self.record.append({"pass": "fwd", "conv": conv, "x": x, "z": z, "a": a, "r": r})
+            self.record.append({"pass": "fwd", "conv": conv, "x": x, "up": up, "z": z, "a": a,
+                                "r": r})
         return a
 
     def forward(self, cond, B, train=False):
@@ -251,16 +262,18 @@ class UNet:
         for (ca, cb) in self.dec:
             sk, rs = skips.pop()
             cu, cs = h.shape[-1], sk.shape[-1]
-            cat = self._bf(B, 2 * r, 2 * r, 2 * r, cu + cs)
             if self.fused:
-                call("lbmx_nn_upcat", P(h), P(sk), P(cat), B, r, r, r, cu, cs, s)
+                r *= 2
+                cache.append({"kind": "upcat", "r": r, "cu": cu, "cs": cs})
+                h = self._conv(ca, None, B, r, cache, up=(h, sk, cu, cs))
             else:
+                cat = self._bf(B, 2 * r, 2 * r, 2 * r, cu + cs)
                 u = self._bf(B, 2 * r, 2 * r, 2 * r, cu)
                 call("lbmx_nn_up2", P(h), P(u), B, r, r, r, cu, 0, s)
                 call("lbmx_nn_concat", P(u), P(sk), P(cat), B * (2 * r) ** 3, cu, cs, 0, s)
-            r *= 2
-            cache.append({"kind": "upcat", "r": r, "cu": cu, "cs": cs})
-            h = self._conv(ca, cat, B, r, cache)
+                r *= 2
+                cache.append({"kind": "upcat", "r": r, "cu": cu, "cs": cs})
+                h = self._conv(ca, cat, B, r, cache)
             h = self._conv(cb, h, B, r, cache)
         pred = torch.empty((B, m ** 3, 16), dtype=torch.float32, device="cuda")
         call("lbmx_nn_conv3d_fwd", P(h), P(self.head.wb), P(self.head.b), P(pred), 1, B, m, m, m,
@@ -299,9 +312,14 @@ class UNet:
             it = cache[i]
             if it["kind"] == "conv":
                 conv, x, r = it["conv"], it["x"], it["r"]
-                call("lbmx_nn_conv3d_wgrad", P(x), P(g), P(conv.gw), P(conv.gb), B, r, r, r,
-                     conv.ci, conv.co, s)
-                rec = {"pass": "bwd", "conv": conv, "x": x, "gz": g, "r": r}
+                if it["up"] is not None:
+                    low, skip, cu, cs = it["up"]
+                    call("lbmx_nn_conv3d_wgrad_upcat", P(low), P(skip), P(g), P(conv.gw),
+                         P(conv.gb), B, r, r, r, cu, cs, conv.co, s)
+                else:
+                    call("lbmx_nn_conv3d_wgrad", P(x), P(g), P(conv.gw), P(conv.gb), B, r, r, r,
+                         conv.ci, conv.co, s)
+                rec = {"pass": "bwd", "conv": conv, "x": x, "up": it["up"], "gz": g, "r": r}
                 prev = cache[i - 1] if i > 0 else None
                 if prev is None:
                     rec["dgrad"] = None

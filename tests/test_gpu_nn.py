@@ -353,6 +353,54 @@ def test_conv_epilogue_options(shape, ci, co):
                  S())
 
 
+@pytest.mark.parametrize("shape", [(2, 10, 10, 36), (1, 4, 6, 14)])
+def test_conv_with_upcat_input_read_in_place(shape):
+    """lbmx_nn_conv3d_fwd_upcat / lbmx_nn_conv3d_wgrad_upcat (a decoder
+    layer's input [up2(low) | skip] read in place) against lbmx_nn_upcat
+    followed by the plain kernels: the forward bit for bit (same values, same
+    summation order), the weight gradients up to the order of the FP32 atomic
+    additions; both against the oracle.  (2, 10, 10, 36) has interior bricks
+    and ragged ones (x: 16 + 16 + 4), (1, 4, 6, 14) only partial bricks."""
+    print(f"case: conv with in-place upsample-and-concatenate input {shape}", flush=True)
+    B, D, H, W = shape
+    Cu, Cs, Co = 32, 16, 32
+    low, sk = rnd((B, D // 2, H // 2, W // 2, Cu), 61), rnd((B, D, H, W, Cs), 62)
+    w, b, g = rnd((Co, 27, Cu + Cs), 63, 0.1), rnd((Co,), 64), rnd((B, D, H, W, Co), 65)
+    tl, ts, tw, tb, tg = to_bf(low), to_bf(sk), to_bf(w), to_f32(b), to_bf(g)
+    cat = bf_tensor((B, D, H, W, Cu + Cs))
+    call("lbmx_nn_upcat", P(tl), P(ts), P(cat), B, D // 2, H // 2, W // 2, Cu, Cs, S())
+    z1, a1, z2, a2 = (bf_tensor((B, D, H, W, Co)) for _ in range(4))
+    call("lbmx_nn_conv3d_fwd_upcat", P(tl), P(ts), P(tw), P(tb), P(z1), P(a1), B, D, H, W, Cu, Cs,
+         Co, S())
+    call("lbmx_nn_conv3d_fwd_ep", P(cat), P(tw), P(tb), P(z2), P(a2), None, None, 0, B, D, H, W,
+         Cu + Cs, Co, S())
+    assert np.array_equal(bits_of(from_bf(z1)), bits_of(from_bf(z2)))
+    assert np.array_equal(bits_of(from_bf(a1)), bits_of(from_bf(a2)))
+    x = np.concatenate([N.up2(low), sk], axis=-1)
+    ref = N.conv3d(x, w, b)
+    bnd = 2e-5 * N.conv3d(np.abs(x), np.abs(w), np.abs(b)) + 1e-6 + ulp_bf(ref)
+    assert np.all(np.abs(from_bf(z1) - ref) <= bnd)
+    import torch
+    gw1, gw2 = (torch.zeros((Co, 27, Cu + Cs), device="cuda") for _ in range(2))
+    gb1, gb2 = (torch.zeros(Co, device="cuda") for _ in range(2))
+    call("lbmx_nn_conv3d_wgrad_upcat", P(tl), P(ts), P(tg), P(gw1), P(gb1), B, D, H, W, Cu, Cs, Co,
+         S())
+    call("lbmx_nn_conv3d_wgrad", P(cat), P(tg), P(gw2), P(gb2), B, D, H, W, Cu + Cs, Co, S())
+    gw_ref, gb_ref = N.conv3d_wgrad(x, g)
+    bw, bb = N.conv3d_wgrad(np.abs(x), np.abs(g))
+    for gw, gb in ((gw1, gb1), (gw2, gb2)):
+        assert np.all(np.abs(gw.cpu().numpy() - gw_ref) <= 2e-5 * bw + 1e-5)
+        assert np.all(np.abs(gb.cpu().numpy() - gb_ref) <= 2e-5 * bb + 1e-5)
+    assert np.abs(gw1.cpu().numpy() - gw2.cpu().numpy()).max() <= 1e-6 * (np.abs(gw_ref).max() + 1)
+    # rejected: odd extents, upsampled channels not a multiple of 16 below the total
+    from paper_1511_04633_amd import lbmx as LB
+    for args in ((B, D, H, W + 1, Cu, Cs), (B, D, H, W, 8, Cs + 24), (B, D, H, W, 0, Cu + Cs)):
+        with pytest.raises(LB.LbmxError):
+            call("lbmx_nn_conv3d_fwd_upcat", P(tl), P(ts), P(tw), P(tb), P(z1), None, *args, Co, S())
+        with pytest.raises(LB.LbmxError):
+            call("lbmx_nn_conv3d_wgrad_upcat", P(tl), P(ts), P(tg), P(gw1), None, *args, Co, S())
+
+
 def test_upcat_and_gated_gradients():
     """lbmx_nn_upcat equals up2 + concat (and the oracle's definitions) bit
     for bit; lbmx_nn_pool2_bwd_gate equals pool2 backward + add + SiLU
@@ -437,7 +485,10 @@ def test_unet_layers_elementwise_against_oracle():
     nf = nb = 0
     for rec in net.record:
         c = rec["conv"]
-        x = from_bf(rec["x"])
+        if rec["up"] is not None:  # decoder input read in place: [up2(low) | skip]
+            x = np.concatenate([N.up2(from_bf(rec["up"][0])), from_bf(rec["up"][1])], axis=-1)
+        else:
+            x = from_bf(rec["x"])
         w = W[id(c)]
         if rec["pass"] == "fwd":
             ref = N.conv3d(x, w, Bv[id(c)])
@@ -474,10 +525,10 @@ def test_unet_layers_elementwise_against_oracle():
 
 
 def test_unet_fused_matches_unfused():
-    """The fused training step (epilogues, upsample-and-concatenate, gated
-    pooling and upsampling gradients) against the separate kernels: the same
-    prediction bit for bit, and the same weight gradients up to the order of
-    the FP32 atomic additions."""
+    """The fused training step (epilogues, the decoder inputs read in place,
+    gated pooling and upsampling gradients) against the separate kernels:
+    the same prediction bit for bit, and the same weight gradients up to the
+    order of the FP32 atomic additions."""
     import torch
     from paper_1511_04633_amd import unet
 
