@@ -480,6 +480,23 @@ lbmx_status lbmx_nn_up2(const void *in, void *out, int32_t B, int32_t D, int32_t
 lbmx_status lbmx_nn_concat(void *a, void *b, void *out, int64_t nvox, int32_t Ca, int32_t Cb,
                            int32_t backward, void *stream);
 
+/* The network head and its loss in one pass (the convolution epilogue
+ * computes the loss, and the FP32 head output is never stored unless pred
+ * is not NULL): z = lbmx_nn_conv3d_fwd(in, w, bias) in FP32 registers,
+ * nvox = B D H W; for channels c < K, e = z[p][c] - target[p][c] (target
+ * FP32 [nvox][K]) and grad[p][c] = bf16(2 e / (nvox K)); grad[p][c] = 0 for
+ * K <= c < Co (grad BF16 [nvox][Co]); partial[0 .. npartial) receives
+ * per-block sums of e^2 (their sum / (nvox K) is the loss; entries past the
+ * last block are zeroed); pred (FP32 [nvox][Co]) receives z if not NULL.
+ * grad equals lbmx_nn_conv3d_fwd (FP32) followed by lbmx_nn_mse bit for bit;
+ * the partial sums differ only in FP64 summation order.  16 <= Ci, Co <=
+ * 1024, multiples of 16, 1 <= K <= Co, npartial >= 1, nvox Co < 2^31.
+ * EINVAL otherwise. */
+lbmx_status lbmx_nn_conv3d_mse(const void *in, const void *w, const float *bias, const float *target,
+                               int32_t K, void *grad, double *partial, int32_t npartial, float *pred,
+                               int32_t B, int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                               void *stream);
+
 /* Squared error of the first K of C channels of pred [nvox][C] against
  * target [nvox][K] (both FP32): grad [nvox][C] BF16 = 2 (pred - target) /
  * (nvox K) (0 for channels >= K); partial[0..npartial) receives per-block

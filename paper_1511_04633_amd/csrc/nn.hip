@@ -197,12 +197,26 @@ struct Epilogue {
     int split;
 };
 
+// The squared-error loss fused into a head convolution (k_conv_fwd with
+// LOSS): z = conv + bias stays FP32 in registers; for channels c < K,
+// e = z - target[p][c], grad[p][c] = bf16(2 e scale), 0 for c >= K; each
+// block writes the sum of its e^2 to partial[block] and block 0 clears
+// partial[blocks .. npartial); out (FP32 [.][Co]) receives z if not null.
+struct LossEp {
+    const float *target;
+    int K;
+    float scale;
+    bf *grad;
+    double *partial;
+    int npartial;
+};
+
 // Occupancy is register-bound: 3 waves per SIMD for one channel tile (no
-// spills; 4 would spill), 2 for two.
-template <int NCO>
-__global__ __launch_bounds__(FC_THREADS) __attribute__((amdgpu_waves_per_eu(NCO == 1 ? 3 : 2))) void
+// spills; 4 would spill), 2 for two and for the loss variant.
+template <int NCO, bool LOSS>
+__global__ __launch_bounds__(FC_THREADS) __attribute__((amdgpu_waves_per_eu(NCO == 1 && !LOSS ? 3 : 2))) void
 k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias, void *__restrict__ out,
-           int out_f32, Dims d, int nbx, int nby, int nbz, Epilogue ep)
+           int out_f32, Dims d, int nbx, int nby, int nbz, Epilogue ep, LossEp ls)
 {
     constexpr int WITEMS = 27 * NCO * 16 * 2;       // 16-byte pieces of the weight tile
     constexpr int WITERS = (WITEMS + FC_THREADS - 1) / FC_THREADS;
@@ -332,6 +346,7 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
 #pragma unroll
         for (int j = 0; j < NCO; ++j)
             acc[rr][j] = f4{0.f, 0.f, 0.f, 0.f};
+    double sq = 0.0;  // LOSS: this lane's sum of squared errors
 
     for (int i = threadIdx.x; i < NCO * 16 * 16 / 8; i += FC_THREADS)
         reinterpret_cast<uint4 *>(ws + 27 * NCO * 16 * 16)[i] = make_uint4(0, 0, 0, 0);
@@ -351,6 +366,23 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
         __syncthreads();
         if (item + 1 < nitems)
             load_round(bw.first + ((item + 1) / R) * bw.stride, ((item + 1) % R) * 16, !w_once);
+        // LOSS: this lane's targets (its 4 rows, channels kq 4 ..) are loaded
+        // before the last round's products, so their latency overlaps them
+        float tg[4][4];
+        if constexpr (LOSS) {
+            if (round + 1 == R) {
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const int g = wv * 4 + rr;
+                    const int x = x0 + col, y = y0 + g % FC_Y, z = z0 + g / FC_Y;
+                    const bool ok = x < d.W && y < d.H && z < d.D;
+                    const size_t p = ok ? size_t(((b * d.D + z) * d.H + y) * d.W + x) : 0;
+#pragma unroll
+                    for (int k = 0; k < 4; ++k)
+                        tg[rr][k] = ok && kq * 4 + k < ls.K ? ls.target[p * ls.K + kq * 4 + k] : 0.f;
+                }
+            }
+        }
 #pragma unroll
         for (int pr = 0; pr < 14; ++pr) {
             bf8v a[NCO];
@@ -388,6 +420,24 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
             f4 v = acc[rr][j];
             if (bias)
                 v += bj[j];
+            if constexpr (LOSS) {
+                if (out)
+                    *reinterpret_cast<f4 *>(reinterpret_cast<float *>(out) + p * Co + cb) = v;
+                float gv[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    gv[k] = 0.f;
+                    if (cb + k < ls.K) {
+                        const float e = v[k] - tg[rr][k];
+                        sq += double(e) * e;
+                        gv[k] = 2.f * e * ls.scale;
+                    }
+                }
+                *reinterpret_cast<uint2 *>(ls.grad + p * Co + cb) =
+                    make_uint2(uint32_t(f2bf(gv[0])) | (uint32_t(f2bf(gv[1])) << 16),
+                               uint32_t(f2bf(gv[2])) | (uint32_t(f2bf(gv[3])) << 16));
+                continue;
+            }
             if (out_f32) {
                 *reinterpret_cast<f4 *>(reinterpret_cast<float *>(out) + p * Co + cb) = v;
                 continue;
@@ -420,6 +470,24 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
 #pragma unroll
             for (int j = 0; j < NCO; ++j)
                 acc[rr][j] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+    if constexpr (LOSS) {
+        __shared__ double red[FC_THREADS / 64];
+        for (int o = 32; o > 0; o >>= 1)
+            sq += __shfl_xor(sq, o);
+        if (lane == 0)
+            red[wv] = sq;
+        __syncthreads();
+        const int blk = int(blockIdx.x + blockIdx.y * gridDim.x), nblk = int(gridDim.x * gridDim.y);
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+            for (int k = 0; k < FC_THREADS / 64; ++k)
+                t += red[k];
+            ls.partial[blk] = t;
+        }
+        if (blk == 0)
+            for (int i = nblk + int(threadIdx.x); i < ls.npartial; i += FC_THREADS)
+                ls.partial[i] = 0.0;
     }
 }
 
@@ -1134,9 +1202,9 @@ lbmx_status check_dims(int B, int D, int H, int W)
     return LBMX_OK;
 }
 
-template <int NCO>
+template <int NCO, bool LOSS = false>
 void launch_fwd(ConvIn src, const bf *w, const float *bias, void *out, int out_f32, Dims d, hipStream_t s,
-                Epilogue ep)
+                Epilogue ep, LossEp ls = LossEp{})
 {
     const int nbx = (d.W + FC_X - 1) / FC_X, nby = (d.H + FC_Y - 1) / FC_Y, nbz = (d.D + FC_Z - 1) / FC_Z;
     const unsigned bricks = unsigned(d.B * nbx * nby * nbz);
@@ -1147,7 +1215,8 @@ void launch_fwd(ConvIn src, const bf *w, const float *bias, void *out, int out_f
     // kept a multiple of 8 for the XCD-aware brick order.
     static const int per_cu = [] {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fwd<NCO>, FC_THREADS, 0) != hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fwd<NCO, LOSS>, FC_THREADS, 0) !=
+            hipSuccess)
             nb = 1;
         return nb < 1 ? 1 : nb;
     }();
@@ -1157,10 +1226,12 @@ void launch_fwd(ConvIn src, const bf *w, const float *bias, void *out, int out_f
         cus = 256;
     const unsigned resident = unsigned(per_cu) * unsigned(cus) / groups;
     unsigned grid = std::max(1u, std::min(bricks, resident));
+    if (LOSS)  // one partial sum per block
+        grid = std::max(1u, std::min(grid, unsigned(ls.npartial) / groups));
     if (grid >= 8)
         grid -= grid % 8;
-    hipLaunchKernelGGL(k_conv_fwd<NCO>, dim3(grid, groups), dim3(FC_THREADS), 0, s, src, w, bias, out,
-                       out_f32, d, nbx, nby, nbz, ep);
+    hipLaunchKernelGGL((k_conv_fwd<NCO, LOSS>), dim3(grid, groups), dim3(FC_THREADS), 0, s, src, w, bias, out,
+                       out_f32, d, nbx, nby, nbz, ep, ls);
 }
 
 // Rejects an upsample-and-concatenate input whose low part is malformed.
@@ -1236,6 +1307,30 @@ lbmx_status lbmx_nn_conv3d_fwd_ep(const void *in, const void *w, const float *bi
                 reinterpret_cast<bf *>(out2), split};
     return conv_fwd(ConvIn{reinterpret_cast<const bf *>(in), nullptr, 0}, w, bias, out, 0, B, D, H, W, Ci, Co,
                     stream, ep);
+}
+
+lbmx_status lbmx_nn_conv3d_mse(const void *in, const void *w, const float *bias, const float *target,
+                               int32_t K, void *grad, double *partial, int32_t npartial, float *pred,
+                               int32_t B, int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
+                               void *stream)
+{
+    lbmx_status st = check_dims(B, D, H, W);
+    if (st != LBMX_OK)
+        return st;
+    if (!in || !w || !target || !grad || !partial)
+        return fail(LBMX_EINVAL, "conv3d_mse: NULL tensor");
+    if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 1024 || K < 1 || K > Co ||
+        npartial < 1)
+        return fail(LBMX_EINVAL, "conv3d_mse: need Ci, Co multiples of 16 in [16, 1024], 1 <= K <= Co, "
+                                 "npartial >= 1");
+    const long long nvox = (long long)B * D * H * W;
+    if (nvox * Co >= (1LL << 31))
+        return fail(LBMX_EINVAL, "conv3d_mse: %lld voxels exceed 32-bit element indices", nvox);
+    LossEp ls{target, K, 1.0f / float(double(nvox) * K), reinterpret_cast<bf *>(grad), partial, npartial};
+    launch_fwd<1, true>(ConvIn{reinterpret_cast<const bf *>(in), nullptr, 0}, reinterpret_cast<const bf *>(w),
+                        bias, pred, 1, Dims{B, D, H, W, Ci, Co}, S(stream), Epilogue{}, ls);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
 }
 
 lbmx_status lbmx_nn_conv3d_fwd_upcat(const void *low, const void *skip, const void *w, const float *bias,

@@ -59,6 +59,8 @@ def nn():
                                          _i32, _i32, _i32, _vp],
             "lbmx_nn_conv3d_wgrad_upcat": [_vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32,
                                            _i32, _i32, _i32, _vp],
+            "lbmx_nn_conv3d_mse": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _i32, _i32,
+                                   _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_pool2_bwd_gate": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_up2_bwd_gate": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_conv3d_flip_many": [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_int64),
@@ -243,6 +245,40 @@ class UNet:
 
         s = stream_ptr()
         m = self.m
+        cache, h = self._trunk(cond, B)
+        pred = torch.empty((B, m ** 3, 16), dtype=torch.float32, device="cuda")
+        call("lbmx_nn_conv3d_fwd", P(h), P(self.head.wb), P(self.head.b), P(pred), 1, B, m, m, m,
+             self.head.ci, 16, s)
+        self._cache = (cache, h, B) if train else None
+        return pred
+
+    def forward_loss(self, cond, B, target, partial, pred=None, K=NOUT):
+        """Training forward whose head computes the squared-error loss in its
+        epilogue (fused; the unfused network runs forward + mse_loss):
+        target FP32 [B, m^3, K]; per-block sums of squared errors go to
+        partial (device FP64 [1024]); pred (FP32 [B, m^3, 16]) receives the
+        prediction if given.  Returns (BF16 gradient [B, m^3, 16] for
+        backward(), element count)."""
+        import torch
+
+        m = self.m
+        if not self.fused:
+            p = self.forward(cond, B, train=True)
+            if pred is not None:
+                pred.copy_(p)
+            return mse_loss(p, target, partial, K)
+        cache, h = self._trunk(cond, B)
+        grad = torch.empty((B, m ** 3, 16), dtype=torch.bfloat16, device="cuda")
+        call("lbmx_nn_conv3d_mse", P(h), P(self.head.wb), P(self.head.b), P(target), K, P(grad),
+             P(partial), partial.numel(), P(pred), B, m, m, m, self.head.ci, 16, stream_ptr())
+        self._cache = (cache, h, B)
+        return grad, B * m ** 3 * K
+
+    def _trunk(self, cond, B):
+        """Input construction, encoder and decoder; returns (layer cache, last
+        activation [B, m, m, m, 16])."""
+        s = stream_ptr()
+        m = self.m
         cache = []
         x = self._bf(B, m, m, m, NFEAT)
         call("lbmx_nn_make_input", P(cond), P(x), B, m, s)
@@ -275,11 +311,7 @@ class UNet:
                 cache.append({"kind": "upcat", "r": r, "cu": cu, "cs": cs})
                 h = self._conv(ca, cat, B, r, cache)
             h = self._conv(cb, h, B, r, cache)
-        pred = torch.empty((B, m ** 3, 16), dtype=torch.float32, device="cuda")
-        call("lbmx_nn_conv3d_fwd", P(h), P(self.head.wb), P(self.head.b), P(pred), 1, B, m, m, m,
-             self.head.ci, 16, s)
-        self._cache = (cache, h, B) if train else None
-        return pred
+        return cache, h
 
     # ---- backward ------------------------------------------------------------
     def backward(self, gpred):
@@ -493,8 +525,7 @@ def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=1e-3, seed=0
                      _vp(target.data_ptr() + j * sample_bytes), 1, V, NOUT, NOUT, 1, P(inv),
                      stream_ptr())
             cond = cond_tensor(log10_ra[idx], wall_type[idx])
-            pred = net.forward(cond, batch, train=True)
-            grad, cnt = mse_loss(pred, target, partials[k])
+            grad, cnt = net.forward_loss(cond, batch, target, partials[k])
             net.backward(grad)
             if step < warmup:
                 lr_t = lr * (step + 1) / warmup
@@ -544,8 +575,7 @@ def bench_step(batch=4, m=64, steps=20, warmup=3, fused=True):
     partial = torch.zeros(1024, dtype=torch.float64, device="cuda")
 
     def one():
-        pred = net.forward(cond, batch, train=True)
-        grad, _ = mse_loss(pred, target, partial)
+        grad, _ = net.forward_loss(cond, batch, target, partial)
         net.backward(grad)
         net.adam(1e-4)
 

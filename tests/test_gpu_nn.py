@@ -401,6 +401,56 @@ def test_conv_with_upcat_input_read_in_place(shape):
             call("lbmx_nn_conv3d_wgrad_upcat", P(tl), P(ts), P(tg), P(gw1), None, *args, Co, S())
 
 
+@pytest.mark.parametrize("shape,K,npart", [((2, 9, 10, 35), 4, 1024), ((1, 5, 4, 7), 6, 1024),
+                                           ((2, 8, 8, 32), 16, 8)])
+def test_head_convolution_with_fused_loss(shape, K, npart):
+    """lbmx_nn_conv3d_mse against lbmx_nn_conv3d_fwd (FP32 output) followed
+    by lbmx_nn_mse: prediction and BF16 gradient bit for bit, the loss up to
+    FP64 summation order; partial entries past the last block are cleared
+    (the buffer starts non-zero); fewer partials than resident blocks
+    (npart 8) shrinks the grid; and against the oracle."""
+    import torch
+    print(f"case: head conv + fused loss {shape} K={K} npartial={npart}", flush=True)
+    B, D, H, W = shape
+    ci, co = 16, 16
+    x, w, b = rnd((B, D, H, W, ci), 71), rnd((co, 27, ci), 72, 0.1), rnd((co,), 73)
+    nv = B * D * H * W
+    tgt = np.random.default_rng(74).standard_normal((nv, K))
+    tx, tw, tb, tt = to_bf(x), to_bf(w), to_f32(b), to_f32(tgt)
+    pred1 = torch.empty((nv, co), dtype=torch.float32, device="cuda")
+    grad1 = torch.empty((nv, co), dtype=torch.bfloat16, device="cuda")
+    part1 = torch.full((npart,), 7.0, dtype=torch.float64, device="cuda")
+    call("lbmx_nn_conv3d_mse", P(tx), P(tw), P(tb), P(tt), K, P(grad1), P(part1), npart, P(pred1),
+         B, D, H, W, ci, co, S())
+    pred2 = torch.empty((nv, co), dtype=torch.float32, device="cuda")
+    grad2 = torch.empty((nv, co), dtype=torch.bfloat16, device="cuda")
+    part2 = torch.zeros(64, dtype=torch.float64, device="cuda")
+    call("lbmx_nn_conv3d_fwd", P(tx), P(tw), P(tb), P(pred2), 1, B, D, H, W, ci, co, S())
+    call("lbmx_nn_mse", P(pred2), P(tt), P(grad2), P(part2), 64, nv, co, K, S())
+    assert np.array_equal(pred1.cpu().numpy(), pred2.cpu().numpy())
+    assert np.array_equal(bits_of(from_bf(grad1)), bits_of(from_bf(grad2)))
+    s1, s2 = part1.cpu().numpy().sum(), part2.cpu().numpy().sum()
+    assert abs(s1 - s2) <= 1e-12 * s2
+    # against the oracle: the prediction, then the loss on the GPU's own prediction
+    ref = N.conv3d(x, w, b).reshape(nv, co)
+    bnd = 2e-5 * N.conv3d(np.abs(x), np.abs(w), np.abs(b)).reshape(nv, co) + 1e-6
+    p1 = pred1.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(p1 - ref) <= bnd)
+    loss, g = N.mse(p1, tgt.astype(np.float32).astype(np.float64), K)
+    assert abs(s1 / (nv * K) - loss) <= 1e-6 * loss
+    assert np.all(np.abs(from_bf(grad1) - g) <= 2 ** -8 * np.abs(g) + 1e-12)
+    # without the prediction output: the same gradient
+    grad3 = torch.empty((nv, co), dtype=torch.bfloat16, device="cuda")
+    call("lbmx_nn_conv3d_mse", P(tx), P(tw), P(tb), P(tt), K, P(grad3), P(part1), npart, None,
+         B, D, H, W, ci, co, S())
+    assert np.array_equal(bits_of(from_bf(grad3)), bits_of(from_bf(grad1)))
+    from paper_1511_04633_amd import lbmx as LB
+    for k, n in ((0, npart), (co + 1, npart), (K, 0)):
+        with pytest.raises(LB.LbmxError):
+            call("lbmx_nn_conv3d_mse", P(tx), P(tw), P(tb), P(tt), k, P(grad3), P(part1), n, None,
+                 B, D, H, W, ci, co, S())
+
+
 def test_upcat_and_gated_gradients():
     """lbmx_nn_upcat equals up2 + concat (and the oracle's definitions) bit
     for bit; lbmx_nn_pool2_bwd_gate equals pool2 backward + add + SiLU
@@ -526,7 +576,8 @@ def test_unet_layers_elementwise_against_oracle():
 
 def test_unet_fused_matches_unfused():
     """The fused training step (epilogues, the decoder inputs read in place,
-    gated pooling and upsampling gradients) against the separate kernels:
+    the loss in the head's epilogue, gated pooling and upsampling
+    gradients) against the separate kernels:
     the same prediction bit for bit, and the same weight gradients up to the
     order of the FP32 atomic additions."""
     import torch
@@ -540,14 +591,17 @@ def test_unet_fused_matches_unfused():
     for fused in (True, False):
         net = unet.UNet(seed=7, m=m)
         net.fused = fused
-        pred = net.forward(cond, B, train=True)
+        pred = torch.empty((B, m ** 3, 16), dtype=torch.float32, device="cuda")
         part = torch.zeros(1024, dtype=torch.float64, device="cuda")
-        grad, _ = unet.mse_loss(pred, target, part)
+        grad, _ = net.forward_loss(cond, B, target, part, pred=pred)
         net.backward(grad)
         torch.cuda.synchronize()
         out.append((pred.cpu().numpy(), [(c.gw.cpu().numpy(), c.gb.cpu().numpy())
-                                          for c in net.convs()]))
+                                          for c in net.convs()], part.cpu().numpy().sum(),
+                    bits_of(from_bf(grad))))
     assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][3], out[1][3])  # the loss gradient, fused into the head or not
+    assert abs(out[0][2] - out[1][2]) <= 1e-12 * out[1][2]
     for (gw1, gb1), (gw2, gb2) in zip(out[0][1], out[1][1]):
         sc = np.abs(gw2).max() + 1e-30
         assert np.abs(gw1 - gw2).max() <= 1e-4 * sc
