@@ -213,19 +213,29 @@ struct LossEp {
 
 // Occupancy is register-bound: 3 waves per SIMD for one channel tile (no
 // spills; 4 would spill), 2 for two and for the loss variant.
-template <int NCO, bool LOSS>
-__global__ __launch_bounds__(FC_THREADS) __attribute__((amdgpu_waves_per_eu(NCO == 1 && !LOSS ? 3 : 2))) void
+//
+// KS > 1 (layers with several rounds on small grids): the block has KS
+// groups of FC_THREADS threads, each with its own LDS tiles; group g takes
+// rounds g, g + KS, ... of the same brick, which shortens the block's
+// serial chain of rounds KS times; at the end of a brick the other groups
+// add their sums into group 0's through LDS, and group 0 stores.
+constexpr int fc_waves(int nco, bool loss, int ks) { return nco == 1 && !loss && ks == 1 ? 3 : 2; }
+template <int NCO, bool LOSS, int KS>
+__global__ __launch_bounds__(FC_THREADS * KS) __attribute__((amdgpu_waves_per_eu(fc_waves(NCO, LOSS, KS)))) void
 k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias, void *__restrict__ out,
            int out_f32, Dims d, int nbx, int nby, int nbz, Epilogue ep, LossEp ls)
 {
     constexpr int WITEMS = 27 * NCO * 16 * 2;       // 16-byte pieces of the weight tile
     constexpr int WITERS = (WITEMS + FC_THREADS - 1) / FC_THREADS;
-    __shared__ __attribute__((aligned(16))) bf xs[FC_HVOX * 16];
-    __shared__ __attribute__((aligned(16))) bf ws[28 * NCO * 16 * 16];
+    __shared__ __attribute__((aligned(16))) bf xsa[KS][FC_HVOX * 16];
+    __shared__ __attribute__((aligned(16))) bf wsa[KS][28 * NCO * 16 * 16];
     __shared__ __attribute__((aligned(16))) bf zs[FC_ZERO];
+    __shared__ f4 red[KS > 1 ? (KS - 1) * 4 * NCO * FC_THREADS : 1];
+    const int tid = int(threadIdx.x) % FC_THREADS, kg = int(threadIdx.x) / FC_THREADS;
+    bf *const xs = xsa[kg], *const ws = wsa[kg];
     const int Ci = d.Ci, Co = d.Co;
     const int cs = Ci - src.cu;  // channel stride of src.in
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = tid & 63, wv = tid >> 6;
     const int col = lane & 15, kq = lane >> 4;
     const int h = kq >> 1, part = kq & 1;   // tap parity and channel half of this lane's K slice
     const int co0 = blockIdx.y * NCO * 16;
@@ -236,11 +246,11 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
         grid.at(j, FC_X, FC_Y, FC_Z, bb, xx, yy, zz);
     };
 
-    // This thread's input pieces i = threadIdx.x + k FC_THREADS (halo voxel
+    // This thread's input pieces i = tid + k FC_THREADS (halo voxel
     // i / 2, channel half i % 2): their element offsets from the brick's
     // first voxel; and its weight pieces' row offsets in w (-1: none).
     auto halo_of = [&](int k, int &hx, int &hy, int &hz) {
-        const int hv = (int(threadIdx.x) + k * FC_THREADS) >> 1, hrow = hv / FC_HX;
+        const int hv = (tid + k * FC_THREADS) >> 1, hrow = hv / FC_HX;
         hx = hv % FC_HX, hy = hrow % FC_HY, hz = hrow / FC_HY;
     };
     int rel[FC_XITERS], wrow[WITERS];
@@ -248,11 +258,11 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
     for (int k = 0; k < FC_XITERS; ++k) {
         int hx, hy, hz;
         halo_of(k, hx, hy, hz);
-        rel[k] = (((hz - 1) * d.H + (hy - 1)) * d.W + (hx - 1)) * cs + (threadIdx.x & 1) * 8;
+        rel[k] = (((hz - 1) * d.H + (hy - 1)) * d.W + (hx - 1)) * cs + (tid & 1) * 8;
     }
 #pragma unroll
     for (int k = 0; k < WITERS; ++k) {
-        const int i = threadIdx.x + k * FC_THREADS;
+        const int i = tid + k * FC_THREADS;
         const int row = i >> 1, tap = row / (NCO * 16), co = row % (NCO * 16);
         wrow[k] = i < WITEMS ? ((co0 + co) * 27 + tap) * Ci + (i & 1) * 8 : -1;
     }
@@ -275,18 +285,18 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
                 int hx, hy, hz;
                 halo_of(k, hx, hy, hz);
                 const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-                if (int(threadIdx.x) + k * FC_THREADS < FC_XITEMS && x >= 0 && x < d.W && y >= 0 &&
+                if (tid + k * FC_THREADS < FC_XITEMS && x >= 0 && x < d.W && y >= 0 &&
                     y < d.H && z >= 0 && z < d.D) {
                     const int l = ((b * Dl + (z >> 1)) * Hl + (y >> 1)) * Wl + (x >> 1);
                     v = *reinterpret_cast<const uint4 *>(src.low + size_t(l) * src.cu + c0 +
-                                                         (threadIdx.x & 1) * 8);
+                                                         (tid & 1) * 8);
                 }
                 xv[k] = v;
             }
         } else if (interior) {  // the whole halo is inside the volume
 #pragma unroll
             for (int k = 0; k < FC_XITERS; ++k)
-                if (int(threadIdx.x) + k * FC_THREADS < FC_XITEMS)
+                if (tid + k * FC_THREADS < FC_XITEMS)
                     xv[k] = *reinterpret_cast<const uint4 *>(base + rel[k]);
         } else {
 #pragma unroll
@@ -295,7 +305,7 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
                 int hx, hy, hz;
                 halo_of(k, hx, hy, hz);
                 const int x = x0 + hx - 1, y = y0 + hy - 1, z = z0 + hz - 1;
-                if (int(threadIdx.x) + k * FC_THREADS < FC_XITEMS && x >= 0 && x < d.W && y >= 0 &&
+                if (tid + k * FC_THREADS < FC_XITEMS && x >= 0 && x < d.W && y >= 0 &&
                     y < d.H && z >= 0 && z < d.D)
                     v = *reinterpret_cast<const uint4 *>(base + rel[k]);
                 xv[k] = v;
@@ -311,7 +321,7 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
     auto store_round = [&](bool with_w) {
 #pragma unroll
         for (int k = 0; k < FC_XITERS; ++k) {
-            const int i = threadIdx.x + k * FC_THREADS;
+            const int i = tid + k * FC_THREADS;
             if (i < FC_XITEMS)
                 *reinterpret_cast<uint4 *>(xs + fc_slot(i >> 1, i & 1, (i >> 1) % FC_HX)) = xv[k];
         }
@@ -319,7 +329,7 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
             return;
 #pragma unroll
         for (int k = 0; k < WITERS; ++k) {
-            const int i = threadIdx.x + k * FC_THREADS;
+            const int i = tid + k * FC_THREADS;
             if (i < WITEMS)
                 *reinterpret_cast<uint4 *>(ws + fc_slot(i >> 1, i & 1, (i >> 1) % 16)) = wt[k];
         }
@@ -348,24 +358,28 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
             acc[rr][j] = f4{0.f, 0.f, 0.f, 0.f};
     double sq = 0.0;  // LOSS: this lane's sum of squared errors
 
-    for (int i = threadIdx.x; i < NCO * 16 * 16 / 8; i += FC_THREADS)
+    for (int i = tid; i < NCO * 16 * 16 / 8; i += FC_THREADS)
         reinterpret_cast<uint4 *>(ws + 27 * NCO * 16 * 16)[i] = make_uint4(0, 0, 0, 0);
-    for (int i = threadIdx.x; i < FC_ZERO / 8; i += FC_THREADS)
+    for (int i = tid; i < FC_ZERO / 8; i += FC_THREADS)
         reinterpret_cast<uint4 *>(zs)[i] = make_uint4(0, 0, 0, 0);
     const BrickWalk bw = brick_walk(nbricks);
-    const int nitems = bw.count * R;  // (brick, round) pairs of this block
-    if (nitems > 0)
-        load_round(bw.first, 0, true);
+    const int NR = (R + KS - 1) / KS;  // steps per brick; group kg takes round kg + KS step
+    const int nitems = bw.count * NR;  // (brick, step) pairs of this block
+    auto round_of = [&](int it) { return kg + KS * (it % NR); };
+    if (nitems > 0 && round_of(0) < R)
+        load_round(bw.first, round_of(0) * 16, true);
     int b = 0, x0 = 0, y0 = 0, z0 = 0;
     for (int item = 0; item < nitems; ++item) {
-        const int round = item % R;
-        if (round == 0)
-            brick_at(bw.first + (item / R) * bw.stride, b, x0, y0, z0);
+        const int step = item % NR, round = round_of(item);
+        const bool active = round < R;  // false for a group left without a round (R % KS != 0)
+        if (step == 0)
+            brick_at(bw.first + (item / NR) * bw.stride, b, x0, y0, z0);
         __syncthreads();  // the previous round's operands are no longer read
-        store_round(!w_once || item == 0);
+        if (active)
+            store_round(!w_once || item == 0);
         __syncthreads();
-        if (item + 1 < nitems)
-            load_round(bw.first + ((item + 1) / R) * bw.stride, ((item + 1) % R) * 16, !w_once);
+        if (item + 1 < nitems && round_of(item + 1) < R)
+            load_round(bw.first + ((item + 1) / NR) * bw.stride, round_of(item + 1) * 16, !w_once);
         // LOSS: this lane's targets (its 4 rows, channels kq 4 ..) are loaded
         // before the last round's products, so their latency overlaps them
         float tg[4][4];
@@ -385,6 +399,8 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
         }
 #pragma unroll
         for (int pr = 0; pr < 14; ++pr) {
+            if (!active)
+                break;
             bf8v a[NCO];
 #pragma unroll
             for (int jj = 0; jj < NCO; ++jj)
@@ -397,8 +413,24 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
                     acc[rr][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[jj], bv, acc[rr][jj], 0, 0, 0);
             }
         }
-        if (round + 1 < R)
+        if (step + 1 < NR)
             continue;  // more input channels of this brick to accumulate
+        if constexpr (KS > 1) {
+            if (kg > 0)
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                    for (int j = 0; j < NCO; ++j)
+                        red[(((kg - 1) * 4 + rr) * NCO + j) * FC_THREADS + tid] = acc[rr][j];
+            __syncthreads();
+            if (kg == 0)
+                for (int g = 1; g < KS; ++g)
+#pragma unroll
+                    for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                        for (int j = 0; j < NCO; ++j)
+                            acc[rr][j] += red[(((g - 1) * 4 + rr) * NCO + j) * FC_THREADS + tid];
+        }
         f4 bj[NCO];
 #pragma unroll
         for (int j = 0; j < NCO; ++j) {
@@ -411,7 +443,7 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
         for (int rr = 0; rr < 4; ++rr) {
         const int g = wv * 4 + rr;
         const int x = x0 + col, y = y0 + g % FC_Y, z = z0 + g / FC_Y;
-        if (x >= d.W || y >= d.H || z >= d.D)
+        if (kg > 0 || x >= d.W || y >= d.H || z >= d.D)
             continue;
         const size_t p = size_t(((b * d.D + z) * d.H + y) * d.W + x);
 #pragma unroll
@@ -472,21 +504,21 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
                 acc[rr][j] = f4{0.f, 0.f, 0.f, 0.f};
     }
     if constexpr (LOSS) {
-        __shared__ double red[FC_THREADS / 64];
+        __shared__ double lred[FC_THREADS / 64];
         for (int o = 32; o > 0; o >>= 1)
             sq += __shfl_xor(sq, o);
         if (lane == 0)
-            red[wv] = sq;
+            lred[wv] = sq;
         __syncthreads();
         const int blk = int(blockIdx.x + blockIdx.y * gridDim.x), nblk = int(gridDim.x * gridDim.y);
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             double t = 0.0;
             for (int k = 0; k < FC_THREADS / 64; ++k)
-                t += red[k];
+                t += lred[k];
             ls.partial[blk] = t;
         }
         if (blk == 0)
-            for (int i = nblk + int(threadIdx.x); i < ls.npartial; i += FC_THREADS)
+            for (int i = nblk + tid; i < ls.npartial; i += FC_THREADS)
                 ls.partial[i] = 0.0;
     }
 }
@@ -1202,7 +1234,7 @@ lbmx_status check_dims(int B, int D, int H, int W)
     return LBMX_OK;
 }
 
-template <int NCO, bool LOSS = false>
+template <int NCO, bool LOSS = false, int KS = 1>
 void launch_fwd(ConvIn src, const bf *w, const float *bias, void *out, int out_f32, Dims d, hipStream_t s,
                 Epilogue ep, LossEp ls = LossEp{})
 {
@@ -1215,8 +1247,8 @@ void launch_fwd(ConvIn src, const bf *w, const float *bias, void *out, int out_f
     // kept a multiple of 8 for the XCD-aware brick order.
     static const int per_cu = [] {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fwd<NCO, LOSS>, FC_THREADS, 0) !=
-            hipSuccess)
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_fwd<NCO, LOSS, KS>, FC_THREADS * KS,
+                                                         0) != hipSuccess)
             nb = 1;
         return nb < 1 ? 1 : nb;
     }();
@@ -1230,8 +1262,8 @@ void launch_fwd(ConvIn src, const bf *w, const float *bias, void *out, int out_f
         grid = std::max(1u, std::min(grid, unsigned(ls.npartial) / groups));
     if (grid >= 8)
         grid -= grid % 8;
-    hipLaunchKernelGGL((k_conv_fwd<NCO, LOSS>), dim3(grid, groups), dim3(FC_THREADS), 0, s, src, w, bias, out,
-                       out_f32, d, nbx, nby, nbz, ep, ls);
+    hipLaunchKernelGGL((k_conv_fwd<NCO, LOSS, KS>), dim3(grid, groups), dim3(FC_THREADS * KS), 0, s, src, w,
+                       bias, out, out_f32, d, nbx, nby, nbz, ep, ls);
 }
 
 // Rejects an upsample-and-concatenate input whose low part is malformed.
@@ -1278,8 +1310,12 @@ lbmx_status conv_fwd(ConvIn src, const void *w, const float *bias, void *out, in
     // CU (small grids: more blocks hide more latency)
     const long long bricks =
         (long long)B * ((W + FC_X - 1) / FC_X) * ((H + FC_Y - 1) / FC_Y) * ((D + FC_Z - 1) / FC_Z);
+    // and two groups per block splitting the rounds when even one tile per
+    // block leaves at most one block per CU
     if ((Co / 16) % 2 == 0 && bricks * (Co / 32) >= 512)
         launch_fwd<2>(src, wb, bias, out, out_f32, d, s, ep);
+    else if (Ci >= 32 && bricks * (Co / 16) <= 256)
+        launch_fwd<1, false, 2>(src, wb, bias, out, out_f32, d, s, ep);
     else
         launch_fwd<1>(src, wb, bias, out, out_f32, d, s, ep);
     HIP_TRY(hipGetLastError());
