@@ -596,6 +596,7 @@ constexpr int WB_ONES = (3 * 6 + 2) * WB_X + 16;    // ones block: the bias slot
 constexpr int WB_ITASKS = WB_HROWS * (WB_X / 2) * 2;   // (halo row, x pair, channel half) = 576
 constexpr int WB_ITERS = (WB_ITASKS + 255) / 256;
 constexpr long long WG_TARGET_BLOCKS = 512;         // blocks per launch, all channel pairs
+constexpr long long WG_MIN_BRICKS = 4;              // bricks per block, at least (where there are)
 
 // 32-bit words (channel c of voxel A, channel c of voxel B) for the 8
 // channels of two 16-byte channel-last pieces, low voxel in the low half:
@@ -1491,10 +1492,12 @@ lbmx_status conv_wgrad(ConvIn src, const void *gout, float *gw, float *gb, int32
     const int nbx = (W + WB_X - 1) / WB_X, nby = (H + WB_Y - 1) / WB_Y, nbz = (D + WB_Z - 1) / WB_Z;
     const long long nbricks = (long long)B * nbx * nby * nbz;
     const int pairs = (Co / 16) * (Ci / 16);
-    // about two blocks per CU in total; each block sums several bricks in
-    // registers before its atomic adds
+    // about two blocks per CU in total; each block sums at least
+    // WG_MIN_BRICKS bricks in registers before its atomic adds (on small
+    // grids the atomics of many short blocks onto the same addresses cost
+    // more than the parallelism gains)
     long long gx = (WG_TARGET_BLOCKS + pairs - 1) / pairs;
-    if (gx > nbricks) gx = nbricks;
+    gx = std::min(gx, (nbricks + WG_MIN_BRICKS - 1) / WG_MIN_BRICKS);
     if (gx >= 8) gx -= gx % 8;  // x extent a multiple of 8: XCD-aware brick order
     if (gx < 1) gx = 1;
     hipLaunchKernelGGL(k_conv_wgrad, dim3(unsigned(gx), unsigned(pairs)), dim3(256), 0, S(stream), src,
