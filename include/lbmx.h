@@ -510,6 +510,17 @@ lbmx_status lbmx_nn_mse(const float *pred, const float *target, void *grad, doub
 lbmx_status lbmx_nn_adam(float *w, float *g, float *m, float *v, void *w_bf16, int64_t n, float lr,
                          float b1, float b2, float eps, int64_t step, float wd, void *stream);
 
+/* lbmx_nn_adam that also writes the flipped BF16 copies of `count` (<= 32)
+ * layers, as lbmx_nn_conv3d_flip_many of w_bf16 would (bit for bit): layer
+ * l's weights [co[l]][27][ci[l]] start at element offsets[l] of w, its
+ * flipped copy at the same offset of w_flip; the layers ascend, do not
+ * overlap and lie in [0, n); elements outside them get no flipped copy.
+ * w_bf16 and w_flip are required.  EINVAL otherwise. */
+lbmx_status lbmx_nn_adam_flip(float *w, float *g, float *m, float *v, void *w_bf16, void *w_flip,
+                              int64_t n, float lr, float b1, float b2, float eps, int64_t step, float wd,
+                              int32_t count, const int64_t *offsets, const int32_t *ci, const int32_t *co,
+                              void *stream);
+
 /* FP32 -> BF16 (round to nearest even). */
 lbmx_status lbmx_nn_to_bf16(const float *a, void *b, int64_t n, void *stream);
 

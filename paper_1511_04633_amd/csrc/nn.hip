@@ -1128,10 +1128,13 @@ __global__ __launch_bounds__(256) void k_mse_v(const float *__restrict__ pred, c
 
 // Adam with decoupled weight decay on FP32 master weights; refreshes the
 // BF16 copy (nullable) and clears the gradient.
+// With wt (not null), also the flipped BF16 copies of the layers in fs
+// (offsets ascending), as k_conv_flip_many of wb would write them.
 __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, float *__restrict__ g,
                                               float *__restrict__ m, float *__restrict__ v,
                                               bf *__restrict__ wb, long long n, float lr, float b1,
-                                              float b2, float eps, float c1, float c2, float wd)
+                                              float b2, float eps, float c1, float c2, float wd,
+                                              bf *__restrict__ wt, FlipSet fs)
 {
     for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (long long)gridDim.x * blockDim.x) {
@@ -1145,6 +1148,18 @@ __global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, float *__re
         if (wb)
             wb[i] = f2bf(wi);
         g[i] = 0.f;
+        if (wt) {
+            int l = 0;
+            while (l + 1 < fs.count && fs.off[l + 1] <= i)
+                ++l;
+            const long long local = i - fs.off[l];
+            const int Ci = fs.ci[l], Co = fs.co[l];
+            if (local >= 0 && local < (long long)Co * 27 * Ci) {
+                const int li = int(local);
+                const int ci = li % Ci, tap = (li / Ci) % 27, co = li / (27 * Ci);
+                wt[fs.off[l] + ((long long)ci * 27 + (26 - tap)) * Co + co] = f2bf(wi);
+            }
+        }
     }
 }
 
@@ -1447,22 +1462,43 @@ lbmx_status lbmx_nn_conv3d_flip(const void *w, void *wt, int32_t Ci, int32_t Co,
     return LBMX_OK;
 }
 
-lbmx_status lbmx_nn_conv3d_flip_many(const void *w, void *wt, int32_t count, const int64_t *offsets,
-                                     const int32_t *ci, const int32_t *co, void *stream)
+}  // extern "C"
+
+namespace {
+
+// The layer table of a flip; *most = the largest layer's element count.
+lbmx_status flip_set(int32_t count, const int64_t *offsets, const int32_t *ci, const int32_t *co,
+                     const char *what, FlipSet &fs, long long *most)
 {
-    if (!w || !wt || !offsets || !ci || !co || count < 1 || count > FLIP_MAX)
-        return fail(LBMX_EINVAL, "conv3d_flip_many: bad arguments (1 <= count <= %d)", FLIP_MAX);
-    FlipSet fs;
+    if (!offsets || !ci || !co || count < 1 || count > FLIP_MAX)
+        return fail(LBMX_EINVAL, "%s: bad layer table (1 <= count <= %d)", what, FLIP_MAX);
     fs.count = count;
-    long long most = 0;
+    *most = 0;
     for (int l = 0; l < count; ++l) {
-        if (ci[l] < 1 || co[l] < 1 || offsets[l] < 0)
-            return fail(LBMX_EINVAL, "conv3d_flip_many: layer %d has bad shape or offset", l);
+        if (ci[l] < 1 || co[l] < 1 || offsets[l] < 0 || (long long)co[l] * 27 * ci[l] >= (1LL << 31))
+            return fail(LBMX_EINVAL, "%s: layer %d has bad shape or offset", what, l);
         fs.off[l] = offsets[l];
         fs.ci[l] = ci[l];
         fs.co[l] = co[l];
-        most = std::max(most, (long long)co[l] * 27 * ci[l]);
+        *most = std::max(*most, (long long)co[l] * 27 * ci[l]);
     }
+    return LBMX_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+lbmx_status lbmx_nn_conv3d_flip_many(const void *w, void *wt, int32_t count, const int64_t *offsets,
+                                     const int32_t *ci, const int32_t *co, void *stream)
+{
+    if (!w || !wt)
+        return fail(LBMX_EINVAL, "conv3d_flip_many: NULL tensor");
+    FlipSet fs;
+    long long most = 0;
+    lbmx_status st = flip_set(count, offsets, ci, co, "conv3d_flip_many", fs, &most);
+    if (st != LBMX_OK)
+        return st;
     hipLaunchKernelGGL(k_conv_flip_many, dim3(blocks_for(most), unsigned(count)), dim3(256), 0, S(stream),
                        reinterpret_cast<const bf *>(w), reinterpret_cast<bf *>(wt), fs);
     HIP_TRY(hipGetLastError());
@@ -1632,7 +1668,33 @@ lbmx_status lbmx_nn_adam(float *w, float *g, float *m, float *v, void *w_bf16, i
     const float c1 = float(1.0 / (1.0 - std::pow(double(b1), double(step))));
     const float c2 = float(1.0 / (1.0 - std::pow(double(b2), double(step))));
     hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, S(stream), w, g, m, v,
-                       reinterpret_cast<bf *>(w_bf16), (long long)n, lr, b1, b2, eps, c1, c2, wd);
+                       reinterpret_cast<bf *>(w_bf16), (long long)n, lr, b1, b2, eps, c1, c2, wd,
+                       static_cast<bf *>(nullptr), FlipSet{});
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_adam_flip(float *w, float *g, float *m, float *v, void *w_bf16, void *w_flip,
+                              int64_t n, float lr, float b1, float b2, float eps, int64_t step, float wd,
+                              int32_t count, const int64_t *offsets, const int32_t *ci, const int32_t *co,
+                              void *stream)
+{
+    if (!w || !g || !m || !v || !w_bf16 || !w_flip || n < 0 || step < 1)
+        return fail(LBMX_EINVAL, "adam_flip: bad arguments");
+    FlipSet fs;
+    long long most = 0;
+    lbmx_status st = flip_set(count, offsets, ci, co, "adam_flip", fs, &most);
+    if (st != LBMX_OK)
+        return st;
+    for (int l = 0; l < count; ++l)
+        if ((l > 0 && offsets[l] < offsets[l - 1] + (long long)co[l - 1] * 27 * ci[l - 1]) ||
+            offsets[l] + (long long)co[l] * 27 * ci[l] > n)
+            return fail(LBMX_EINVAL, "adam_flip: layers overlap, are not ascending or exceed n");
+    const float c1 = float(1.0 / (1.0 - std::pow(double(b1), double(step))));
+    const float c2 = float(1.0 / (1.0 - std::pow(double(b2), double(step))));
+    hipLaunchKernelGGL(k_adam, dim3(blocks_for(n)), dim3(256), 0, S(stream), w, g, m, v,
+                       reinterpret_cast<bf *>(w_bf16), (long long)n, lr, b1, b2, eps, c1, c2, wd,
+                       reinterpret_cast<bf *>(w_flip), fs);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }

@@ -61,6 +61,10 @@ def nn():
                                            _i32, _i32, _i32, _vp],
             "lbmx_nn_conv3d_mse": [_vp, _vp, _vp, _vp, _i32, _vp, _vp, _i32, _vp, _i32, _i32,
                                    _i32, _i32, _i32, _i32, _vp],
+            "lbmx_nn_adam_flip": [_vp, _vp, _vp, _vp, _vp, _vp, _i64, _f32, _f32, _f32, _f32, _i64,
+                                  _f32, _i32, ctypes.POINTER(ctypes.c_int64),
+                                  ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                  _vp],
             "lbmx_nn_pool2_bwd_gate": [_vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_up2_bwd_gate": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _vp],
             "lbmx_nn_conv3d_flip_many": [_vp, _vp, _i32, ctypes.POINTER(ctypes.c_int64),
@@ -434,16 +438,16 @@ class UNet:
                 g = gh
 
     def adam(self, lr, wd=0.0, b1=0.9, b2=0.999, eps=1e-8):
-        """One Adam step on every layer (as Conv.adam per layer, in three
-        launches over the flat buffers)."""
+        """One Adam step on every layer (as Conv.adam per layer, in two
+        launches over the flat buffers: the weights, with their BF16 and
+        flipped BF16 copies, and the biases)."""
         self.step_count += 1
         s = stream_ptr()
-        call("lbmx_nn_adam", P(self._fw), P(self._fgw), P(self._fmw), P(self._fvw), P(self._fwb),
-             self._fw.numel(), lr, b1, b2, eps, self.step_count, wd, s)
+        call("lbmx_nn_adam_flip", P(self._fw), P(self._fgw), P(self._fmw), P(self._fvw),
+             P(self._fwb), P(self._fwflip), self._fw.numel(), lr, b1, b2, eps, self.step_count, wd,
+             len(self.convs()), *self._flip_args, s)
         call("lbmx_nn_adam", P(self._fb), P(self._fgb), P(self._fmb), P(self._fvb), None,
              self._fb.numel(), lr, b1, b2, eps, self.step_count, 0.0, s)
-        call("lbmx_nn_conv3d_flip_many", P(self._fwb), P(self._fwflip), len(self.convs()),
-             *self._flip_args, s)
 
     # ---- persistence -----------------------------------------------------------
     def state(self):

@@ -256,9 +256,10 @@ def test_silu_add_mse_adam_layout_input():
 
 
 def test_flip_many_and_mse_paths():
-    """lbmx_nn_conv3d_flip_many equals the per-layer flips bit for bit; the
-    loss kernel's vector path (C % 8 == 0, K <= 8) and scalar path give the
-    oracle's loss and gradient."""
+    """lbmx_nn_conv3d_flip_many equals the per-layer flips bit for bit, and
+    lbmx_nn_adam_flip equals lbmx_nn_adam followed by it; the loss kernel's
+    vector path (C % 8 == 0, K <= 8) and scalar path give the oracle's loss
+    and gradient."""
     import ctypes
     import torch
     shapes = [(16, 16), (48, 16), (32, 96)]
@@ -276,6 +277,37 @@ def test_flip_many_and_mse_paths():
         call("lbmx_nn_conv3d_flip", P(tw), P(one), ci, co, S())
         o = int(offs[k])
         assert np.array_equal(from_bf(out)[o:o + ws[k].size], from_bf(one).reshape(-1))
+    # Adam writing the flipped copies equals Adam + flip_many, bit for bit;
+    # a tail of elements outside every layer gets no flipped copy
+    tab = ((ctypes.c_int64 * 3)(*offs.tolist()), (ctypes.c_int32 * 3)(*[c for c, _ in shapes]),
+           (ctypes.c_int32 * 3)(*[c for _, c in shapes]))
+    n = flat.size + 37
+    rng = np.random.default_rng(66)
+    w0, g0 = rng.standard_normal(n).astype(np.float32), rng.standard_normal(n).astype(np.float32)
+    res = []
+    for fused in (True, False):
+        tw, tg = to_f32(w0), to_f32(g0)
+        tm, tv = torch.zeros(n, device="cuda"), torch.zeros(n, device="cuda")
+        wb = torch.zeros(n, dtype=torch.bfloat16, device="cuda")
+        wf = torch.zeros(n, dtype=torch.bfloat16, device="cuda")
+        for step in (1, 2):
+            tg.copy_(to_f32(g0 * step))
+            if fused:
+                call("lbmx_nn_adam_flip", P(tw), P(tg), P(tm), P(tv), P(wb), P(wf), n, 1e-3, 0.9,
+                     0.999, 1e-8, step, 0.01, 3, *tab, S())
+            else:
+                call("lbmx_nn_adam", P(tw), P(tg), P(tm), P(tv), P(wb), n, 1e-3, 0.9, 0.999, 1e-8,
+                     step, 0.01, S())
+                call("lbmx_nn_conv3d_flip_many", P(wb), P(wf), 3, *tab, S())
+        res.append([bits_of(from_bf(wb)), bits_of(from_bf(wf)), tw.cpu().numpy(), tm.cpu().numpy()])
+    for a, b in zip(res[0], res[1]):
+        assert np.array_equal(a, b)
+    assert not np.any(res[0][1][flat.size:])  # the tail: no flipped copy
+    from paper_1511_04633_amd import lbmx as LB
+    bad = (ctypes.c_int64 * 3)(int(offs[1]), int(offs[0]), int(offs[2]))  # not ascending
+    with pytest.raises(LB.LbmxError):
+        call("lbmx_nn_adam_flip", P(tw), P(tg), P(tm), P(tv), P(wb), P(wf), n, 1e-3, 0.9, 0.999,
+             1e-8, 3, 0.0, 3, bad, tab[1], tab[2], S())
     for C, K in ((16, 4), (24, 5), (12, 3)):
         V = 3001
         pr, tg = np.random.default_rng(C).standard_normal((V, C)), np.random.default_rng(K).standard_normal((V, K))
