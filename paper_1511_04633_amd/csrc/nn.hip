@@ -596,7 +596,7 @@ constexpr int WB_ONES = (3 * 6 + 2) * WB_X + 16;    // ones block: the bias slot
 constexpr int WB_ITASKS = WB_HROWS * (WB_X / 2) * 2;   // (halo row, x pair, channel half) = 576
 constexpr int WB_ITERS = (WB_ITASKS + 255) / 256;
 constexpr long long WG_TARGET_BLOCKS = 512;         // blocks per launch, all channel pairs
-constexpr long long WG_MIN_BRICKS = 4;              // bricks per block, at least (where there are)
+constexpr long long WG_MIN_BRICKS = 3;              // bricks per block, at least (where there are)
 
 // 32-bit words (channel c of voxel A, channel c of voxel B) for the 8
 // channels of two 16-byte channel-last pieces, low voxel in the low half:
