@@ -9,24 +9,27 @@
 //
 // Convolution = implicit GEMM on the matrix cores: out[p][co] =
 // sum_{tap, ci} W[co][tap][ci] in[p + off(tap)][ci] with M = co, N = voxels,
-// K = (tap, ci), FP32 accumulation.  Both convolution kernels work on bricks
-// of 16 x 4 x 4 voxels staged in LDS, so that every MFMA operand is one
-// aligned LDS read and each staged element serves all 27 taps:
+// K = (tap, ci), FP32 accumulation.  Both convolution kernels run on
+// v_mfma_f32_16x16x32_bf16 (gfx950) over bricks of 16 x 4 x 4 voxels staged
+// in LDS, so that every MFMA operand is one aligned 16-byte LDS read and each
+// staged element serves all 27 taps; blocks walk the bricks in an XCD-aware
+// order (brick_walk):
 //   - forward (and the data gradient, the same convolution of the output
 //     gradient with the flipped, transposed weights W'[ci][26-tap][co] =
 //     W[co][tap][ci]): a block stages its brick's input with a one-voxel halo
-//     and the weights of all taps per 16 input channels, channel-last, and
-//     runs v_mfma_f32_16x16x32_bf16 (gfx950), whose K = 32 covers two taps of
-//     the 16 channels; details at k_conv_fwd;
+//     and the weights of all taps per 16 input channels, channel-last; K = 32
+//     covers two taps of the 16 channels; the epilogue can apply SiLU, its
+//     derivative, a channel split or the squared-error loss; the input can be
+//     a decoder's upsampled-and-concatenated tensor read in place; details
+//     at k_conv_fwd;
 //   - weight gradient: a block owns one (output-channel tile, input-channel
 //     tile) pair, walks the bricks, stages output gradient and input halo
-//     transposed to [channel][voxel], and accumulates all 27 taps with
-//     v_mfma_f32_16x16x16_bf16 (the bias gradient is one more MFMA against
-//     ones); the block's sums are added to the global gradient atomically;
-//     details at k_conv_wgrad.
-// MFMA operand layout (checked on the device): for the 16x16x16 form lane l
-// holds A[l%16][4(l/16)+j] and B[4(l/16)+j][l%16], j < 4, and gets
-// D[4(l/16)+j][l%16]; the 16x16x32 form holds 8 consecutive k per lane.
+//     transposed to [channel][voxel]; K = 32 covers two brick rows of voxels;
+//     the bias gradient is one more MFMA against ones; the block's sums are
+//     added to the global gradient atomically; details at k_conv_wgrad.
+// MFMA operand layout of v_mfma_f32_16x16x32_bf16 (checked on the device):
+// lane l holds A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. 8(l/16)+7][l%16]
+// and gets D[4(l/16)+j][l%16], j < 4.
 #include <hip/hip_bf16.h>
 #include <hip/hip_runtime.h>
 
