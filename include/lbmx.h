@@ -539,6 +539,18 @@ lbmx_status lbmx_nn_add(const void *a, const void *b, void *out, int64_t n, void
 lbmx_status lbmx_nn_layout(const float *a, float *b, int32_t B, int64_t V, int32_t K, int32_t C,
                            int32_t to_channel_last, const float *scale, void *stream);
 
+/* lbmx_nn_layout (channel-first a [B][K][m^3] -> channel-last b [B][m^3][C])
+ * on a cubic grid, transformed by a symmetry of the cavity: output voxel
+ * (x, y, z) (x fastest) takes input voxel (x', y', z') with x' = m - 1 - x if
+ * flip & 1, y' likewise if flip & 2, z' if flip & 4; channel k is multiplied
+ * by signs[k] (host array of K floats) and scale[k] (device, may be NULL).
+ * For the fields (u, v, w, theta) of the cavity (Sec. 2): flip 1 with signs
+ * (-1, 1, 1, 1) is the spanwise mirror, flip 7 with (-1, -1, -1, -1) the
+ * inversion about the centre (hot and cold walls exchanged, theta negated).
+ * 1 <= K <= min(C, 8), 0 <= flip <= 7.  EINVAL otherwise. */
+lbmx_status lbmx_nn_layout_flip(const float *a, float *b, int32_t B, int32_t m, int32_t K, int32_t C,
+                                int32_t flip, const float *signs, const float *scale, void *stream);
+
 const char *lbmx_strerror(lbmx_status s);
 const char *lbmx_last_error(void);
 

@@ -1229,6 +1229,36 @@ __global__ __launch_bounds__(256) void k_cl_to_cf(const float *__restrict__ a, f
     }
 }
 
+// Channel-first [B][K][m^3] -> channel-last [B][m^3][C] (first K of C
+// channels) on a cubic grid, with axis flips and per-channel signs: output
+// voxel (x, y, z) takes input voxel (x', y', z'), x' = m - 1 - x if flip & 1
+// (y: & 2, z: & 4), else x; channel k times sign[k] * scale[k].
+struct ChannelSigns {
+    float s[8];
+};
+__global__ __launch_bounds__(256) void k_cf_to_cl_flip(const float *__restrict__ a, float *__restrict__ b,
+                                                       int B, int m, int K, int C, int flip, ChannelSigns sg,
+                                                       const float *__restrict__ scale)
+{
+    const long long V = (long long)m * m * m;
+    const long long n = (long long)B * V * C;
+    for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (long long)gridDim.x * blockDim.x) {
+        const int c = int(i % C);
+        const long long v = (i / C) % V, bb = i / (C * V);
+        if (c >= K) {
+            b[i] = 0.f;
+            continue;
+        }
+        int x = int(v % m), y = int((v / m) % m), z = int(v / ((long long)m * m));
+        if (flip & 1) x = m - 1 - x;
+        if (flip & 2) y = m - 1 - y;
+        if (flip & 4) z = m - 1 - z;
+        const long long vs = ((long long)z * m + y) * m + x;
+        b[i] = a[(bb * K + c) * V + vs] * sg.s[c] * (scale ? scale[c] : 1.f);
+    }
+}
+
 // out = a + b (BF16, computed in FP32).
 __global__ __launch_bounds__(256) void k_add(const bf *__restrict__ a, const bf *__restrict__ b,
                                              bf *__restrict__ out, long long n)
@@ -1729,6 +1759,21 @@ lbmx_status lbmx_nn_add(const void *a, const void *b, void *out, int64_t n, void
         return fail(LBMX_EINVAL, "add: bad arguments");
     hipLaunchKernelGGL(k_add, dim3(blocks_for(n)), dim3(256), 0, S(stream), reinterpret_cast<const bf *>(a),
                        reinterpret_cast<const bf *>(b), reinterpret_cast<bf *>(out), (long long)n);
+    HIP_TRY(hipGetLastError());
+    return LBMX_OK;
+}
+
+lbmx_status lbmx_nn_layout_flip(const float *a, float *b, int32_t B, int32_t m, int32_t K, int32_t C,
+                                int32_t flip, const float *signs, const float *scale, void *stream)
+{
+    if (!a || !b || B < 1 || m < 1 || K < 1 || K > 8 || K > C || flip < 0 || flip > 7 || !signs)
+        return fail(LBMX_EINVAL, "layout_flip: bad arguments (1 <= K <= min(C, 8), 0 <= flip <= 7)");
+    ChannelSigns sg{};
+    for (int k = 0; k < K; ++k)
+        sg.s[k] = signs[k];
+    const long long n = (long long)B * m * m * m * C;
+    hipLaunchKernelGGL(k_cf_to_cl_flip, dim3(blocks_for(n)), dim3(256), 0, S(stream), a, b, B, m, K, C, flip,
+                       sg, scale);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }

@@ -41,7 +41,7 @@ SYMBOLS = [
     "lbmx_nn_adam", "lbmx_nn_to_bf16", "lbmx_nn_make_input", "lbmx_nn_add", "lbmx_nn_layout",
     "lbmx_nn_conv3d_fwd_ep", "lbmx_nn_upcat", "lbmx_nn_pool2_bwd_gate", "lbmx_nn_up2_bwd_gate",
     "lbmx_nn_conv3d_flip_many", "lbmx_nn_conv3d_fwd_upcat", "lbmx_nn_conv3d_wgrad_upcat",
-    "lbmx_nn_conv3d_mse", "lbmx_nn_adam_flip",
+    "lbmx_nn_conv3d_mse", "lbmx_nn_adam_flip", "lbmx_nn_layout_flip",
 ]
 BATCH_STATE = {0: "active", 1: "converged", 2: "max_steps", 3: "diverged"}
 

@@ -52,6 +52,8 @@ def nn():
             "lbmx_nn_make_input": [_vp, _vp, _i32, _i32, _vp],
             "lbmx_nn_add": [_vp, _vp, _vp, _i64, _vp],
             "lbmx_nn_layout": [_vp, _vp, _i32, _i64, _i32, _i32, _i32, _vp, _vp],
+            "lbmx_nn_layout_flip": [_vp, _vp, _i32, _i32, _i32, _i32, _i32,
+                                    ctypes.POINTER(ctypes.c_float), _vp, _vp],
             "lbmx_nn_conv3d_fwd_ep": [_vp, _vp, _vp, _vp, _vp, _vp, _vp, _i32, _i32, _i32, _i32,
                                       _i32, _i32, _i32, _vp],
             "lbmx_nn_upcat": [_vp, _vp, _vp, _i32, _i32, _i32, _i32, _i32, _i32, _vp],
@@ -489,13 +491,51 @@ def mse_loss(pred, target_cl, partial, K=NOUT):
     return grad, nv * K
 
 
+# The cavity's symmetries (Sec. 2) acting on the fields (u, v, w, theta) of
+# a node-centred m^3 grid [z][y][x]: (axis flips for lbmx_nn_layout_flip,
+# per-channel signs).  The walls and gravity are symmetric under the
+# spanwise mirror x -> H - x (u odd); the inversion about the centre
+# exchanges the hot and cold walls (theta_h = -theta_c), reverses gravity's
+# axis and maps each linear wall profile (Eqs. 9-10) to minus itself, so u
+# and theta are odd under it.  Together with the identity and their product
+# they form the group the training augmentation draws from.
+SYMMETRIES = (
+    (0, (1.0, 1.0, 1.0, 1.0)),      # identity
+    (1, (-1.0, 1.0, 1.0, 1.0)),     # x mirror
+    (7, (-1.0, -1.0, -1.0, -1.0)),  # inversion about the centre
+    (6, (1.0, -1.0, -1.0, -1.0)),   # both
+)
+
+
+def transform_fields(f, g):
+    """Symmetry g of SYMMETRIES applied to host fields [..., 4, m, m, m]
+    (z, y, x): the reference for the device gather and the dataset check."""
+    flip, signs = SYMMETRIES[g]
+    out = np.asarray(f)
+    for bit, ax in ((1, -1), (2, -2), (4, -3)):
+        if flip & bit:
+            out = np.flip(out, axis=ax)
+    return out * np.array(signs).reshape((4, 1, 1, 1))
+
+
+def field_asymmetry(fields):
+    """max |T f - f| / max |f| over the set (fields [N, 4, m, m, m]) for each
+    non-identity symmetry T: how far the steady fields already are
+    symmetric (the augmentation adds information only where they are not)."""
+    top = float(np.abs(fields).max()) or 1.0
+    return {g: float(np.abs(transform_fields(fields, g) - fields).max()) / top
+            for g in range(1, len(SYMMETRIES))}
+
+
 def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=1e-3, seed=0, log=None,
-          warmup=None):
+          warmup=None, augment=True):
     """Fit the network to steady fields [N, 4, m, m, m] (channel-first FP32;
     velocities already divided by u_c).  Per-channel target scales are the
     fields' standard deviations; the learning rate rises linearly over
     `warmup` steps (default 5 % of the run, at least 10) and then follows a
-    cosine decay."""
+    cosine decay.  With augment, every sample of every step is transformed by
+    a symmetry drawn uniformly from SYMMETRIES while it is gathered into the
+    target (lbmx_nn_layout_flip), the condition (Ra, wall type) unchanged."""
     import time
 
     import torch
@@ -514,6 +554,8 @@ def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=1e-3, seed=0
     per_epoch = N // batch
     partials = torch.zeros((per_epoch, 1024), dtype=torch.float64, device="cuda")
     rng = np.random.default_rng(seed)
+    arng = np.random.default_rng(seed + 1)  # symmetry draws
+    sym = [(flip, (ctypes.c_float * NOUT)(*signs)) for flip, signs in SYMMETRIES]
     nsteps = epochs * per_epoch
     if warmup is None:
         warmup = max(10, nsteps // 20)
@@ -525,9 +567,10 @@ def train(net, fields, log10_ra, wall_type, epochs=300, batch=4, lr=1e-3, seed=0
         for k in range(per_epoch):
             idx = order[k * batch:(k + 1) * batch]
             for j, i in enumerate(idx):
-                call("lbmx_nn_layout", _vp(dev_fields.data_ptr() + int(i) * sample_bytes),
-                     _vp(target.data_ptr() + j * sample_bytes), 1, V, NOUT, NOUT, 1, P(inv),
-                     stream_ptr())
+                flip, signs = sym[int(arng.integers(len(sym)))] if augment else sym[0]
+                call("lbmx_nn_layout_flip", _vp(dev_fields.data_ptr() + int(i) * sample_bytes),
+                     _vp(target.data_ptr() + j * sample_bytes), 1, m, NOUT, NOUT, flip, signs,
+                     P(inv), stream_ptr())
             cond = cond_tensor(log10_ra[idx], wall_type[idx])
             grad, cnt = net.forward_loss(cond, batch, target, partials[k])
             net.backward(grad)

@@ -39,8 +39,10 @@ def train_main(a):
         raise RuntimeError("no usable steady fields to train on")
     net = unet.UNet(seed=a.net_seed, m=64)
     log(f"U-Net parameters: {net.nparams()}")
+    asym = unet.field_asymmetry(ds["fields"])
+    log(f"steady fields' asymmetry (x mirror, inversion, both): {asym}")
     res = unet.train(net, ds["fields"], ds["log10_ra"], ds["wall_type"], epochs=a.epochs,
-                     batch=a.batch, lr=a.lr, log=log)
+                     batch=a.batch, lr=a.lr, log=log, augment=not a.no_augment)
     st = net.state()
     st["log10_ra"] = ds["log10_ra"]
     st["wall_type"] = ds["wall_type"]
@@ -48,6 +50,7 @@ def train_main(a):
     np.savez_compressed(a.out, **st)
     print(json.dumps({"dataset_s": round(t_data, 2), "dataset": ds["summary"],
                       "params": net.nparams(), "epochs": a.epochs, "batch": a.batch,
+                      "augment": not a.no_augment, "asymmetry": asym,
                       "train_s": round(res["seconds"], 2), "steps": res["steps"],
                       "loss_first": res["loss"][0], "loss_last": res["loss"][-1]}), flush=True)
 
@@ -165,6 +168,8 @@ def main(argv=None):
     t.add_argument("--net-seed", type=int, default=0)
     t.add_argument("--max-steps", type=int, default=300_000)
     t.add_argument("--tune-cache", default=None)
+    t.add_argument("--no-augment", action="store_true",
+                   help="train without the symmetry augmentation")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--ra", default="2e4,3e5,8e5")

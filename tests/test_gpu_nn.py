@@ -483,6 +483,32 @@ def test_head_convolution_with_fused_loss(shape, K, npart):
                  B, D, H, W, ci, co, S())
 
 
+def test_layout_with_symmetry_transform():
+    """lbmx_nn_layout_flip against unet.transform_fields (the host reference,
+    itself pinned to the oracle's fields on the CPU) followed by the
+    channel-last layout and the per-channel scale, bit for bit, for every
+    element of the training symmetry group; channels past K are zero."""
+    import ctypes
+    import torch
+    from paper_1511_04633_amd import unet
+    B, m, K, C = 2, 6, 4, 8
+    a = np.random.default_rng(91).standard_normal((B, K, m, m, m)).astype(np.float32)
+    sc = np.array([0.5, 2.0, -1.5, 3.0], np.float32)
+    ta, tsc = to_f32(a), to_f32(sc)
+    for g, (flip, signs) in enumerate(unet.SYMMETRIES):
+        out = torch.full((B, m ** 3, C), 7.0, dtype=torch.float32, device="cuda")
+        call("lbmx_nn_layout_flip", P(ta), P(out), B, m, K, C, flip,
+             (ctypes.c_float * K)(*signs), P(tsc), S())
+        ref = np.zeros((B, m ** 3, C), np.float32)
+        t = unet.transform_fields(a, g).astype(np.float32)  # [B, K, z, y, x]
+        ref[..., :K] = t.reshape(B, K, -1).transpose(0, 2, 1) * sc
+        assert np.array_equal(out.cpu().numpy(), ref), g
+    from paper_1511_04633_amd import lbmx as LB
+    with pytest.raises(LB.LbmxError):
+        call("lbmx_nn_layout_flip", P(ta), P(out), B, m, K, C, 8, (ctypes.c_float * K)(*signs),
+             None, S())
+
+
 def test_upcat_and_gated_gradients():
     """lbmx_nn_upcat equals up2 + concat (and the oracle's definitions) bit
     for bit; lbmx_nn_pool2_bwd_gate equals pool2 backward + add + SiLU
@@ -738,7 +764,9 @@ def test_unet_gradients_against_oracle():
 
 def test_unet_training_reduces_loss():
     """A few Adam steps on one synthetic sample lower the loss (the training
-    loop runs entirely through the library kernels)."""
+    loop runs entirely through the library kernels).  Without the symmetry
+    augmentation: these synthetic targets (w even about the centre) are not
+    the cavity's symmetric fields."""
     from paper_1511_04633_amd import unet
 
     m = 16
@@ -749,5 +777,5 @@ def test_unet_training_reduces_loss():
     fields[:, 3] = th
     fields[:, 2] = 0.1 * np.sin(np.pi * yy)[None, :, None]
     hist = unet.train(net, fields, np.array([3.5, 4.0, 5.0, 5.5]), np.array([1, 2, 3, 1]),
-                      epochs=40, batch=2, lr=1e-3)["loss"]
+                      epochs=40, batch=2, lr=1e-3, augment=False)["loss"]
     assert hist[-1] < 0.2 * hist[0], hist

@@ -443,6 +443,51 @@ def test_x_mirror_symmetry(wall_type):
     assert np.abs(rho - flip(rho)).max() < 1e-15
 
 
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
+def test_centre_inversion_symmetry(wall_type):
+    """Under the inversion (x, y, z) -> (H - x, H - y, H - z) the hot and cold
+    walls exchange (theta_h = -theta_c), gravity's axis reverses and the
+    linear wall profiles of Eqs. 9-10 are odd about the centre; the
+    Boussinesq force is odd in theta (theta_ref = 0), so the evolution from
+    rest without noise is symmetric: u and theta odd, rho even.  It fails for
+    a linear profile off the centre (y instead of y + 1/2), a force with a
+    non-zero reference temperature, or bounce-back placing the two walls of an
+    axis differently."""
+    n = 10
+    o = O.Oracle(n, wall_type, ra=1e5)
+    o.step(300)
+    rho, ux, uy, uz, th = o.macro()
+    assert np.abs(uz).max() > 1e-4
+    inv = lambda a: a[::-1, ::-1, ::-1]
+    scale = np.abs(np.stack([ux, uy, uz])).max()
+    for a in (ux, uy, uz):
+        assert np.abs(a + inv(a)).max() < 1e-12 * scale
+    assert np.abs(th + inv(th)).max() < 1e-13
+    assert np.abs(rho - inv(rho)).max() < 1e-14
+
+
+@pytest.mark.parametrize("wall_type", [1, 2, 3])
+def test_training_symmetries_leave_the_oracle_fields_unchanged(wall_type):
+    """The symmetry group the network's training draws from (axis flips and
+    signs of u, v, w, theta in unet.SYMMETRIES) maps the oracle's fields from
+    rest onto themselves for every wall type: the table's axes and signs are
+    the physics' (a wrong axis or sign moves a field by its own size)."""
+    from paper_1511_04633_amd import unet
+    o = O.Oracle(10, wall_type, ra=1e5)
+    o.step(300)
+    rho, ux, uy, uz, th = o.macro()
+    f = np.stack([ux, uy, uz, th])  # [4, z, y, x]
+    top = np.abs(f).max()
+    for g in range(len(unet.SYMMETRIES)):
+        assert np.abs(unet.transform_fields(f, g) - f).max() < 1e-12 * top, g
+    assert max(unet.field_asymmetry(f[None]).values()) < 1e-12
+    # the group: every element is its own inverse, mirror x inversion = both
+    for g in range(4):
+        assert np.array_equal(unet.transform_fields(unet.transform_fields(f, g), g), f)
+    assert np.array_equal(unet.transform_fields(unet.transform_fields(f, 1), 2),
+                          unet.transform_fields(f, 3))
+
+
 def _decay_ratio(n, ra, kind, t0=100, t1=1100):
     """Measured decay rate of a sine mode of wavelength n in a periodic box,
     divided by (coefficient * k^2) with the coefficient the oracle derived."""
