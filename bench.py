@@ -12,6 +12,10 @@ roofline: algorithmic bytes per launch (26 populations read + written per
 node, 208 B at FP32) over the average kernel time from HIP events recorded
 on the stream the kernels run on, against the 8 TB/s HBM peak.
 cpu_baseline: the FP64 CPU oracle timed on a bounded sample (64^3, same case).
+cpu_oracle_detail: the host (CPU model, logical CPUs), the oracle with one
+thread on the same 64^3 sample, and the 16^3, Ra 1e3, Type 1 cavity for
+2000 steps with one thread and with all threads (child processes with
+OMP_NUM_THREADS set, no GPU use).
 time_to_steady: 128^3, Ra 1e5, FP32, wall types 1-3, wall time to |dNu_3D| <
 1e-6 per 1000 steps from rest, from the shipped U-Net's predicted fields
 (warm start; inference and initialisation included), and by grid sequencing
@@ -54,6 +58,58 @@ def cpu_baseline(seconds: float, n: int = 64, ra: float = 1e6, wall_type: int = 
     return {"value": round(n ** 3 * steps / dt / 1e6, 3), "unit": "MLUPS",
             "cores": ora.threads(), "kind": "oracle",
             "sample": f"FP64 oracle, {n}^3 Type {wall_type} Ra {ra:g}, {steps} steps in {dt:.1f} s"}
+
+
+def _oracle_timing_child(n: int, ra: float, wall_type: int, steps: int, seconds: float):
+    """Runs in a child process (no GPU): the oracle's MLUPS for `steps`
+    steps, or for about `seconds` when steps = 0; prints one JSON line."""
+    from oracle import oracle as ora
+    from paper_1511_04633_amd import inputs
+
+    o = ora.Oracle(n, wall_type, ra=ra, theta0=inputs.theta_noise(n, 20151115))
+    o.step(1)
+    done, t0 = 0, time.perf_counter()
+    if steps:
+        o.step(steps)
+        done = steps
+    else:
+        while time.perf_counter() - t0 < seconds:
+            o.step(5)
+            done += 5
+    dt = time.perf_counter() - t0
+    print(json.dumps({"threads": ora.threads(), "steps": done, "seconds": round(dt, 3),
+                      "mlups": round(n ** 3 * done / dt / 1e6, 3)}), flush=True)
+
+
+def cpu_oracle_detail(seconds: float, ra: float, wall_type: int):
+    """Host description and one-thread / all-thread oracle timings, each in a
+    child process started with OMP_NUM_THREADS (the oracle's OpenMP runtime
+    reads it once)."""
+    import subprocess
+
+    def child(threads, n, ra_, wt, steps, secs):
+        env = dict(os.environ)
+        if threads:
+            env["OMP_NUM_THREADS"] = str(threads)
+        r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--oracle-timing",
+                            str(n), repr(ra_), str(wt), str(steps), repr(secs)],
+                           env=env, capture_output=True, text=True, timeout=600, check=True)
+        return json.loads(r.stdout.strip().splitlines()[-1])
+
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(),
+            "usable_cpus": len(os.sched_getaffinity(0)),
+            "oracle_64cube_1_thread": child(1, 64, ra, wall_type, 0, seconds),
+            "config1_16cube_ra1e3_type1_2000_steps": {"1_thread": child(1, 16, 1e3, 1, 2000, 0.0),
+                                                      "all_threads": child(0, 16, 1e3, 1, 2000, 0.0)}}
 
 
 def time_to_steady(wall_type: int, net=None, coarse: int = 64, n: int = 128, ra: float = 1e5):
@@ -197,6 +253,10 @@ def copy_probe(nbytes: int, reps: int = 20) -> float:
 
 
 def main():
+    if len(sys.argv) > 1 and sys.argv[1] == "--oracle-timing":  # child of cpu_oracle_detail
+        n, ra, wt, steps, secs = sys.argv[2:7]
+        _oracle_timing_child(int(n), float(ra), int(wt), int(steps), float(secs))
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
@@ -332,6 +392,7 @@ def main():
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wall_type=args.wall_type, ra=args.ra)
+        line["cpu_oracle_detail"] = cpu_oracle_detail(5.0, args.ra, args.wall_type)
         # the GPU on the oracle's sample, same size and precision class (FP64)
         c64 = lbmx.Cavity(n=64, wall_type=args.wall_type, ra=args.ra, storage="f64",
                           theta0=inputs.theta_noise(64, 20151115))
