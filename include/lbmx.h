@@ -490,8 +490,9 @@ lbmx_status lbmx_nn_concat(void *a, void *b, void *out, int64_t nvox, int32_t Ca
  * last block are zeroed); pred (FP32 [nvox][Co]) receives z if not NULL.
  * grad equals lbmx_nn_conv3d_fwd (FP32) followed by lbmx_nn_mse bit for bit;
  * the partial sums differ only in FP64 summation order.  16 <= Ci, Co <=
- * 1024, multiples of 16, 1 <= K <= Co, npartial >= 1, nvox Co < 2^31.
- * EINVAL otherwise. */
+ * 1024, multiples of 16, 1 <= K <= Co, npartial >= Co / 16 (the grid has at
+ * most npartial blocks, at least one per 16 output channels), nvox Co <
+ * 2^31.  EINVAL otherwise. */
 lbmx_status lbmx_nn_conv3d_mse(const void *in, const void *w, const float *bias, const float *target,
                                int32_t K, void *grad, double *partial, int32_t npartial, float *pred,
                                int32_t B, int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,

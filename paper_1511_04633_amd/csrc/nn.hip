@@ -1405,9 +1405,10 @@ lbmx_status lbmx_nn_conv3d_mse(const void *in, const void *w, const float *bias,
     if (!in || !w || !target || !grad || !partial)
         return fail(LBMX_EINVAL, "conv3d_mse: NULL tensor");
     if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 1024 || K < 1 || K > Co ||
-        npartial < 1)
+        npartial < Co / 16)
         return fail(LBMX_EINVAL, "conv3d_mse: need Ci, Co multiples of 16 in [16, 1024], 1 <= K <= Co, "
-                                 "npartial >= 1");
+                                 "npartial >= Co / 16 (one partial per block, at least a block per "
+                                 "output-channel tile)");
     const long long nvox = (long long)B * D * H * W;
     if (nvox * Co >= (1LL << 31))
         return fail(LBMX_EINVAL, "conv3d_mse: %lld voxels exceed 32-bit element indices", nvox);

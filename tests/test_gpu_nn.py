@@ -481,6 +481,12 @@ def test_head_convolution_with_fused_loss(shape, K, npart):
         with pytest.raises(LB.LbmxError):
             call("lbmx_nn_conv3d_mse", P(tx), P(tw), P(tb), P(tt), k, P(grad3), P(part1), n, None,
                  B, D, H, W, ci, co, S())
+    # fewer partials than output-channel tiles (32 channels, one partial)
+    w32 = to_bf(rnd((32, 27, ci), 75, 0.1))
+    g32 = torch.empty((nv, 32), dtype=torch.bfloat16, device="cuda")
+    with pytest.raises(LB.LbmxError):
+        call("lbmx_nn_conv3d_mse", P(tx), P(w32), None, P(tt), K, P(g32), P(part1), 1, None,
+             B, D, H, W, ci, 32, S())
 
 
 def test_layout_with_symmetry_transform():
