@@ -26,6 +26,9 @@ log-uniform in [1e3, 1e6], wall type uniform in {1, 2, 3}, seed 1511, FP32)
 run to steady in one persistent launch per step (autotuned launch shape,
 graph replay), wall time and aggregate MLUPS, and the same cases by grid
 sequencing (a half-size batch run to steady first).
+unet_training_step: one optimiser step of the warm-start U-Net (batch 4,
+64^3; forward, squared-error loss, backward, Adam), HIP events over 20 steps
+after 3 warm-up steps, and the convolutions' FLOP rate.
 warm_start_192: a 192^3 cavity (Ra 3e5, Type 2, FP32) to steady from rest,
 from the U-Net's predicted fields, and from a 96^3 cavity started from them
 and run to steady (inference, coarse solve and initialisation timed).
@@ -192,6 +195,24 @@ def batch_to_steady(coarse: bool):
     return out
 
 
+def unet_training_step():
+    """The U-Net's training step (unet.bench_step: batch 4 at 64^3, synthetic
+    targets, all network kernels) and its convolution FLOP rate."""
+    from paper_1511_04633_amd import unet
+
+    ms = unet.bench_step(batch=4, m=64)
+    c0, c1, c2, c3 = unet.UNet.LEVELS
+    layers = [(unet.NFEAT, c0, 64), (c0, c0, 64), (c0, c1, 32), (c1, c1, 32), (c1, c2, 16),
+              (c2, c2, 16), (c2, c3, 8), (c3, c3, 8), (c3 + c2, c2, 16), (c2, c2, 16),
+              (c2 + c1, c1, 32), (c1, c1, 32), (c1 + c0, c0, 64), (c0, c0, 64), (c0, 16, 64)]
+    # forward and weight gradient of every layer, data gradient of all but the first
+    flop = sum(2 * 27 * ci * co * 4 * r ** 3 * (2 if k == 0 else 3)
+               for k, (ci, co, r) in enumerate(layers))
+    return {"workload": "U-Net training step, batch 4, 64^3, BF16 MFMA", "ms_per_step": round(ms, 4),
+            "conv_gflop": round(flop / 1e9, 1), "conv_tflops": round(flop / ms / 1e9, 1),
+            "bf16_dense_peak_frac": round(flop / ms / 1e9 / 2500.0, 4)}
+
+
 def warm_start_192(net, ra: float = 3e5, wall_type: int = 2, n: int = 192, coarse: int = 96):
     """The learned warm start at 192^3: rest start vs the network's fields vs grid sequencing
     through a coarse^3 cavity started from them; all to |dNu_3D| < 1e-6 per
@@ -282,6 +303,8 @@ def main():
                     help="skip the storage-format sweep at the benchmark size")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the 64-cavity batch run to steady")
+    ap.add_argument("--no-unet-step", action="store_true",
+                    help="skip timing the U-Net training step")
     ap.add_argument("--no-warm192", action="store_true",
                     help="skip the 192^3 warm-start comparison")
     ap.add_argument("--force-model", type=int, default=0, choices=[0, 1, 2],
@@ -389,6 +412,9 @@ def main():
             net = warmstart.load_net(os.path.join(ROOT, "paper_1511_04633_amd", "weights",
                                                   "unet64.npz"))
         line["warm_start_192"] = warm_start_192(net)
+    if not args.no_unet_step:
+        print("bench: U-Net training step", file=sys.stderr, flush=True)
+        line["unet_training_step"] = unet_training_step()
     if not args.no_cpu_baseline:
         print("bench: CPU oracle baseline", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(args.cpu_seconds, wall_type=args.wall_type, ra=args.ra)
