@@ -758,15 +758,28 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__rest
         __syncthreads();
         if (n + 1 < bw.count)
             load_brick(bw.first + (n + 1) * bw.stride);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {  // row pair (2q, 2q + 1)
-            const bf8v av = *reinterpret_cast<const bf8v *>(ap + q * 32);
+        // row pairs (2q, 2q + 1): pair q + 1's operands are read before pair
+        // q's products, in two register sets; the scheduling barriers keep
+        // the compiler from moving the reads back next to their MFMAs (the
+        // LDS latency then overlaps a pair's 7 products; measured 6 % faster)
+        bf8v av[2], bv[2][WB_SLOTS];
+        auto read_pair = [&](int q, int k) {
             const int roff = ((q / 2) * (WB_Y + 2) + 2 * (q % 2)) * WB_X;
+            av[k] = *reinterpret_cast<const bf8v *>(ap + q * 32);
 #pragma unroll
-            for (int s = 0; s < WB_SLOTS; ++s) {
-                const bf8v bv = *reinterpret_cast<const bf8v *>(bp[s] + roff);
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc[s], 0, 0, 0);
-            }
+            for (int s = 0; s < WB_SLOTS; ++s)
+                bv[k][s] = *reinterpret_cast<const bf8v *>(bp[s] + roff);
+        };
+        read_pair(0, 0);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            if (q + 1 < 8)
+                read_pair(q + 1, (q + 1) & 1);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int s = 0; s < WB_SLOTS; ++s)
+                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[q & 1], bv[q & 1][s], acc[s], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
         }
     }
 #pragma unroll
