@@ -400,20 +400,51 @@ k_conv_fwd(ConvIn src, const bf *__restrict__ w, const float *__restrict__ bias,
                 }
             }
         }
+        // 14 tap pairs (27 taps and a zero tap), each a K = 32 product.  At 3
+        // waves per SIMD the register budget holds one operand set; at 2 the
+        // next pair's operands are read from LDS while the current pair's
+        // products run (two register sets, the scheduling barriers keep the
+        // reads ahead of the products).
+        if constexpr (fc_waves(NCO, LOSS, KS) == 3) {
 #pragma unroll
-        for (int pr = 0; pr < 14; ++pr) {
-            if (!active)
-                break;
-            bf8v a[NCO];
-#pragma unroll
-            for (int jj = 0; jj < NCO; ++jj)
-                a[jj] = *reinterpret_cast<const bf8v *>(wa + (2 * pr * NCO + jj) * 256);
-#pragma unroll
-            for (int rr = 0; rr < 4; ++rr) {
-                const bf8v bv = *reinterpret_cast<const bf8v *>(bp[pr] + rr * FC_HX * 16);
+            for (int pr = 0; pr < 14; ++pr) {
+                if (!active)
+                    break;
+                bf8v a[NCO];
 #pragma unroll
                 for (int jj = 0; jj < NCO; ++jj)
-                    acc[rr][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[jj], bv, acc[rr][jj], 0, 0, 0);
+                    a[jj] = *reinterpret_cast<const bf8v *>(wa + (2 * pr * NCO + jj) * 256);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr) {
+                    const bf8v bv = *reinterpret_cast<const bf8v *>(bp[pr] + rr * FC_HX * 16);
+#pragma unroll
+                    for (int jj = 0; jj < NCO; ++jj)
+                        acc[rr][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[jj], bv, acc[rr][jj], 0, 0, 0);
+                }
+            }
+        } else if (active) {
+            bf8v a[2][NCO], bv[2][4];
+            auto read_pr = [&](int pr, int k) {
+#pragma unroll
+                for (int jj = 0; jj < NCO; ++jj)
+                    a[k][jj] = *reinterpret_cast<const bf8v *>(wa + (2 * pr * NCO + jj) * 256);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+                    bv[k][rr] = *reinterpret_cast<const bf8v *>(bp[pr] + rr * FC_HX * 16);
+            };
+            read_pr(0, 0);
+#pragma unroll
+            for (int pr = 0; pr < 14; ++pr) {
+                if (pr + 1 < 14)
+                    read_pr(pr + 1, (pr + 1) & 1);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int rr = 0; rr < 4; ++rr)
+#pragma unroll
+                    for (int jj = 0; jj < NCO; ++jj)
+                        acc[rr][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[pr & 1][jj], bv[pr & 1][rr],
+                                                                              acc[rr][jj], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
         if (step + 1 < NR)
