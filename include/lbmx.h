@@ -379,7 +379,8 @@ lbmx_status lbmx_batch_autotune(lbmx_batch *b, const char *cache_path, double *u
 
 /* out[p][co] = bias[co] + sum_{tap,ci} w[co][tap][ci] in[p + off(tap)][ci];
  * out is BF16 (out_f32 = 0) or FP32 [B][D][H][W][Co].  bias may be NULL.
- * 16 <= Ci, Co <= 1024, multiples of 16; B D H W < 2^31.  EINVAL otherwise. */
+ * 16 <= Ci, Co <= 1024, multiples of 16; B D H W < 2^31 and 6 (H + 1) (W + 2)
+ * Ci < 2^31 (32-bit element offsets within a few planes).  EINVAL otherwise. */
 lbmx_status lbmx_nn_conv3d_fwd(const void *in, const void *w, const float *bias, void *out,
                                int32_t out_f32, int32_t B, int32_t D, int32_t H, int32_t W,
                                int32_t Ci, int32_t Co, void *stream);
@@ -447,7 +448,8 @@ lbmx_status lbmx_nn_conv3d_flip_many(const void *w, void *wt, int32_t count, con
 /* gw[co][tap][ci] += sum_p gout[p][co] in[p + off(tap)][ci] and, if gb is
  * not NULL, gb[co] += sum_p gout[p][co] (FP32, accumulated atomically, so
  * the summation order varies between runs).  16 <= Ci, Co <= 1024,
- * multiples of 16; B D H W max(Ci, Co) < 2^31.  EINVAL otherwise. */
+ * multiples of 16; B D H W max(Ci, Co) < 2^31 and 6 (H + 1) (W + 2) max(Ci,
+ * Co) < 2^31.  EINVAL otherwise. */
 lbmx_status lbmx_nn_conv3d_wgrad(const void *in, const void *gout, float *gw, float *gb, int32_t B,
                                  int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,
                                  void *stream);
@@ -492,7 +494,7 @@ lbmx_status lbmx_nn_concat(void *a, void *b, void *out, int64_t nvox, int32_t Ca
  * the partial sums differ only in FP64 summation order.  16 <= Ci, Co <=
  * 1024, multiples of 16, 1 <= K <= Co, npartial >= Co / 16 (the grid has at
  * most npartial blocks, at least one per 16 output channels), nvox Co <
- * 2^31.  EINVAL otherwise. */
+ * 2^31 and 6 (H + 1) (W + 2) Ci < 2^31.  EINVAL otherwise. */
 lbmx_status lbmx_nn_conv3d_mse(const void *in, const void *w, const float *bias, const float *target,
                                int32_t K, void *grad, double *partial, int32_t npartial, float *pred,
                                int32_t B, int32_t D, int32_t H, int32_t W, int32_t Ci, int32_t Co,

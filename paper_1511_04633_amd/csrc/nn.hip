@@ -1359,6 +1359,16 @@ void launch_fwd(ConvIn src, const bf *w, const float *bias, void *out, int out_f
                        bias, out, out_f32, d, nbx, nby, nbz, ep, ls);
 }
 
+// Rejects planes whose brick-relative element offsets (a few planes of
+// H W voxels of C channels, computed once per thread in 32 bits) overflow.
+lbmx_status check_plane(int32_t H, int32_t W, int32_t C, const char *what)
+{
+    if (6 * ((long long)H + 1) * ((long long)W + 2) * C >= (1LL << 31))
+        return fail(LBMX_EINVAL, "%s: H W planes too large for 32-bit brick offsets (need "
+                                 "6 (H + 1) (W + 2) C < 2^31)", what);
+    return LBMX_OK;
+}
+
 // Rejects an upsample-and-concatenate input whose low part is malformed.
 lbmx_status check_upcat(const ConvIn &src, int32_t D, int32_t H, int32_t W, int32_t Ci, const char *what)
 {
@@ -1393,7 +1403,8 @@ lbmx_status conv_fwd(ConvIn src, const void *w, const float *bias, void *out, in
         return fail(LBMX_EINVAL, "conv3d: act and gate exclude each other");
     if (!ep.out2)
         ep.split = 0;
-    if ((st = check_upcat(src, D, H, W, Ci, "conv3d")) != LBMX_OK)
+    if ((st = check_upcat(src, D, H, W, Ci, "conv3d")) != LBMX_OK ||
+        (st = check_plane(H, W, Ci, "conv3d")) != LBMX_OK)
         return st;
     const Dims d{B, D, H, W, Ci, Co};
     const bf *wb = reinterpret_cast<const bf *>(w);
@@ -1456,6 +1467,8 @@ lbmx_status lbmx_nn_conv3d_mse(const void *in, const void *w, const float *bias,
     const long long nvox = (long long)B * D * H * W;
     if (nvox * Co >= (1LL << 31))
         return fail(LBMX_EINVAL, "conv3d_mse: %lld voxels exceed 32-bit element indices", nvox);
+    if ((st = check_plane(H, W, Ci, "conv3d_mse")) != LBMX_OK)
+        return st;
     LossEp ls{target, K, 1.0f / float(double(nvox) * K), reinterpret_cast<bf *>(grad), partial, npartial};
     launch_fwd<1, true>(ConvIn{reinterpret_cast<const bf *>(in), nullptr, 0}, reinterpret_cast<const bf *>(w),
                         bias, pred, 1, Dims{B, D, H, W, Ci, Co}, S(stream), Epilogue{}, ls);
@@ -1597,7 +1610,8 @@ lbmx_status conv_wgrad(ConvIn src, const void *gout, float *gw, float *gb, int32
         return fail(LBMX_EINVAL, "conv3d_wgrad: NULL tensor");
     if (Ci < 16 || Ci % 16 || Ci > 1024 || Co < 16 || Co % 16 || Co > 1024)
         return fail(LBMX_EINVAL, "conv3d_wgrad: need Ci, Co multiples of 16 in [16, 1024]");
-    if ((st = check_upcat(src, D, H, W, Ci, "conv3d_wgrad")) != LBMX_OK)
+    if ((st = check_upcat(src, D, H, W, Ci, "conv3d_wgrad")) != LBMX_OK ||
+        (st = check_plane(H, W, Ci > Co ? Ci : Co, "conv3d_wgrad")) != LBMX_OK)
         return st;
     const Dims d{B, D, H, W, Ci, Co};
     const long long nv = (long long)B * D * H * W;

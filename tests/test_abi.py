@@ -136,3 +136,22 @@ def test_batch_rejects_mixed_force_models():
     h = ctypes.c_void_p()
     assert lib.lbmx_batch_create(arr, 2, None, ctypes.byref(h)) == 1
     assert b"force model" in lib.lbmx_last_error()
+
+
+def test_convolution_plane_limits_rejected_on_host():
+    """The convolution launchers reject, before any device call, shapes whose
+    32-bit brick-relative offsets (a few H x W planes of C channels) would
+    overflow although the voxel count fits: one 8192 x 8192 plane of 16
+    channels.  The pointers are never dereferenced."""
+    from paper_1511_04633_amd import unet
+    lib = unet.nn()
+    p = ctypes.c_void_p(256)
+    shape = (1, 1, 8192, 8192, 16, 16)
+    assert lib.lbmx_nn_conv3d_fwd(p, p, None, p, 0, *shape, None) == 1
+    assert b"brick offsets" in lib.lbmx_last_error()
+    assert lib.lbmx_nn_conv3d_wgrad(p, p, p, None, *shape, None) == 1
+    assert b"brick offsets" in lib.lbmx_last_error()
+    assert lib.lbmx_nn_conv3d_mse(p, p, None, p, 4, p, p, 64, None, *shape, None) == 1
+    assert b"brick offsets" in lib.lbmx_last_error()
+    assert lib.lbmx_nn_conv3d_fwd(p, p, None, p, 0, 1, 1, 8192, 8192, 16, 1040, None) == 1
+    assert b"multiples of 16" in lib.lbmx_last_error()
