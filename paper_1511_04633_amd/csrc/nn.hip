@@ -11,9 +11,10 @@
 // sum_{tap, ci} W[co][tap][ci] in[p + off(tap)][ci] with M = co, N = voxels,
 // K = (tap, ci), FP32 accumulation.  Both convolution kernels run on
 // v_mfma_f32_16x16x32_bf16 (gfx950) over bricks of 16 x 4 x 4 voxels staged
-// in LDS, so that every MFMA operand is one aligned 16-byte LDS read and each
-// staged element serves all 27 taps; blocks walk the bricks in an XCD-aware
-// order (brick_walk):
+// in LDS, so that MFMA operands are aligned 16-byte LDS reads (the weight
+// gradient's x-shifted taps take them one word on or one element on, by a
+// byte permute) and each staged element serves all 27 taps; blocks walk the
+// bricks in an XCD-aware order (brick_walk):
 //   - forward (and the data gradient, the same convolution of the output
 //     gradient with the flipped, transposed weights W'[ci][26-tap][co] =
 //     W[co][tap][ci]): a block stages its brick's input with a one-voxel halo
@@ -24,9 +25,11 @@
 //     at k_conv_fwd;
 //   - weight gradient: a block owns one (output-channel tile, input-channel
 //     tile) pair, walks the bricks, stages output gradient and input halo
-//     transposed to [channel][voxel]; K = 32 covers two brick rows of voxels;
-//     the bias gradient is one more MFMA against ones; the block's sums are
-//     added to the global gradient atomically; details at k_conv_wgrad.
+//     transposed to [channel][voxel] (one copy of the input); K = 32 covers
+//     two brick rows of voxels; two LDS reads feed the three taps that differ
+//     only in dx; the bias gradient is one more MFMA against ones; the
+//     block's sums are added to the global gradient atomically; details at
+//     k_conv_wgrad.
 // MFMA operand layout of v_mfma_f32_16x16x32_bf16 (checked on the device):
 // lane l holds A[l%16][8(l/16) .. 8(l/16)+7] and B[8(l/16) .. 8(l/16)+7][l%16]
 // and gets D[4(l/16)+j][l%16], j < 4.
@@ -603,33 +606,33 @@ __global__ __launch_bounds__(256) void k_conv_flip_many(const bf *__restrict__ w
 // consecutive voxels of one channel: per brick the block stages in LDS,
 // transposed to [channel][voxel]:
 //   gT: the brick's gout tile, 16 channels x 256 voxels;
-//   iT: the input tile on the brick plus a one-voxel halo in y and z, in
-//       three copies shifted by dx = -1, 0, +1 along x (copy dx holds
-//       in[x + dx] at x), so a tap's 8 consecutive voxels are one aligned
-//       16-byte read.
+//   iT: the input tile on the brick plus a one-voxel halo, 36 halo rows
+//       (y, z) of 18 voxels (x0 - 1 .. x0 + 16) per channel, each row
+//       starting on a 16-byte boundary (24-element stride).
 // The transpose packs two x-neighbours of one channel into each 32-bit LDS
-// word, and consecutive lanes write consecutive words.  Channel rows are
-// padded by 8 elements (16 bytes), which puts the 8 channels read by one
-// 8-lane phase of a 16-byte read on distinct banks.
+// word, and consecutive lanes write consecutive words.
 // The products run on v_mfma_f32_16x16x32_bf16 with K = 32 voxels, two brick
-// rows (lanes 0-31 row 2q, lanes 32-63 row 2q + 1, 8 voxels per lane).  Wave
-// w runs the taps w, w + 4, ... (7 or 6) over the brick's 8 row pairs,
-// reusing the gout operand across its taps; wave 3's free slot accumulates
-// the bias gradient as an MFMA against an LDS block of ones.  Each lane's
+// rows (lanes 0-31 row 2q, lanes 32-63 row 2q + 1, 8 voxels per lane).  The
+// 27 taps form 9 groups (dy, dz) of three x offsets: a lane reads the 16
+// halo voxels from x = 8 h - 1 on (two aligned 16-byte reads) and takes the
+// operand of dx = -1 as the first read, dx = +1 as its words 1-4 and dx = 0
+// as those words shifted by one element (v_perm_b32), so two LDS reads feed
+// three products.  Wave w runs groups w and w + 4 (wave 0 also group 8),
+// reusing the gout operand across its taps; wave 3 accumulates the bias
+// gradient as a product with a register operand of ones.  Each lane's
 // operand addresses are computed once per launch, a row pair step is an
-// immediate offset, so the inner loop is LDS reads and MFMAs only.  Partial
-// sums stay in registers across the block's bricks and are added to gw / gb
-// atomically at the end.  Voxel and element indices are 32-bit (the host
-// checks B D H W C < 2^31).
+// immediate offset, so the inner loop is LDS reads, permutes and MFMAs.
+// Partial sums stay in registers across the block's bricks and are added to
+// gw / gb atomically at the end.  Voxel and element indices are 32-bit (the
+// host checks B D H W C < 2^31 and the plane extents).
 constexpr int WB_X = 16, WB_Y = 4, WB_Z = 4, WB_V = WB_X * WB_Y * WB_Z;
-constexpr int WB_HROWS = (WB_Y + 2) * (WB_Z + 2);   // halo rows of 16 voxels
-constexpr int WB_PLANE = WB_HROWS * WB_X + 8;       // one channel of one shifted copy
+constexpr int WB_HROWS = (WB_Y + 2) * (WB_Z + 2);   // halo rows (y, z)
+constexpr int WB_RW = 24;                           // LDS row: 18 halo voxels, 16-byte aligned stride
+constexpr int WB_PLANE = WB_HROWS * WB_RW + 8; // one input channel
 constexpr int WB_GROW = WB_V + 8;                   // one channel of the gout tile
-constexpr int WB_SLOTS = 7;                         // taps per wave (27 = 7 + 7 + 7 + 6)
-constexpr int WB_ONES = (3 * 6 + 2) * WB_X + 16;    // ones block: the bias slot's 8 row-pair reads
-constexpr int WB_ITASKS = WB_HROWS * (WB_X / 2) * 2;   // (halo row, x pair, channel half) = 576
+constexpr int WB_XP = (WB_X + 2) / 2;               // voxel pairs per halo row
+constexpr int WB_ITASKS = WB_HROWS * WB_XP * 2;     // (halo row, x pair, channel half) = 648
 constexpr int WB_ITERS = (WB_ITASKS + 255) / 256;
-constexpr long long WG_TARGET_BLOCKS = 512;         // blocks per launch, all channel pairs
 constexpr long long WG_MIN_BRICKS = 3;              // bricks per block, at least (where there are)
 
 // 32-bit words (channel c of voxel A, channel c of voxel B) for the 8
@@ -651,47 +654,48 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__rest
                                                     int nbx, int nby, int nbz)
 {
     __shared__ __attribute__((aligned(16))) bf gT[16 * WB_GROW];
-    __shared__ __attribute__((aligned(16))) bf iT[3 * 16 * WB_PLANE];
-    __shared__ __attribute__((aligned(16))) bf oT[WB_ONES];
+    __shared__ __attribute__((aligned(16))) bf iT[16 * WB_PLANE];
     const int Ci = d.Ci, Co = d.Co;
     const int CIT = Ci / 16;
     const int ct = blockIdx.y / CIT, it = blockIdx.y % CIT;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int col = lane & 15, kq = lane >> 4;
-    const bool do_bias = gb != nullptr && it == 0;
+    const bool bias_wave = wv == 3 && gb != nullptr && it == 0;
+    const bool g3 = wv == 0;               // wave 0 also runs group 8
     const int nbricks = d.B * nbx * nby * nbz;
     const int cs = Ci - src.cu;            // channel stride of src.in
     const bool up = it * 16 < src.cu;      // this block's input channels come from src.low
     const int cin = it * 16 - src.cu;      // channel offset in src.in (when !up)
 
     // Operand addresses of this lane at row pair 0: the gout operand (row
-    // kq >> 1, voxels 8 (kq & 1) ..) and, per slot, the input operand of tap
-    // wv + 4 s at the same voxels; wave 3's last slot reads the ones block.
-    // Row pair q adds (q / 2) 6 + 2 (q % 2) halo rows to every input address.
+    // kq >> 1, voxels 8 (kq & 1) ..) and, per group, the first of the two
+    // input reads (halo voxel 8 (kq & 1), i.e. x = 8 (kq & 1) - 1).  Row pair
+    // q adds (q / 2) 6 + 2 (q % 2) halo rows to every input address.
     const bf *ap = gT + col * WB_GROW + kq * 8;
-    const bf *bp[WB_SLOTS];
+    const bf *bb[3];
 #pragma unroll
-    for (int s = 0; s < WB_SLOTS; ++s) {
-        const int tap = wv + 4 * s;
-        const int dx = tap % 3 - 1, dy = (tap / 3) % 3 - 1, dz = tap / 9 - 1;
+    for (int gs = 0; gs < 3; ++gs) {
+        const int G = wv + 4 * gs < 9 ? wv + 4 * gs : 8;
+        const int dy = G % 3 - 1, dz = G / 3 - 1;
         const int hrow = (1 + dz) * (WB_Y + 2) + (kq >> 1) + 1 + dy;
-        bp[s] = tap < 27 ? iT + ((dx + 1) * 16 + col) * WB_PLANE + hrow * WB_X + (kq & 1) * 8 : oT;
+        bb[gs] = iT + col * WB_PLANE + hrow * WB_RW + (kq & 1) * 8;
     }
-    f4 acc[WB_SLOTS];
+    f4 acc[3][3], accb = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s = 0; s < WB_SLOTS; ++s)
-        acc[s] = f4{0.f, 0.f, 0.f, 0.f};
-    for (int i = threadIdx.x; i < WB_ONES / 2; i += 256)
-        reinterpret_cast<uint32_t *>(oT)[i] = 0x3f803f80u;  // BF16 1.0, 1.0
+    for (int gs = 0; gs < 3; ++gs)
+#pragma unroll
+        for (int x = 0; x < 3; ++x)
+            acc[gs][x] = f4{0.f, 0.f, 0.f, 0.f};
+    const bf8v ones = __builtin_bit_cast(bf8v, make_uint4(0x3f803f80u, 0x3f803f80u, 0x3f803f80u, 0x3f803f80u));
 
     // Staging tasks.  gout: thread t packs voxels 2p, 2p + 1 (p = t & 127) of
-    // channel half t >> 7.  Input: task k = (x pair a = k & 7, halo row
-    // r = (k >> 3) % 36, channel half k / 288) loads the four voxels x0 + 2a
-    // - 1 .. x0 + 2a + 2 of its row and writes positions 2a, 2a + 1 of the
-    // three shifted copies.  The next brick's loads are issued before this
-    // brick's MFMAs and written to LDS afterwards.
-    // Element offsets from the brick's first voxel: the gout pair of this
-    // thread, and voxel x0 + 2a - 1 of each input task (+ m Ci for voxel m).
+    // channel half t >> 7.  Input: task k = (x pair a = k % 9, halo row
+    // r = (k / 9) % 36, channel half k / 324) loads voxels x0 + 2a - 1 and
+    // x0 + 2a of its row and writes halo positions 2a, 2a + 1.  The next
+    // brick's loads are issued before this brick's MFMAs and written to LDS
+    // afterwards.  Element offsets from the brick's first voxel: the gout
+    // pair of this thread, and voxel x0 + 2a - 1 of each input task (+ Ci for
+    // the second voxel).
     const BrickGrid grid(nbx, nby, nbz);
     int goff, ioff[WB_ITERS];
     {
@@ -701,11 +705,11 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__rest
 #pragma unroll
     for (int k = 0; k < WB_ITERS; ++k) {
         const int task = threadIdx.x + 256 * k;
-        const int a = task & 7, r = (task >> 3) % WB_HROWS, h = task / (8 * WB_HROWS);
+        const int a = task % WB_XP, r = (task / WB_XP) % WB_HROWS, h = task / (WB_XP * WB_HROWS);
         const int hy = r % (WB_Y + 2), hz = r / (WB_Y + 2);
         ioff[k] = (((hz - 1) * d.H + (hy - 1)) * d.W + (2 * a - 1)) * cs + cin + h * 8;
     }
-    uint4 gl[2], il[WB_ITERS][4];
+    uint4 gl[2], il[WB_ITERS][2];
     auto load_brick = [&](int br) {
         int b, x0, y0, z0;
         grid.at(br, WB_X, WB_Y, WB_Z, b, x0, y0, z0);
@@ -718,7 +722,7 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__rest
             for (int k = 0; k < WB_ITERS; ++k)
                 if (threadIdx.x + 256 * k < WB_ITASKS)
 #pragma unroll
-                    for (int m = 0; m < 4; ++m)
+                    for (int m = 0; m < 2; ++m)
                         il[k][m] = *reinterpret_cast<const uint4 *>(src.in + vb * cs + ioff[k] + m * cs);
             return;
         }
@@ -738,13 +742,13 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__rest
 #pragma unroll
         for (int k = 0; k < WB_ITERS; ++k) {
             const int task = threadIdx.x + 256 * k;
-            const int a = task & 7, r = (task >> 3) % WB_HROWS, h = task / (8 * WB_HROWS);
+            const int a = task % WB_XP, r = (task / WB_XP) % WB_HROWS, h = task / (WB_XP * WB_HROWS);
             const int y = y0 + r % (WB_Y + 2) - 1, z = z0 + r / (WB_Y + 2) - 1;
             const bool row_ok = task < WB_ITASKS && y >= 0 && y < d.H && z >= 0 && z < d.D;
             const int q0 = ((b * d.D + z) * d.H + y) * d.W;
             const int l0 = ((b * (d.D >> 1) + (z >> 1)) * (d.H >> 1) + (y >> 1)) * (d.W >> 1);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
+            for (int m = 0; m < 2; ++m) {
                 const int x = x0 + 2 * a - 1 + m;
                 il[k][m] = make_uint4(0, 0, 0, 0);
                 if (row_ok && x >= 0 && x < d.W)
@@ -768,15 +772,12 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__rest
             const int task = threadIdx.x + 256 * k;
             if (task >= WB_ITASKS)
                 continue;
-            const int a = task & 7, r = (task >> 3) % WB_HROWS, h = task / (8 * WB_HROWS);
+            const int a = task % WB_XP, r = (task / WB_XP) % WB_HROWS, h = task / (WB_XP * WB_HROWS);
+            uint32_t w[8];
+            pair_words(il[k][0], il[k][1], w);
 #pragma unroll
-            for (int c3 = 0; c3 < 3; ++c3) {  // copy c3 holds in[x + (c3 - 1)] at x
-                uint32_t w[8];
-                pair_words(il[k][c3], il[k][c3 + 1], w);
-#pragma unroll
-                for (int c = 0; c < 8; ++c)
-                    reinterpret_cast<uint32_t *>(iT + (c3 * 16 + h * 8 + c) * WB_PLANE + r * WB_X)[a] = w[c];
-            }
+            for (int c = 0; c < 8; ++c)
+                reinterpret_cast<uint32_t *>(iT + (h * 8 + c) * WB_PLANE + r * WB_RW)[a] = w[c];
         }
     };
 
@@ -791,15 +792,18 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__rest
             load_brick(bw.first + (n + 1) * bw.stride);
         // row pairs (2q, 2q + 1): pair q + 1's operands are read before pair
         // q's products, in two register sets; the scheduling barriers keep
-        // the compiler from moving the reads back next to their MFMAs (the
-        // LDS latency then overlaps a pair's 7 products; measured 6 % faster)
-        bf8v av[2], bv[2][WB_SLOTS];
+        // the compiler from moving the reads back next to their MFMAs
+        bf8v av[2];
+        uint4 lo[2][3], hi[2][3];
         auto read_pair = [&](int q, int k) {
-            const int roff = ((q / 2) * (WB_Y + 2) + 2 * (q % 2)) * WB_X;
+            const int roff = ((q / 2) * (WB_Y + 2) + 2 * (q % 2)) * WB_RW;
             av[k] = *reinterpret_cast<const bf8v *>(ap + q * 32);
 #pragma unroll
-            for (int s = 0; s < WB_SLOTS; ++s)
-                bv[k][s] = *reinterpret_cast<const bf8v *>(bp[s] + roff);
+            for (int gs = 0; gs < 3; ++gs)
+                if (gs < 2 || g3) {
+                    lo[k][gs] = *reinterpret_cast<const uint4 *>(bb[gs] + roff);
+                    hi[k][gs] = *reinterpret_cast<const uint4 *>(bb[gs] + roff + 8);
+                }
         };
         read_pair(0, 0);
 #pragma unroll
@@ -807,24 +811,46 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn src, const bf *__rest
             if (q + 1 < 8)
                 read_pair(q + 1, (q + 1) & 1);
             __builtin_amdgcn_sched_barrier(0);
+            const int k = q & 1;
 #pragma unroll
-            for (int s = 0; s < WB_SLOTS; ++s)
-                acc[s] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[q & 1], bv[q & 1][s], acc[s], 0, 0, 0);
+            for (int gs = 0; gs < 3; ++gs)
+                if (gs < 2 || g3) {
+                    const uint4 l = lo[k][gs], h = hi[k][gs];
+                    // halo elements 1-8 (dx = 0) and 2-9 (dx = +1) of the 16 read
+                    const uint4 s0 = make_uint4(__builtin_amdgcn_perm(l.y, l.x, 0x05040302u),
+                                                __builtin_amdgcn_perm(l.z, l.y, 0x05040302u),
+                                                __builtin_amdgcn_perm(l.w, l.z, 0x05040302u),
+                                                __builtin_amdgcn_perm(h.x, l.w, 0x05040302u));
+                    const uint4 s1 = make_uint4(l.y, l.z, l.w, h.x);
+                    acc[gs][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[k], __builtin_bit_cast(bf8v, l),
+                                                                         acc[gs][0], 0, 0, 0);
+                    acc[gs][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[k], __builtin_bit_cast(bf8v, s0),
+                                                                         acc[gs][1], 0, 0, 0);
+                    acc[gs][2] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[k], __builtin_bit_cast(bf8v, s1),
+                                                                         acc[gs][2], 0, 0, 0);
+                }
+            if (bias_wave)
+                accb = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[k], ones, accb, 0, 0, 0);
             __builtin_amdgcn_sched_barrier(0);
         }
     }
 #pragma unroll
-    for (int s = 0; s < WB_SLOTS; ++s) {
-        const int tap = wv + 4 * s;
+    for (int gs = 0; gs < 3; ++gs) {
+        const int G = wv + 4 * gs;
+        if (G >= 9)
+            continue;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int co = ct * 16 + kq * 4 + r, ci = it * 16 + col;
-            if (tap < 27)
-                atomicAdd(&gw[(co * 27 + tap) * Ci + ci], acc[s][r]);
-            else if (do_bias && col == 0)  // wave 3, last slot: D[co][*] = sum_k gout[k][co]
-                atomicAdd(&gb[co], acc[s][r]);
-        }
+        for (int x = 0; x < 3; ++x)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int co = ct * 16 + kq * 4 + r, ci = it * 16 + col;
+                atomicAdd(&gw[(co * 27 + 3 * G + x) * Ci + ci], acc[gs][x][r]);
+            }
     }
+    if (bias_wave && col == 0)  // D[co][*] = sum_k gout[k][co]
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            atomicAdd(&gb[ct * 16 + kq * 4 + r], accb[r]);
 }
 
 // ------------------------------------------------------------ elementwise
@@ -1620,11 +1646,22 @@ lbmx_status conv_wgrad(ConvIn src, const void *gout, float *gw, float *gb, int32
     const int nbx = (W + WB_X - 1) / WB_X, nby = (H + WB_Y - 1) / WB_Y, nbz = (D + WB_Z - 1) / WB_Z;
     const long long nbricks = (long long)B * nbx * nby * nbz;
     const int pairs = (Co / 16) * (Ci / 16);
-    // about two blocks per CU in total; each block sums at least
-    // WG_MIN_BRICKS bricks in registers before its atomic adds (on small
-    // grids the atomics of many short blocks onto the same addresses cost
-    // more than the parallelism gains)
-    long long gx = (WG_TARGET_BLOCKS + pairs - 1) / pairs;
+    // one wave of resident blocks over all channel pairs (two per CU, the
+    // register limit); each block sums at least WG_MIN_BRICKS bricks in
+    // registers before its atomic adds (on small grids the atomics of many
+    // short blocks onto the same addresses cost more than the parallelism
+    // gains)
+    static const int per_cu = [] {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_conv_wgrad, 256, 0) != hipSuccess)
+            nb = 1;
+        return nb < 1 ? 1 : nb;
+    }();
+    int dev = 0, cus = 256;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+        cus = 256;
+    long long gx = ((long long)per_cu * cus + pairs - 1) / pairs;
     gx = std::min(gx, (nbricks + WG_MIN_BRICKS - 1) / WG_MIN_BRICKS);
     if (gx >= 8) gx -= gx % 8;  // x extent a multiple of 8: XCD-aware brick order
     if (gx < 1) gx = 1;
