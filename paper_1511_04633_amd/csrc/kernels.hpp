@@ -261,11 +261,17 @@ struct Access {
     template <typename S>
     using gptr = __attribute__((address_space(1))) S *;
     // Loads return the storage bits (Codec<S>::Raw); Codec<S>::dec converts.
+    // 8-byte populations (FP64 storage) are read non-temporally as well
+    // (measured 2.5 % faster at 256^3); narrower ones are not (slower: a
+    // wavefront's x-shifted reads share cache lines with its neighbours').
     template <typename S>
     static __device__ __forceinline__ typename Codec<S>::Raw ld(const char *base, I byte)
     {
         using R = typename Codec<S>::Raw;
-        return *(gptr<const R>)((gptr<const char>)base + byte);
+        if constexpr (sizeof(R) == 8)
+            return __builtin_nontemporal_load((gptr<const R>)((gptr<const char>)base + byte));
+        else
+            return *(gptr<const R>)((gptr<const char>)base + byte);
     }
     template <typename S>
     static __device__ __forceinline__ void st(char *base, I byte, typename Codec<S>::Raw v)
