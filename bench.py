@@ -28,7 +28,9 @@ graph replay), wall time and aggregate MLUPS, and the same cases by grid
 sequencing (a half-size batch run to steady first).
 unet_training_step: one optimiser step of the warm-start U-Net (batch 4,
 64^3; forward, squared-error loss, backward, Adam), HIP events over 20 steps
-after 3 warm-up steps, and the convolutions' FLOP rate.
+after 3 warm-up steps, the convolutions' FLOP rate, and the floor of the
+convolutions (per launch the larger of HBM and MFMA time) with the step's
+ratio to it.
 warm_start_192: a 192^3 cavity (Ra 3e5, Type 2, FP32) to steady from rest,
 from the U-Net's predicted fields, and from a 96^3 cavity started from them
 and run to steady (inference, coarse solve and initialisation timed).
@@ -197,20 +199,19 @@ def batch_to_steady(coarse: bool):
 
 def unet_training_step():
     """The U-Net's training step (unet.bench_step: batch 4 at 64^3, synthetic
-    targets, all network kernels) and its convolution FLOP rate."""
+    targets, all network kernels), its convolution FLOP rate and the floor of
+    its convolutions (unet.conv_floor: per launch the larger of HBM and MFMA
+    time)."""
     from paper_1511_04633_amd import unet
 
     ms = unet.bench_step(batch=4, m=64)
-    c0, c1, c2, c3 = unet.UNet.LEVELS
-    layers = [(unet.NFEAT, c0, 64), (c0, c0, 64), (c0, c1, 32), (c1, c1, 32), (c1, c2, 16),
-              (c2, c2, 16), (c2, c3, 8), (c3, c3, 8), (c3 + c2, c2, 16), (c2, c2, 16),
-              (c2 + c1, c1, 32), (c1, c1, 32), (c1 + c0, c0, 64), (c0, c0, 64), (c0, 16, 64)]
-    # forward and weight gradient of every layer, data gradient of all but the first
-    flop = sum(2 * 27 * ci * co * 4 * r ** 3 * (2 if k == 0 else 3)
-               for k, (ci, co, r) in enumerate(layers))
+    flop, floor_s, hbm_s, mfma_s = unet.conv_floor(4, 64)
     return {"workload": "U-Net training step, batch 4, 64^3, BF16 MFMA", "ms_per_step": round(ms, 4),
             "conv_gflop": round(flop / 1e9, 1), "conv_tflops": round(flop / ms / 1e9, 1),
-            "bf16_dense_peak_frac": round(flop / ms / 1e9 / 2500.0, 4)}
+            "bf16_dense_peak_frac": round(flop / ms / 1e9 / 2500.0, 4),
+            "conv_floor_us": round(floor_s * 1e6, 1), "conv_floor_hbm_only_us": round(hbm_s * 1e6, 1),
+            "conv_floor_mfma_only_us": round(mfma_s * 1e6, 1),
+            "step_over_conv_floor": round(ms * 1e-3 / floor_s, 2)}
 
 
 def warm_start_192(net, ra: float = 3e5, wall_type: int = 2, n: int = 192, coarse: int = 96):

@@ -603,6 +603,47 @@ def predict_fields(net, log10_ra, wall_type, u_c=1.0):
     return out
 
 
+def conv_layers(m=64):
+    """(ci, co, resolution, upsampled input channels) of every convolution of
+    the network, in forward order, the head last."""
+    c0, c1, c2, c3 = UNet.LEVELS
+    return [(NFEAT, c0, m, 0), (c0, c0, m, 0), (c0, c1, m // 2, 0), (c1, c1, m // 2, 0),
+            (c1, c2, m // 4, 0), (c2, c2, m // 4, 0), (c2, c3, m // 8, 0), (c3, c3, m // 8, 0),
+            (c3 + c2, c2, m // 4, c3), (c2, c2, m // 4, 0), (c2 + c1, c1, m // 2, c2),
+            (c1, c1, m // 2, 0), (c1 + c0, c0, m, c1), (c0, c0, m, 0), (c0, 16, m, 0)]
+
+
+def conv_floor(batch=4, m=64, hbm_bps=8e12, mfma_flops=2.5e15):
+    """FLOPs of one training step's convolutions and the floor of their time:
+    per launch (forward and weight gradient of every layer, data gradient of
+    all but the first) the larger of its HBM time (BF16 activations read once
+    and written once: the forward reads its input and writes z and SiLU(z),
+    the weight gradient reads input and output gradient, the data gradient
+    reads the output gradient and the gating pre-activation and writes the
+    input gradient; the head reads its FP32 targets and writes its BF16 loss
+    gradient) and its MFMA time at the dense BF16 peak.  Returns (flop,
+    floor_s, hbm_only_s, mfma_only_s)."""
+    flop_tot = floor = hbm = mf = 0.0
+    layers = conv_layers(m)
+    for k, (ci, co, r, cu) in enumerate(layers):
+        v = batch * r ** 3
+        fl = 2.0 * 27 * ci * co * v
+        inb = 2.0 * (v // 8 * cu + v * (ci - cu))
+        if k == len(layers) - 1:  # head: loss in the epilogue, no SiLU
+            launches = [2.0 * v * ci + 4.0 * v * NOUT + 2.0 * v * co, inb + 2.0 * v * co,
+                        2.0 * v * co + 4.0 * v * ci]
+        else:
+            launches = [inb + 4.0 * v * co, inb + 2.0 * v * co]
+            if k > 0:
+                launches.append(2.0 * v * co + 4.0 * v * ci)
+        for b in launches:
+            flop_tot += fl
+            floor += max(b / hbm_bps, fl / mfma_flops)
+            hbm += b / hbm_bps
+            mf += fl / mfma_flops
+    return flop_tot, floor, hbm, mf
+
+
 def bench_step(batch=4, m=64, steps=20, warmup=3, fused=True):
     """Time one training step (forward, loss, backward, Adam) of the U-Net at
     `batch` x m^3 on synthetic targets (seeded smooth fields); returns the
