@@ -613,11 +613,11 @@ __global__ __launch_bounds__(256) void k_conv_flip_many(const bf *__restrict__ w
 // word, and consecutive lanes write consecutive words.
 // The products run on v_mfma_f32_16x16x32_bf16 with K = 32 voxels, two brick
 // rows (lanes 0-31 row 2q, lanes 32-63 row 2q + 1, 8 voxels per lane).  The
-// 27 taps form 9 groups (dy, dz) of three x offsets: a lane reads the 16
-// halo voxels from x = 8 h - 1 on (two aligned 16-byte reads) and takes the
-// operand of dx = -1 as the first read, dx = +1 as its words 1-4 and dx = 0
-// as those words shifted by one element (v_perm_b32), so two LDS reads feed
-// three products.  Wave w runs groups w and w + 4 (wave 0 also group 8),
+// 27 taps form 9 groups (dy, dz) of three x offsets: a lane reads the 10
+// halo voxels from x = 8 h - 1 on (an aligned 16-byte read and the 32-bit
+// word after it) and takes the operand of dx = -1 as the 16-byte read, dx = +1
+// as words 1-4 and dx = 0 as those words shifted by one element
+// (v_perm_b32), so two LDS reads feed three products.  Wave w runs groups w and w + 4 (wave 0 also group 8),
 // reusing the gout operand across its taps; wave 3 accumulates the bias
 // gradient as a product with a register operand of ones.  Each lane's
 // operand addresses are computed once per launch, a row pair step is an
@@ -628,7 +628,9 @@ __global__ __launch_bounds__(256) void k_conv_flip_many(const bf *__restrict__ w
 constexpr int WB_X = 16, WB_Y = 4, WB_Z = 4, WB_V = WB_X * WB_Y * WB_Z;
 constexpr int WB_HROWS = (WB_Y + 2) * (WB_Z + 2);   // halo rows (y, z)
 constexpr int WB_RW = 24;                           // LDS row: 18 halo voxels, 16-byte aligned stride
-constexpr int WB_PLANE = WB_HROWS * WB_RW + 8; // one input channel
+constexpr int WB_PLANE = WB_HROWS * WB_RW + 8;      // one input channel; the 8 padding elements put the
+                                                    // channels of one 8-lane phase of a 16-byte read on
+                                                    // distinct banks
 constexpr int WB_GROW = WB_V + 8;                   // one channel of the gout tile
 constexpr int WB_XP = (WB_X + 2) / 2;               // voxel pairs per halo row
 constexpr int WB_ITASKS = WB_HROWS * WB_XP * 2;     // (halo row, x pair, channel half) = 648
