@@ -1247,30 +1247,26 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float *__restrict__ a
 
 // Network input on an m^3 node-centred grid, 16 channels per voxel:
 // normalised log10 Ra, one-hot wall type (3), node coordinates in [-1, 1]
-// (3), zeros.  cond[b] = {log-Ra feature, wall type}.
-__global__ __launch_bounds__(256) void k_make_input(const float *__restrict__ cond, bf *__restrict__ out, int B,
-                                                    int m)
+// (3), zeros.  cond[b] = {log-Ra feature, wall type}.  Block r writes the
+// row r = (b m + z) m + y of voxels (x fastest), its wavefronts striding
+// over x; the row's indices and coordinates are computed once per block.
+__global__ __launch_bounds__(64) void k_make_input(const float *__restrict__ cond, bf *__restrict__ out, int m)
 {
-    const long long n = (long long)B * m * m * m;
-    for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < n;
-         p += (long long)gridDim.x * blockDim.x) {
-        long long r = p;
-        const int x = int(r % m); r /= m;
-        const int y = int(r % m); r /= m;
-        const int z = int(r % m);
-        const int b = int(r / m);
-        const float lra = cond[2 * b], wt = cond[2 * b + 1];
-        float ch[16] = {0.f};
-        ch[0] = lra;
-        ch[1] = wt == 1.f ? 1.f : 0.f;
-        ch[2] = wt == 2.f ? 1.f : 0.f;
-        ch[3] = wt == 3.f ? 1.f : 0.f;
+    const int r = int(blockIdx.x);
+    const int y = r % m, z = (r / m) % m, b = r / (m * m);
+    const float lra = cond[2 * b], wt = cond[2 * b + 1];
+    float ch[16] = {0.f};
+    ch[0] = lra;
+    ch[1] = wt == 1.f ? 1.f : 0.f;
+    ch[2] = wt == 2.f ? 1.f : 0.f;
+    ch[3] = wt == 3.f ? 1.f : 0.f;
+    ch[5] = (2.f * y + 1.f) / m - 1.f;
+    ch[6] = (2.f * z + 1.f) / m - 1.f;
+    uint4 *o = reinterpret_cast<uint4 *>(out + size_t(r) * m * 16);  // 32 bytes per voxel
+    for (int x = int(threadIdx.x); x < m; x += int(blockDim.x)) {
         ch[4] = (2.f * x + 1.f) / m - 1.f;
-        ch[5] = (2.f * y + 1.f) / m - 1.f;
-        ch[6] = (2.f * z + 1.f) / m - 1.f;
-        uint4 *o = reinterpret_cast<uint4 *>(out + p * 16);  // 32 bytes per voxel
-        o[0] = pack8(ch);
-        o[1] = pack8(ch + 8);
+        o[2 * x] = pack8(ch);
+        o[2 * x + 1] = pack8(ch + 8);
     }
 }
 
@@ -1842,11 +1838,10 @@ lbmx_status lbmx_nn_to_bf16(const float *a, void *b, int64_t n, void *stream)
 
 lbmx_status lbmx_nn_make_input(const float *cond, void *out, int32_t B, int32_t m, void *stream)
 {
-    if (!cond || !out || B < 1 || m < 1)
-        return fail(LBMX_EINVAL, "make_input: bad arguments");
-    const long long n = (long long)B * m * m * m;
-    hipLaunchKernelGGL(k_make_input, dim3(blocks_for(n)), dim3(256), 0, S(stream), cond,
-                       reinterpret_cast<bf *>(out), B, m);
+    if (!cond || !out || B < 1 || m < 1 || (long long)B * m * m >= (1LL << 31))
+        return fail(LBMX_EINVAL, "make_input: bad arguments (B m^2 < 2^31 rows)");
+    hipLaunchKernelGGL(k_make_input, dim3(unsigned(B * m * m)), dim3(64), 0, S(stream), cond,
+                       reinterpret_cast<bf *>(out), m);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;
 }
