@@ -1248,25 +1248,25 @@ __global__ __launch_bounds__(256) void k_f32_to_bf16(const float *__restrict__ a
 // Network input on an m^3 node-centred grid, 16 channels per voxel:
 // normalised log10 Ra, one-hot wall type (3), node coordinates in [-1, 1]
 // (3), zeros.  cond[b] = {log-Ra feature, wall type}.  Block r writes the
-// row r = (b m + z) m + y of voxels (x fastest), its wavefronts striding
-// over x; the row's indices and coordinates are computed once per block.
-__global__ __launch_bounds__(64) void k_make_input(const float *__restrict__ cond, bf *__restrict__ out, int m)
+// row r = (b m + z) m + y of voxels, thread t the 16-byte pieces t, t + 128,
+// ... of the row (piece 2x: voxel x's first 8 channels, 2x + 1: its zeros),
+// so each store instruction covers a contiguous run; the row's indices and
+// coordinates are computed once per block.
+__global__ __launch_bounds__(128) void k_make_input(const float *__restrict__ cond, bf *__restrict__ out, int m)
 {
     const int r = int(blockIdx.x);
     const int y = r % m, z = (r / m) % m, b = r / (m * m);
     const float lra = cond[2 * b], wt = cond[2 * b + 1];
-    float ch[16] = {0.f};
-    ch[0] = lra;
-    ch[1] = wt == 1.f ? 1.f : 0.f;
-    ch[2] = wt == 2.f ? 1.f : 0.f;
-    ch[3] = wt == 3.f ? 1.f : 0.f;
-    ch[5] = (2.f * y + 1.f) / m - 1.f;
-    ch[6] = (2.f * z + 1.f) / m - 1.f;
+    float ch[8] = {lra, wt == 1.f ? 1.f : 0.f, wt == 2.f ? 1.f : 0.f, wt == 3.f ? 1.f : 0.f, 0.f,
+                   (2.f * y + 1.f) / m - 1.f, (2.f * z + 1.f) / m - 1.f, 0.f};
     uint4 *o = reinterpret_cast<uint4 *>(out + size_t(r) * m * 16);  // 32 bytes per voxel
-    for (int x = int(threadIdx.x); x < m; x += int(blockDim.x)) {
-        ch[4] = (2.f * x + 1.f) / m - 1.f;
-        o[2 * x] = pack8(ch);
-        o[2 * x + 1] = pack8(ch + 8);
+    for (int p = int(threadIdx.x); p < 2 * m; p += int(blockDim.x)) {
+        uint4 v = make_uint4(0, 0, 0, 0);
+        if ((p & 1) == 0) {
+            ch[4] = (2.f * (p >> 1) + 1.f) / m - 1.f;
+            v = pack8(ch);
+        }
+        o[p] = v;
     }
 }
 
@@ -1840,7 +1840,7 @@ lbmx_status lbmx_nn_make_input(const float *cond, void *out, int32_t B, int32_t 
 {
     if (!cond || !out || B < 1 || m < 1 || (long long)B * m * m >= (1LL << 31))
         return fail(LBMX_EINVAL, "make_input: bad arguments (B m^2 < 2^31 rows)");
-    hipLaunchKernelGGL(k_make_input, dim3(unsigned(B * m * m)), dim3(64), 0, S(stream), cond,
+    hipLaunchKernelGGL(k_make_input, dim3(unsigned(B * m * m)), dim3(128), 0, S(stream), cond,
                        reinterpret_cast<bf *>(out), m);
     HIP_TRY(hipGetLastError());
     return LBMX_OK;

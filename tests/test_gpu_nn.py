@@ -242,17 +242,20 @@ def test_silu_add_mse_adam_layout_input():
     back = torch.empty((B, K, V), dtype=torch.float32, device="cuda")
     call("lbmx_nn_layout", P(cl), P(back), B, V, K, C, 0, P(tinv), S())
     assert np.abs(back.cpu().numpy() - a).max() < 1e-6
-    # network input
-    m = 8
+    # network input (m = 70: rows longer than the kernel's 64 threads)
     cond = to_f32(np.array([[0.25, 2.0], [-1.0, 3.0]]))
-    x = torch.empty((2, m, m, m, 16), dtype=torch.bfloat16, device="cuda")
-    call("lbmx_nn_make_input", P(cond), P(x), 2, m, S())
-    xv = from_bf(x)
-    assert np.all(xv[0, ..., 0] == 0.25) and np.all(xv[1, ..., 0] == -1.0)
-    assert np.all(xv[0, ..., 2] == 1) and np.all(xv[0, ..., 1] == 0) and np.all(xv[1, ..., 3] == 1)
-    c = N.bf16_round((2 * np.arange(m) + 1.0) / m - 1.0)
-    assert np.array_equal(xv[0, 0, 0, :, 4], c) and np.array_equal(xv[1, :, 0, 0, 6], c)
-    assert np.all(xv[..., 7:] == 0)
+    for m in (8, 70):
+        x = torch.empty((2, m, m, m, 16), dtype=torch.bfloat16, device="cuda")
+        call("lbmx_nn_make_input", P(cond), P(x), 2, m, S())
+        xv = from_bf(x)
+        assert np.all(xv[0, ..., 0] == 0.25) and np.all(xv[1, ..., 0] == -1.0)
+        assert np.all(xv[0, ..., 2] == 1) and np.all(xv[0, ..., 1] == 0) and np.all(xv[0, ..., 3] == 0)
+        assert np.all(xv[1, ..., 3] == 1) and np.all(xv[1, ..., 1:3] == 0)
+        c = N.bf16_round((2 * np.arange(m) + 1.0) / m - 1.0)
+        assert np.array_equal(xv[..., 4], np.broadcast_to(c[None, None, None, :], xv.shape[:4]))
+        assert np.array_equal(xv[..., 5], np.broadcast_to(c[None, None, :, None], xv.shape[:4]))
+        assert np.array_equal(xv[..., 6], np.broadcast_to(c[None, :, None, None], xv.shape[:4]))
+        assert np.all(xv[..., 7:] == 0)
 
 
 def test_flip_many_and_mse_paths():
