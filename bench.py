@@ -18,8 +18,10 @@ thread on the same 64^3 sample, and the 16^3, Ra 1e3, Type 1 cavity for
 OMP_NUM_THREADS set, no GPU use).
 time_to_steady: 128^3, Ra 1e5, FP32, wall types 1-3, wall time to |dNu_3D| <
 1e-6 per 1000 steps from rest, from the shipped U-Net's predicted fields
-(warm start; inference and initialisation included), and by grid sequencing
-(the prediction run to steady on 64^3 first, that solve included).
+(warm start; inference and initialisation included), by grid sequencing
+(the prediction run to steady on 64^3 first, that solve included), and by
+extrapolated grid sequencing (32^3 from the prediction, then 64^3, the
+128^3 start extrapolated from both).
 storage_sweep: every storage format at the same size and case (500 steps each).
 batch_to_steady: the 64-cavity batch (n uniform in {32, 48, 64, 80, 96}, Ra
 log-uniform in [1e3, 1e6], wall type uniform in {1, 2, 3}, seed 1511, FP32)
@@ -32,8 +34,9 @@ after 3 warm-up steps, the convolutions' FLOP rate, and the floor of the
 convolutions (per launch the larger of HBM and MFMA time) with the step's
 ratio to it.
 warm_start_192: a 192^3 cavity (Ra 3e5, Type 2, FP32) to steady from rest,
-from the U-Net's predicted fields, and from a 96^3 cavity started from them
-and run to steady (inference, coarse solve and initialisation timed).
+from the U-Net's predicted fields, from a 96^3 cavity started from them
+and run to steady, and extrapolated from 48^3 and 96^3 cavities (inference,
+coarse solves and initialisation timed).
 """
 from __future__ import annotations
 
@@ -124,7 +127,10 @@ def time_to_steady(wall_type: int, net=None, coarse: int = 64, n: int = 128, ra:
     initialisation inside the timed region); with coarse = m > 0, by grid
     sequencing: the m^3 cavity run to steady by the same criterion (from the
     network's fields, or from rest without a network) starts the 128^3 one
-    (coarse solve inside the timed region)."""
+    (coarse solve inside the timed region); and with extrapolation: an
+    (m/2)^3 cavity started the same way and run to steady starts the m^3
+    one, and the 128^3 cavity starts from 5/4 of the m^3 fields minus 1/4
+    of the (m/2)^3 fields (both coarse solves inside the timed region)."""
     from paper_1511_04633_amd import warmstart
 
     rest = warmstart.solve(n, ra, wall_type, None, max_steps=2_000_000)
@@ -144,6 +150,13 @@ def time_to_steady(wall_type: int, net=None, coarse: int = 64, n: int = 128, ra:
                              "coarse": ml["coarse"], "init_s": ml["init_s"],
                              "converged": ml["converged"], "nu3d": ml["nu3d"],
                              "nu_rel_diff": abs(ml["nu3d"] - rest["nu3d"]) / rest["nu3d"]}
+        ex = warmstart.solve(n, ra, wall_type, net, coarse=coarse, max_steps=2_000_000,
+                             extrapolate=True)
+        out["extrapolated"] = {"seconds": ex["seconds"], "steps": ex["steps"],
+                               "start": "network" if net is not None else "rest",
+                               "coarse": ex["coarse"], "init_s": ex["init_s"],
+                               "converged": ex["converged"], "nu3d": ex["nu3d"],
+                               "nu_rel_diff": abs(ex["nu3d"] - rest["nu3d"]) / rest["nu3d"]}
     return out
 
 
@@ -216,13 +229,16 @@ def unet_training_step():
 
 def warm_start_192(net, ra: float = 3e5, wall_type: int = 2, n: int = 192, coarse: int = 96):
     """The learned warm start at 192^3: rest start vs the network's fields vs grid sequencing
-    through a coarse^3 cavity started from them; all to |dNu_3D| < 1e-6 per
-    1000 steps, FP32, on this GPU."""
+    through a coarse^3 cavity started from them vs the extrapolated start
+    from (coarse/2)^3 and coarse^3 cavities; all to |dNu_3D| < 1e-6 per 1000
+    steps, FP32, on this GPU."""
     from paper_1511_04633_amd import warmstart
 
     rest = warmstart.solve(n, ra, wall_type, None, max_steps=1_000_000)
     warm = warmstart.solve(n, ra, wall_type, net, max_steps=1_000_000)
     ml = warmstart.solve(n, ra, wall_type, net, coarse=coarse, max_steps=1_000_000)
+    ex = warmstart.solve(n, ra, wall_type, net, coarse=coarse, max_steps=1_000_000,
+                         extrapolate=True)
     rel = lambda r: abs(r["nu3d"] - rest["nu3d"]) / rest["nu3d"]
     return {"workload": f"{n}^3 Type {wall_type} Ra {ra:g} f32",
             "rest": {k: rest[k] for k in ("steps", "seconds", "converged", "nu3d")},
@@ -231,7 +247,10 @@ def warm_start_192(net, ra: float = 3e5, wall_type: int = 2, n: int = 192, coars
                                time_ratio=round(warm["seconds"] / rest["seconds"], 3)),
             "multilevel": dict({k: ml[k] for k in ("steps", "seconds", "init_s", "converged",
                                                     "nu3d", "coarse")}, nu_rel_diff=rel(ml),
-                               time_ratio=round(ml["seconds"] / rest["seconds"], 3))}
+                               time_ratio=round(ml["seconds"] / rest["seconds"], 3)),
+            "extrapolated": dict({k: ex[k] for k in ("steps", "seconds", "init_s", "converged",
+                                                      "nu3d", "coarse")}, nu_rel_diff=rel(ex),
+                                 time_ratio=round(ex["seconds"] / rest["seconds"], 3))}
 
 
 def counter_traffic(storage: str, n: int):

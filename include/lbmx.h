@@ -232,6 +232,23 @@ lbmx_status lbmx_init_fields(lbmx_cavity *h, const float *dev_u, const float *de
  * device, ESTATE for a failed src, EDEVICE for a HIP failure. */
 lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src);
 
+/* Set dst's state at t = 0 from the weighted sum of two other cavities'
+ * fields (grid sequencing with extrapolation; the paper fixes no initial
+ * state): u = wa s_a u_a + wb s_b u_b and theta = wa theta_a + wb theta_b,
+ * where u_k = j / rho and theta_k (Eqs. 20, 25, 30) of cavity k are formed
+ * on the device in FP64 and sampled trilinearly onto dst's nodes as in
+ * lbmx_init_fields, and s_k = u_c(dst) / u_c(k) (Eq. 38); dst takes
+ * f = f^eq(1, u) of Eq. (17) and g = g^eq(theta, u).  With a and b the
+ * steady states of the same case at 1/2 and 1/4 of dst's resolution, the
+ * weights wa = 5/4, wb = -1/4 extrapolate their second-order grid error
+ * to dst's grid.  a and b are only read; each stages its fields (5 n^3
+ * doubles) in its own spare lattice.  All three cavities must live on the
+ * current device.  Synchronises the three streams.  Errors: EINVAL for a
+ * NULL handle, two identical handles, another device or a non-finite
+ * weight, ESTATE for a failed source, EDEVICE for a HIP failure. */
+lbmx_status lbmx_init_from_cavities(lbmx_cavity *dst, lbmx_cavity *a, double wa, lbmx_cavity *b,
+                                    double wb);
+
 /* Advance nsteps >= 0 time steps (fused streaming + double-MRT collision,
  * Eqs. 14 and 29, wall conditions of Eqs. 6-10).  Asynchronous. */
 lbmx_status lbmx_step(lbmx_cavity *h, int64_t nsteps);

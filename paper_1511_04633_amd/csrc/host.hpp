@@ -561,5 +561,44 @@ inline lbmx_status init_from_state(const View &dst, int32_t dst_storage, const V
     return LBMX_OK;
 }
 
+template <class St>
+lbmx_status unstream_two_fields(const View &v, const SourceTwoFields &src)
+{
+    return launch_unstream<St>(v, src);
+}
+
+// dst's state at t = 0 from wa (fields of a) + wb (fields of b): each
+// source's u = j / rho and theta formed in FP64 on the device (staged in its
+// own spare lattice), sampled trilinearly onto dst's nodes with velocities
+// scaled by sa / sb, combined, rho = 1; f = f^eq(1, u), g = g^eq(theta, u).
+// Synchronises the three streams; a and b are only read and must differ.
+inline lbmx_status init_from_two_states(const View &dst, int32_t dst_storage, const View &a,
+                                        int32_t a_storage, double wa, double sa, const View &b,
+                                        int32_t b_storage, double wb, double sb)
+{
+    const View *src[2] = {&a, &b};
+    const int32_t sto[2] = {a_storage, b_storage};
+    SourceFields<double> sf[2];
+    for (int k = 0; k < 2; ++k) {
+        const View &v = *src[k];
+        const size_t mc = (size_t)v.n * v.n * v.n;
+        double *f5 = reinterpret_cast<double *>(v.spare);
+        lbmx_status s = LBMX_DISPATCH(sto[k], launch_macro, v, f5 + 4 * mc, f5, f5 + mc,
+                                      f5 + 2 * mc, f5 + 3 * mc);
+        if (s != LBMX_OK)
+            return s;
+        sf[k] = SourceFields<double>{f5, f5 + mc, f5 + 2 * mc, f5 + 3 * mc, v.n, dst.n,
+                                     k == 0 ? sa : sb, nullptr};
+    }
+    HIP_TRY(hipStreamSynchronize(a.stream));
+    HIP_TRY(hipStreamSynchronize(b.stream));
+    lbmx_status s = LBMX_DISPATCH(dst_storage, unstream_two_fields, dst,
+                                  SourceTwoFields{sf[0], sf[1], wa, wb});
+    if (s != LBMX_OK)
+        return s;
+    HIP_TRY(hipStreamSynchronize(dst.stream));
+    return LBMX_OK;
+}
+
 }  // namespace host
 }  // namespace lbmx

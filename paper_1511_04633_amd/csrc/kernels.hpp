@@ -516,6 +516,40 @@ struct SourceFields {
     }
 };
 
+// Fields combined from two node-centred grids (FP64 fields of two other
+// cavities): u = wa u_a + wb u_b and theta = wa theta_a + wb theta_b, each
+// sampled trilinearly as by SourceFields (velocities scaled there), rho = 1;
+// f = f^eq(1, u) (Eq. 17) and g = w_T theta (1 + 4 e.u).
+struct SourceTwoFields {
+    SourceFields<double> a, b;  // density fields null
+    double wa, wb;
+    __device__ void node(int c, double *vel, double &theta) const
+    {
+        double va[3], vb[3], ta, tb;
+        a.node(c, va, ta);
+        b.node(c, vb, tb);
+        for (int d = 0; d < 3; ++d)
+            vel[d] = wa * va[d] + wb * vb[d];
+        theta = wa * ta + wb * tb;
+    }
+    __device__ double f(int i, int c) const
+    {
+        double vel[3], t;
+        node(c, vel, t);
+        const double eu = ex19(i) * vel[0] + ey19(i) * vel[1] + ez19(i) * vel[2];
+        const double uu = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
+        return w19(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+    }
+    __device__ double g(int i, int c) const
+    {
+        double vel[3], t;
+        node(c, vel, t);
+        const int e[3] = {i == 1 ? 1 : (i == 2 ? -1 : 0), i == 3 ? 1 : (i == 4 ? -1 : 0),
+                          i == 5 ? 1 : (i == 6 ? -1 : 0)};
+        return w7(i) * t * (1.0 + 4.0 * (e[0] * vel[0] + e[1] * vel[1] + e[2] * vel[2]));
+    }
+};
+
 // "Unstream": write the post-collision lattice P whose pull reproduces S.
 // For population i at node y: if y + e_i is inside, P_i(y) = S_i(y + e_i);
 // otherwise P_i(y) is the value that the wall turns into S_ibar(y).  Only

@@ -538,6 +538,32 @@ lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src)
     });
 }
 
+lbmx_status lbmx_init_from_cavities(lbmx_cavity *dst, lbmx_cavity *a, double wa, lbmx_cavity *b,
+                                    double wb)
+{
+    lbmx_status s = check_handle(dst);
+    if (s != LBMX_OK)
+        return s;
+    if ((s = check_usable(a)) != LBMX_OK || (s = check_usable(b)) != LBMX_OK)
+        return s;
+    if (a == dst || b == dst || a == b)
+        return fail(LBMX_EINVAL, "the two sources and the destination must be three cavities");
+    if (!std::isfinite(wa) || !std::isfinite(wb))
+        return fail(LBMX_EINVAL, "weights must be finite");
+    if ((s = check_same_device(a->ws, dst->ws, "cavities")) != LBMX_OK ||
+        (s = check_same_device(b->ws, dst->ws, "cavities")) != LBMX_OK)
+        return s;
+    return reinit(dst, [&]() -> lbmx_status {
+        dst->cur = 0;
+        lbmx_status r = init_from_two_states(view(dst), dst->p.storage, view(a), a->p.storage, wa,
+                                             dst->d.u_c / a->d.u_c, view(b), b->p.storage, wb,
+                                             dst->d.u_c / b->d.u_c);
+        if (r == LBMX_OK)
+            dst->t = 0;
+        return r;
+    });
+}
+
 lbmx_status lbmx_step(lbmx_cavity *h, int64_t nsteps)
 {
     lbmx_status s = check_usable(h);

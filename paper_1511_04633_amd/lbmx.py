@@ -27,7 +27,7 @@ SYMBOLS = [
     "lbmx_params_default", "lbmx_derive", "lbmx_workspace_bytes", "lbmx_bytes_per_cell",
     "lbmx_create", "lbmx_destroy", "lbmx_init_rest", "lbmx_set_populations",
     "lbmx_get_populations", "lbmx_save", "lbmx_load", "lbmx_init_fields", "lbmx_init_from_cavity",
-    "lbmx_step", "lbmx_step_timed", "lbmx_time",
+    "lbmx_init_from_cavities", "lbmx_step", "lbmx_step_timed", "lbmx_time",
     "lbmx_read_macro", "lbmx_nusselt", "lbmx_nusselt_noalloc", "lbmx_run_to_steady",
     "lbmx_set_launch",
     "lbmx_get_launch", "lbmx_strerror", "lbmx_last_error",
@@ -110,6 +110,7 @@ def load() -> ctypes.CDLL:
         "lbmx_load": [_vp, ctypes.c_char_p],
         "lbmx_init_fields": [_vp, _vp, _vp, _vp, _vp, i32],
         "lbmx_init_from_cavity": [_vp, _vp],
+        "lbmx_init_from_cavities": [_vp, _vp, ctypes.c_double, _vp, ctypes.c_double],
         "lbmx_step": [_vp, i64],
         "lbmx_step_timed": [_vp, i64, _dp],
         "lbmx_time": [_vp, ctypes.POINTER(i64)],
@@ -262,6 +263,14 @@ class Cavity:
         """State at t = 0 from another cavity's current fields, resampled
         onto this cavity's nodes on the device (``lbmx_init_from_cavity``)."""
         _check(load().lbmx_init_from_cavity(self._h, other._h))
+        return self
+
+    def init_from_two(self, a: "Cavity", wa: float, b: "Cavity", wb: float):
+        """State at t = 0 from wa (fields of a) + wb (fields of b), each
+        resampled onto this cavity's nodes on the device, rho = 1
+        (``lbmx_init_from_cavities``; wa = 5/4, wb = -1/4 extrapolates the
+        steady states at 1/2 and 1/4 of this resolution)."""
+        _check(load().lbmx_init_from_cavities(self._h, a._h, float(wa), b._h, float(wb)))
         return self
 
     def set_populations(self, f, g, t=0):

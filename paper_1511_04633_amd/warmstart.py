@@ -63,13 +63,17 @@ def load_net(path):
 
 
 def solve(n, ra, wt, net=None, coarse=0, tol=1e-6, every=1000, max_steps=400_000,
-          history=False):
+          history=False, extrapolate=False):
     """Run one cavity to steady from rest (net None, coarse 0), from the
     network's fields (net), or by grid sequencing (coarse = m > 0): an m^3
     cavity of the same case is first run to steady by the same criterion,
     from the network's fields or from rest, and the n^3 cavity starts from
-    its fields (``Cavity.init_from``).  Wall time covers inference, the
-    coarse solve and every initialisation.  With history, step in chunks of
+    its fields (``Cavity.init_from``).  With extrapolate, an (m/2)^3 cavity
+    is run to steady first (from the network or from rest), starts the m^3
+    cavity, and the n^3 cavity starts from 5/4 of the m^3 fields minus 1/4
+    of the (m/2)^3 fields (``Cavity.init_from_two``: their second-order grid
+    error extrapolated to n = 2m).  Wall time covers inference, the coarse
+    solves and every initialisation.  With history, step in chunks of
     `every` from Python (same criterion as lbmx_run_to_steady) and also
     report the first step after which Nu_3D stays within 1e-3 of its final
     value."""
@@ -89,13 +93,28 @@ def solve(n, ra, wt, net=None, coarse=0, tol=1e-6, every=1000, max_steps=400_000
     if coarse:
         cc = lbmx.Cavity(n=coarse, wall_type=wt, ra=ra, storage="f32",
                          theta0=inputs.theta_noise(coarse, 20151115))
-        if net is not None:
+        c2, r2 = None, None
+        if extrapolate:
+            c2 = lbmx.Cavity(n=coarse // 2, wall_type=wt, ra=ra, storage="f32",
+                             theta0=inputs.theta_noise(coarse // 2, 20151115))
+            if net is not None:
+                start_from_net(c2)
+            r2 = c2.run_to_steady(tol=tol, every=every, max_steps=max_steps)
+            cc.init_from(c2)
+        elif net is not None:
             start_from_net(cc)
         rc = cc.run_to_steady(tol=tol, every=every, max_steps=max_steps)
-        cav.init_from(cc)
+        if extrapolate:
+            cav.init_from_two(cc, 1.25, c2, -0.25)
+            c2.close()
+        else:
+            cav.init_from(cc)
         cc.close()
         coarse_info = {"n": coarse, "steps": rc["step"], "converged": rc["converged"],
                        "nu3d": rc["nu3d"]}
+        if r2 is not None:
+            coarse_info["quarter"] = {"n": coarse // 2, "steps": r2["step"],
+                                      "converged": r2["converged"], "nu3d": r2["nu3d"]}
         t_init = time.perf_counter() - t0
     elif net is not None:
         start_from_net(cav)

@@ -92,6 +92,7 @@ def test_null_arguments():
     assert lib.lbmx_step(None, 1) == 1
     assert lib.lbmx_nusselt(None, None, None) == 1
     assert lib.lbmx_init_from_cavity(None, None) == 1
+    assert lib.lbmx_init_from_cavities(None, None, 1.0, None, 0.0) == 1
     assert lib.lbmx_batch_init_from(None, 0, None, 0) == 1
     lib.lbmx_destroy(None)
 
