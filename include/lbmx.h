@@ -234,11 +234,12 @@ lbmx_status lbmx_init_from_cavity(lbmx_cavity *dst, lbmx_cavity *src);
 
 /* Set dst's state at t = 0 from the weighted sum of two other cavities'
  * fields (grid sequencing with extrapolation; the paper fixes no initial
- * state): u = wa s_a u_a + wb s_b u_b and theta = wa theta_a + wb theta_b,
- * where u_k = j / rho and theta_k (Eqs. 20, 25, 30) of cavity k are formed
- * on the device in FP64 and sampled trilinearly onto dst's nodes as in
+ * state): u = wa s_a u_a + wb s_b u_b, theta = wa theta_a + wb theta_b
+ * and rho = 1 + wa s_a^2 (rho_a - 1) + wb s_b^2 (rho_b - 1), where rho_k,
+ * u_k = j / rho_k and theta_k (Eqs. 20, 25, 30) of cavity k are formed on
+ * the device in FP64 and sampled trilinearly onto dst's nodes as in
  * lbmx_init_fields, and s_k = u_c(dst) / u_c(k) (Eq. 38); dst takes
- * f = f^eq(1, u) of Eq. (17) and g = g^eq(theta, u).  With a and b the
+ * f = f^eq(rho, u) of Eq. (17) and g = g^eq(theta, u).  With a and b the
  * steady states of the same case at 1/2 and 1/4 of dst's resolution, the
  * weights wa = 5/4, wb = -1/4 extrapolate their second-order grid error
  * to dst's grid.  a and b are only read; each stages its fields (5 n^3

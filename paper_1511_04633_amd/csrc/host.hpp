@@ -568,9 +568,10 @@ lbmx_status unstream_two_fields(const View &v, const SourceTwoFields &src)
 }
 
 // dst's state at t = 0 from wa (fields of a) + wb (fields of b): each
-// source's u = j / rho and theta formed in FP64 on the device (staged in its
-// own spare lattice), sampled trilinearly onto dst's nodes with velocities
-// scaled by sa / sb, combined, rho = 1; f = f^eq(1, u), g = g^eq(theta, u).
+// source's rho, u = j / rho and theta formed in FP64 on the device (staged in
+// its own spare lattice), sampled trilinearly onto dst's nodes with
+// velocities scaled by sa / sb and rho - 1 by sa^2 / sb^2, combined;
+// f = f^eq(rho, u), g = g^eq(theta, u).
 // Synchronises the three streams; a and b are only read and must differ.
 inline lbmx_status init_from_two_states(const View &dst, int32_t dst_storage, const View &a,
                                         int32_t a_storage, double wa, double sa, const View &b,
@@ -588,7 +589,7 @@ inline lbmx_status init_from_two_states(const View &dst, int32_t dst_storage, co
         if (s != LBMX_OK)
             return s;
         sf[k] = SourceFields<double>{f5, f5 + mc, f5 + 2 * mc, f5 + 3 * mc, v.n, dst.n,
-                                     k == 0 ? sa : sb, nullptr};
+                                     k == 0 ? sa : sb, f5 + 4 * mc};
     }
     HIP_TRY(hipStreamSynchronize(a.stream));
     HIP_TRY(hipStreamSynchronize(b.stream));

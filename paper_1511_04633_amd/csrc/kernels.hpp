@@ -517,11 +517,12 @@ struct SourceFields {
 };
 
 // Fields combined from two node-centred grids (FP64 fields of two other
-// cavities): u = wa u_a + wb u_b and theta = wa theta_a + wb theta_b, each
-// sampled trilinearly as by SourceFields (velocities scaled there), rho = 1;
-// f = f^eq(1, u) (Eq. 17) and g = w_T theta (1 + 4 e.u).
+// cavities): u = wa u_a + wb u_b, theta = wa theta_a + wb theta_b and
+// rho - 1 = wa (rho_a - 1) + wb (rho_b - 1), each sampled trilinearly as by
+// SourceFields (velocities scaled by its vscale, density variations by
+// vscale^2); f = f^eq(rho, u) (Eq. 17) and g = w_T theta (1 + 4 e.u).
 struct SourceTwoFields {
-    SourceFields<double> a, b;  // density fields null
+    SourceFields<double> a, b;  // with density fields
     double wa, wb;
     __device__ void node(int c, double *vel, double &theta) const
     {
@@ -538,7 +539,10 @@ struct SourceTwoFields {
         node(c, vel, t);
         const double eu = ex19(i) * vel[0] + ey19(i) * vel[1] + ez19(i) * vel[2];
         const double uu = vel[0] * vel[0] + vel[1] * vel[1] + vel[2] * vel[2];
-        return w19(i) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        const int x = c % a.n, y = (c / a.n) % a.n, z = c / (a.n * a.n);
+        const double dr = wa * (a.sample(a.rho, x, y, z) - 1.0) * a.vscale * a.vscale +
+                          wb * (b.sample(b.rho, x, y, z) - 1.0) * b.vscale * b.vscale;
+        return w19(i) * (dr + (1.0 + dr) * (3.0 * eu + 4.5 * eu * eu - 1.5 * uu));
     }
     __device__ double g(int i, int c) const
     {

@@ -266,10 +266,10 @@ class Cavity:
         return self
 
     def init_from_two(self, a: "Cavity", wa: float, b: "Cavity", wb: float):
-        """State at t = 0 from wa (fields of a) + wb (fields of b), each
-        resampled onto this cavity's nodes on the device, rho = 1
-        (``lbmx_init_from_cavities``; wa = 5/4, wb = -1/4 extrapolates the
-        steady states at 1/2 and 1/4 of this resolution)."""
+        """State at t = 0 from wa (fields of a) + wb (fields of b): rho, u
+        and theta of each resampled onto this cavity's nodes on the device
+        and combined (``lbmx_init_from_cavities``; wa = 5/4, wb = -1/4
+        extrapolates the steady states at 1/2 and 1/4 of this resolution)."""
         _check(load().lbmx_init_from_cavities(self._h, a._h, float(wa), b._h, float(wb)))
         return self
 
