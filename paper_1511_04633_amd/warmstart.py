@@ -9,9 +9,11 @@ CLI:
       generates the 64-cavity training set with the batched solver, trains,
       saves the weights and prints the loss history summary;
   python -m paper_1511_04633_amd.warmstart eval --weights weights.npz
-      [--ra 2e4,3e5,8e5] [--types 1,2,3] [--n 192] [--coarse 64]
+      [--ra 2e4,3e5,8e5] [--types 1,2,3] [--n 192] [--coarse 64] [--extrapolate]
       prints one JSON line per case; with --coarse also the grid-sequenced
-      start (network -> steady coarse^3 cavity -> n^3 cavity).
+      start (network -> steady coarse^3 cavity -> n^3 cavity), with
+      --extrapolate also the start extrapolated from the (coarse/2)^3 and
+      coarse^3 steady states.
 """
 from __future__ import annotations
 
@@ -171,6 +173,12 @@ def eval_main(a):
                 line["multilevel"] = ml
                 line["multilevel_time_ratio"] = ml["seconds"] / rest["seconds"]
                 line["multilevel_nu_rel_diff"] = abs(ml["nu3d"] - rest["nu3d"]) / rest["nu3d"]
+                if a.extrapolate:
+                    ex = solve(a.n, ra, wt, net, coarse=a.coarse, max_steps=a.max_steps,
+                               history=a.history, extrapolate=True)
+                    line["extrapolated"] = ex
+                    line["extrapolated_time_ratio"] = ex["seconds"] / rest["seconds"]
+                    line["extrapolated_nu_rel_diff"] = abs(ex["nu3d"] - rest["nu3d"]) / rest["nu3d"]
             print(json.dumps(line), flush=True)
 
 
@@ -197,6 +205,9 @@ def main(argv=None):
     e.add_argument("--max-steps", type=int, default=400_000)
     e.add_argument("--coarse", type=int, default=0,
                    help="also solve by grid sequencing: network -> coarse^3 steady -> n^3")
+    e.add_argument("--extrapolate", action="store_true",
+                   help="with --coarse, also start n^3 extrapolated from (coarse/2)^3 and "
+                        "coarse^3 steady states")
     e.add_argument("--history", action="store_true",
                    help="log Nu every 1000 steps and report steps to within 1e-3 of the final Nu")
     a = ap.parse_args(argv)
