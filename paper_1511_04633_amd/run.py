@@ -7,14 +7,21 @@ one of
   network    the shipped U-Net's predicted fields (warm start);
   coarse     a cavity of edge --coarse (default n / 2) run to steady first,
              from rest, whose fields start this one (grid sequencing);
-  network+coarse  the same, with the coarse cavity started from the network.
+  network+coarse  the same, with the coarse cavity started from the network;
+  extrapolated    an (m/2)^3 cavity run to steady (from rest) starts the m^3
+             coarse cavity, also run to steady, and this one starts from 5/4
+             of the m^3 fields minus 1/4 of the (m/2)^3 fields (their
+             second-order grid error extrapolated, lbmx_init_from_cavities;
+             the (m/2)^3 grid must resolve the flow: m/2 >= 16, e.g. n >= 64);
+  network+extrapolated  the same, with the (m/2)^3 cavity started from the
+             network.
 The output file (npz) holds rho, u, v, w, theta (FP32, [z, y, x], lattice
 units), the hot-wall Nu_3D, Nu_2D, Nu_max and local-Nu map (Eqs. 39-41), the
 velocity maxima scaled by Eq. (42), the step count and the wall time.
 
 CLI:
   python -m paper_1511_04633_amd.run --n 128 --ra 1e5 --wall-type 1
-      [--storage f32] [--start network+coarse] [--out result.npz]
+      [--storage f32] [--start network+extrapolated] [--out result.npz]
       [--checkpoint state.ckpt]
 prints one JSON line.
 """
@@ -31,7 +38,11 @@ import numpy as np
 
 from . import inputs, lbmx
 
-STARTS = ("rest", "network", "coarse", "network+coarse")
+STARTS = ("rest", "network", "coarse", "network+coarse", "extrapolated", "network+extrapolated")
+# Coarsest grid of an extrapolated start: below it the steady state is not in
+# the second-order regime the extrapolation assumes (at 8^3 a cavity started
+# from the network settled in another state than from rest).
+MIN_QUARTER = 16
 WEIGHTS = os.path.join(os.path.dirname(os.path.abspath(__file__)), "weights", "unet64.npz")
 
 
@@ -60,16 +71,34 @@ def run(n, ra, wall_type, pr=0.71, ma=0.1, storage="f32", start="rest", coarse=0
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     coarse_info = None
-    if start.endswith("coarse"):
+    if start.endswith("coarse") or start.endswith("extrapolated"):
         m = coarse or max(4, n // 2)
         cc = lbmx.Cavity(n=m, theta0=inputs.theta_noise(m, seed), **kw)
-        if net is not None:
+        cq, rq = None, None
+        if start.endswith("extrapolated"):
+            q = m // 2
+            if q < MIN_QUARTER:
+                raise ValueError(f"an extrapolated start needs the quarter-size cavity to have at "
+                                 f"least {MIN_QUARTER} nodes per edge (coarse {m} gives {q})")
+            cq = lbmx.Cavity(n=q, theta0=inputs.theta_noise(q, seed), **kw)
+            if net is not None:
+                _from_network(cq, net, ra, wall_type)
+            rq = cq.run_to_steady(tol=tol, every=every, max_steps=max_steps)
+            cc.init_from(cq)
+        elif net is not None:
             _from_network(cc, net, ra, wall_type)
         rc = cc.run_to_steady(tol=tol, every=every, max_steps=max_steps)
-        cav.init_from(cc)
+        if cq is not None:
+            cav.init_from_two(cc, 1.25, cq, -0.25)
+            cq.close()
+        else:
+            cav.init_from(cc)
         cc.close()
         coarse_info = {"n": m, "steps": rc["step"], "converged": rc["converged"],
                        "nu3d": rc["nu3d"]}
+        if rq is not None:
+            coarse_info["quarter"] = {"n": m // 2, "steps": rq["step"],
+                                      "converged": rq["converged"], "nu3d": rq["nu3d"]}
     elif net is not None:
         _from_network(cav, net, ra, wall_type)
     r = cav.run_to_steady(tol=tol, every=every, max_steps=max_steps)

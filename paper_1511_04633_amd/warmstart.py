@@ -74,7 +74,8 @@ def solve(n, ra, wt, net=None, coarse=0, tol=1e-6, every=1000, max_steps=400_000
     is run to steady first (from the network or from rest), starts the m^3
     cavity, and the n^3 cavity starts from 5/4 of the m^3 fields minus 1/4
     of the (m/2)^3 fields (``Cavity.init_from_two``: their second-order grid
-    error extrapolated to n = 2m).  Wall time covers inference, the coarse
+    error extrapolated to n = 2m; m/2 >= 16, so that both coarse grids
+    resolve the flow).  Wall time covers inference, the coarse
     solves and every initialisation.  With history, step in chunks of
     `every` from Python (same criterion as lbmx_run_to_steady) and also
     report the first step after which Nu_3D stays within 1e-3 of its final
@@ -97,6 +98,9 @@ def solve(n, ra, wt, net=None, coarse=0, tol=1e-6, every=1000, max_steps=400_000
                          theta0=inputs.theta_noise(coarse, 20151115))
         c2, r2 = None, None
         if extrapolate:
+            if coarse // 2 < 16:
+                raise ValueError("an extrapolated start needs coarse // 2 >= 16 (a resolved "
+                                 "quarter-size cavity)")
             c2 = lbmx.Cavity(n=coarse // 2, wall_type=wt, ra=ra, storage="f32",
                              theta0=inputs.theta_noise(coarse // 2, 20151115))
             if net is not None:

@@ -21,9 +21,9 @@ def _setup():
 
 
 def test_starts_agree_and_outputs_match(tmp_path):
-    print("case: run CLI 32^3 Ra 3e4 type 2, all starts", flush=True)
+    print("case: run CLI 32^3 Ra 3e4 type 2, all starts but the extrapolated ones", flush=True)
     out = {}
-    for start in R.STARTS:
+    for start in [s for s in R.STARTS if "extrapolated" not in s]:
         path = os.path.join(tmp_path, f"{start}.npz")
         ck = os.path.join(tmp_path, f"{start}.ckpt")
         s = R.main(["--n", "32", "--ra", "3e4", "--wall-type", "2", "--start", start,
@@ -43,3 +43,24 @@ def test_starts_agree_and_outputs_match(tmp_path):
     for start, s in out.items():
         assert abs(s["nu3d"] - ref) <= 1e-3 * ref, (start, s["nu3d"], ref)
     assert out["coarse"]["coarse"]["n"] == 16 and out["rest"]["coarse"] is None
+    with pytest.raises(ValueError):  # an 8^3 quarter level is refused
+        R.main(["--n", "32", "--ra", "3e4", "--wall-type", "2", "--start", "extrapolated",
+                "--out", os.path.join(tmp_path, "x.npz")])
+
+
+def test_extrapolated_starts_agree(tmp_path):
+    """The extrapolated starts (16^3 -> 32^3 -> 64^3, from rest and from the
+    network) reach the rest start's steady Nu at 64^3."""
+    print("case: run CLI 64^3 Ra 3e4 type 2, extrapolated starts", flush=True)
+    out = {}
+    for start in ("rest", "extrapolated", "network+extrapolated"):
+        s = R.main(["--n", "64", "--ra", "3e4", "--wall-type", "2", "--start", start,
+                    "--out", os.path.join(tmp_path, f"{start}.npz")])
+        assert s["converged"], s
+        out[start] = s
+    ref = out["rest"]["nu3d"]
+    for start in ("extrapolated", "network+extrapolated"):
+        s = out[start]
+        assert s["coarse"]["converged"] and s["coarse"]["quarter"]["converged"], s
+        assert s["coarse"]["n"] == 32 and s["coarse"]["quarter"]["n"] == 16
+        assert abs(s["nu3d"] - ref) <= 1e-3 * ref, (start, s["nu3d"], ref)
